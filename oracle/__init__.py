@@ -1,0 +1,209 @@
+"""TEST INFRASTRUCTURE ONLY: the checking implementation of sector tracking.
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It wraps ``tpc_oracle.cpp`` (plain C++, built with g++ by
+``build()``), which shares no code with the GPU library.
+
+Entry points:
+    track(cs, params, precision=32)   neighbour finder, cleaning, start hits,
+                                      tracklet constructor (Section 2 of the paper)
+    replay(cs, params, tracklets)     FP64 re-run of given attachment decisions
+    propagate / update                single steps, for the closed-form pins
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "tpc_oracle.cpp")
+LIB = os.path.join(HERE, "libtpc_oracle.so")
+
+CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+            "-shared", "-fPIC"]
+
+
+def build(extra_flags=(), out=LIB):
+    """Compile the oracle with g++ (strict IEEE, no FMA contraction)."""
+    cmd = ["g++", *CXXFLAGS, *extra_flags, SRC, "-o", out]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("win_y", ctypes.c_float), ("win_z", ctypes.c_float), ("d2_max", ctypes.c_float),
+                ("chi2_max", ctypes.c_float), ("sinphi_max", ctypes.c_float),
+                ("u_max", ctypes.c_float), ("sigma_y", ctypes.c_float),
+                ("sigma_z", ctypes.c_float), ("cww0", ctypes.c_float), ("bz", ctypes.c_float),
+                ("min_hits", ctypes.c_int32), ("max_misses", ctypes.c_int32),
+                ("brute", ctypes.c_int32)]
+
+
+@dataclass
+class Params:
+    """Tracking parameters (readings of the paper; values in cm, GeV/c, T)."""
+    win_y: float = 2.0
+    win_z: float = 2.0
+    d2_max: float = 0.36
+    chi2_max: float = 16.0
+    sinphi_max: float = 0.99
+    u_max: float = 0.1
+    sigma_y: float = 0.1
+    sigma_z: float = 0.1
+    cww0: float = 100.0
+    bz: float = 0.5
+    min_hits: int = 10
+    max_misses: int = 8
+
+    def c_struct(self, brute=False):
+        return OrcParams(self.win_y, self.win_z, self.d2_max, self.chi2_max, self.sinphi_max,
+                         self.u_max, self.sigma_y, self.sigma_z, self.cww0, self.bz,
+                         self.min_hits, self.max_misses, 1 if brute else 0)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        L.orc_track.restype = P
+        L.orc_track.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_free.argtypes = [P]
+        L.orc_len.restype = ctypes.c_int64
+        L.orc_len.argtypes = [P, ctypes.c_char_p]
+        L.orc_get.restype = ctypes.c_int
+        L.orc_get.argtypes = [P, ctypes.c_char_p, P]
+        L.orc_replay.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_int64, P, P, P,
+                                 P, P, P, P, P, P, P]
+        L.orc_propagate.restype = ctypes.c_int
+        L.orc_propagate.argtypes = [ctypes.c_int, P, P, ctypes.c_double]
+        L.orc_update.restype = ctypes.c_double
+        L.orc_update.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+_DTYPES = {
+    "link_up": np.int32, "link_down": np.int32, "clean_up": np.int32, "clean_down": np.int32,
+    "starts": np.int64, "t_start": np.int64, "t_hit_begin": np.int64, "t_unit": np.int32,
+    "t_r0": np.int32, "t_n": np.int32, "t_flags": np.int32, "t_row_ref": np.int32,
+    "t_ndf": np.int32, "t_hits": np.int32, "t_rows": np.uint8, "t_param": np.float64,
+    "t_cov": np.float64, "t_chi2": np.float64, "t_xref": np.float64, "counters": np.int64,
+}
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def track(cs, params: Params | None = None, precision=32, brute=False, units=None,
+          n_threads=0, row_x=None):
+    """Run the whole sector tracking on a ClusterSet; returns a dict of arrays.
+
+    Tracklet arrays (prefix ``t_``) hold one entry per start hit, kept or not;
+    ``kept`` marks those with at least ``min_hits`` clusters.
+    """
+    from synth import geometry as G
+    params = params or Params()
+    xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
+    rb = np.ascontiguousarray(cs.row_begin, dtype=np.int64)
+    y = np.ascontiguousarray(cs.y, dtype=np.float32)
+    z = np.ascontiguousarray(cs.z, dtype=np.float32)
+    ps = params.c_struct(brute)
+    lo, hi = (-1, -1) if units is None else units
+    L = lib()
+    h = L.orc_track(precision, _p(xr), len(xr), ctypes.byref(ps), cs.n_units, _p(rb), _p(y),
+                    _p(z), lo, hi, n_threads)
+    try:
+        out = {}
+        for name, dt in _DTYPES.items():
+            n = L.orc_len(h, name.encode())
+            a = np.empty(n, dtype=dt)
+            L.orc_get(h, name.encode(), _p(a))
+            out[name] = a
+    finally:
+        L.orc_free(h)
+    out["t_param"] = out["t_param"].reshape(-1, 5)
+    out["t_cov"] = out["t_cov"].reshape(-1, 15)
+    out["kept"] = out["t_n"] >= params.min_hits
+    c = out.pop("counters")
+    out["counters"] = dict(nf_pairs=int(c[0]), propagations=int(c[1]), searches=int(c[2]),
+                           window_candidates=int(c[3]), attached=int(c[4]))
+    return out
+
+
+def kept_tracklets(res):
+    """Compact the kept tracklets of a track() result into the output layout."""
+    k = np.nonzero(res["kept"])[0]
+    hb = res["t_hit_begin"]
+    n = res["t_n"][k].astype(np.int64)
+    hit_begin = np.zeros(len(k) + 1, dtype=np.int64)
+    np.cumsum(n, out=hit_begin[1:])
+    hits = np.concatenate([res["t_hits"][hb[i]:hb[i + 1]] for i in k]) if len(k) else np.zeros(0, np.int32)
+    rows = np.concatenate([res["t_rows"][hb[i]:hb[i + 1]] for i in k]) if len(k) else np.zeros(0, np.uint8)
+    return dict(index=k, unit=res["t_unit"][k], n=res["t_n"][k], r0=res["t_r0"][k],
+                flags=res["t_flags"][k], start=res["t_start"][k], hit_begin=hit_begin,
+                hits=hits, rows=rows, param=res["t_param"][k], cov=res["t_cov"][k],
+                chi2=res["t_chi2"][k], xref=res["t_xref"][k], ndf=res["t_ndf"][k],
+                row_ref=res["t_row_ref"][k])
+
+
+def replay(cs, tk, params: Params | None = None, precision=64, row_x=None):
+    """Re-run the constructor arithmetic with the given decisions forced.
+
+    ``tk`` is a dict as returned by kept_tracklets (hit_begin, hits, rows, r0,
+    flags).  Returns param [n,5], cov [n,15], chi2, xref and ok flags.
+    """
+    from synth import geometry as G
+    params = params or Params()
+    xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
+    y = np.ascontiguousarray(cs.y, dtype=np.float32)
+    z = np.ascontiguousarray(cs.z, dtype=np.float32)
+    n = len(tk["r0"])
+    hb = np.ascontiguousarray(tk["hit_begin"], dtype=np.int64)
+    hits = np.ascontiguousarray(tk["hits"], dtype=np.int32)
+    rows = np.ascontiguousarray(tk["rows"], dtype=np.uint8)
+    r0 = np.ascontiguousarray(tk["r0"], dtype=np.int32)
+    fl = np.ascontiguousarray(tk["flags"], dtype=np.int32)
+    param = np.zeros((n, 5))
+    cov = np.zeros((n, 15))
+    chi2 = np.zeros(n)
+    xref = np.zeros(n)
+    ok = np.zeros(n, dtype=np.int32)
+    ps = params.c_struct()
+    lib().orc_replay(precision, _p(xr), len(xr), ctypes.byref(ps), _p(y), _p(z), n, _p(hb),
+                     _p(hits), _p(rows), _p(r0), _p(fl), _p(param), _p(cov), _p(chi2), _p(xref),
+                     _p(ok))
+    return dict(param=param, cov=cov, chi2=chi2, xref=xref, ok=ok.astype(bool))
+
+
+STATE_FIELDS = ("x", "y", "z", "s", "t", "w", "cyy", "csy", "css", "cwy", "cws", "cww",
+                "czz", "ctz", "ctt")
+
+
+def propagate(state, x1, params: Params | None = None, precision=64):
+    """One propagation step; state is a length-15 vector (see STATE_FIELDS)."""
+    params = params or Params()
+    st = np.ascontiguousarray(state, dtype=np.float64).copy()
+    ps = params.c_struct()
+    ok = lib().orc_propagate(precision, ctypes.byref(ps), _p(st), float(x1))
+    return st, bool(ok)
+
+
+def update(state, my, mz, params: Params | None = None, precision=64):
+    """One Kalman update; returns (new state, chi2)."""
+    params = params or Params()
+    st = np.ascontiguousarray(state, dtype=np.float64).copy()
+    ps = params.c_struct()
+    ch = lib().orc_update(precision, ctypes.byref(ps), _p(st), float(my), float(mz))
+    return st, ch

@@ -1,0 +1,796 @@
+// TEST INFRASTRUCTURE ONLY -- the checking implementation ("oracle") of the
+// per-sector TPC track finding.  Only the tests, the smoke check and the CPU
+// baseline of the benchmark load it; the GPU library never does.
+//
+// A plain, slow, deliberately unoptimised CPU implementation of what the
+// paper's sector tracking computes (Section 2): a combinatorial seeding based
+// on a cellular automaton (neighbour finder over adjacent pad rows, link
+// cleaning, start hits), then track following that fits each seed with a
+// Kalman filter and picks up further clusters row by row under a chi2 cut.
+// Tracks are found several times; all instances are kept (ambiguity solving is
+// a later step of the paper's chain, not part of this one).
+//
+// The paper gives the algorithm in words only; every formula below is the
+// reading recorded with this implementation's documentation: an exact circle
+// propagation in the bending plane, a block-diagonal covariance, a 2-point
+// seed, greedy nearest-chi2 attachment with ties broken by the cluster index.
+//
+// The code is one template instantiated twice:
+//   float  -- every operation in IEEE binary32, round to nearest, no fused
+//             multiply-add (compile with -ffp-contract=off), correctly rounded
+//             divide and square root.  This precision takes the decisions, as
+//             the tracking kernels do (deterministic mode, Section 5).
+//   double -- the FP64 reference: runs the same steps, or replays the float
+//             decisions, to bound the rounding error of the float results.
+//
+// Candidate searches come in two forms that must give identical results: a
+// brute scan over every cluster of a row, and a scan of a z-sorted index over
+// a conservatively widened z window followed by the same exact predicate.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+extern "C" {
+struct OrcParams {
+  float win_y, win_z;      // neighbour-finder windows per row step [cm]
+  float d2_max;            // neighbour-finder cut on the chord deviation [cm^2]
+  float chi2_max;          // attachment cut (2 degrees of freedom)
+  float sinphi_max;        // propagation guard on |sin(phi)|
+  float u_max;             // propagation guard on |C| * chord / 2
+  float sigma_y, sigma_z;  // cluster errors [cm]
+  float cww0;              // seed variance of q/pT [(GeV/c)^-2]
+  float bz;                // field [T]
+  int32_t min_hits;        // tracklets with fewer hits are dropped
+  int32_t max_misses;      // consecutive rows without attachment that stop following
+  int32_t brute;           // 1: brute-force candidate scans
+};
+}
+
+namespace {
+
+constexpr int kFlagDescentFailed = 1;
+
+template <class T>
+struct Consts {
+  T kappa, sy2, sz2, wy, wz, d2max, chi2max, smax, umax, cww0;
+};
+
+template <class T>
+Consts<T> make_consts(const OrcParams& p) {
+  Consts<T> c;
+  // kappa = c[GeV/(T cm)] * Bz: the rate of change of sin(phi) per cm and per
+  // unit of q/pT.  Computed in double, then rounded once to T.
+  c.kappa = T(2.99792458e-3 * double(p.bz));
+  c.sy2 = T(p.sigma_y) * T(p.sigma_y);
+  c.sz2 = T(p.sigma_z) * T(p.sigma_z);
+  c.wy = T(p.win_y);
+  c.wz = T(p.win_z);
+  c.d2max = T(p.d2_max);
+  c.chi2max = T(p.chi2_max);
+  c.smax = T(p.sinphi_max);
+  c.umax = T(p.u_max);
+  c.cww0 = T(p.cww0);
+  return c;
+}
+
+// asin(u)/u: the ratio of arc length to chord for a chord of half-length u*R.
+inline float arc_over_chord(float u) {
+  const float a1 = float(1.0 / 6.0);
+  const float a2 = float(3.0 / 40.0);
+  float u2 = u * u;
+  return 1.0f + u2 * (a1 + u2 * a2);
+}
+inline double arc_over_chord(double u) { return u > 0.0 ? std::asin(u) / u : 1.0; }
+
+// Track state at the plane x: (y, z, s = sin(phi), t = dz/ds_xy, w = q/pT) and
+// the two diagonal blocks of the covariance, (y, s, w) and (z, t).
+template <class T>
+struct State {
+  T x, y, z, s, t, w;
+  T cyy, csy, css, cwy, cws, cww;
+  T czz, ctz, ctt;
+};
+
+// Propagate to the plane x1 along the circle of curvature -kappa*w.  Returns
+// false (state untouched) when |sin(phi)| would reach smax or the chord is too
+// long for the arc-length series.
+template <class T>
+bool propagate(State<T>& st, T x1, const Consts<T>& c) {
+  T dx = x1 - st.x;
+  T k = c.kappa * st.w;
+  T s1 = st.s - k * dx;
+  if (!(std::fabs(s1) < c.smax)) return false;
+  T c0 = std::sqrt(T(1) - st.s * st.s);
+  T c1 = std::sqrt(T(1) - s1 * s1);
+  T cc = c0 + c1;
+  T ss = st.s + s1;
+  T tg = ss / cc;
+  T dy = dx * tg;
+  T dl = std::sqrt(dx * dx + dy * dy);
+  T u = (std::fabs(k) * dl) * T(0.5);
+  if (!(u <= c.umax)) return false;
+  T dS = dl * arc_over_chord(u);
+  if (dx < T(0)) dS = -dS;
+  // Jacobian of (y, s) with respect to (s, w); z couples to t only.
+  T r0 = st.s / c0;
+  T r1 = s1 / c1;
+  T cc2 = cc * cc;
+  T a = dx * ((T(2) * cc + ss * (r0 + r1)) / cc2);
+  T e = -(c.kappa * dx);
+  T b = (dx * e) * ((cc + ss * r1) / cc2);
+  // C' = J C J^T, y-block
+  T Py = (st.cyy + a * st.csy) + b * st.cwy;
+  T Ps = (st.csy + a * st.css) + b * st.cws;
+  T Pw = (st.cwy + a * st.cws) + b * st.cww;
+  T Qy = st.csy + e * st.cwy;
+  T Qs = st.css + e * st.cws;
+  T Qw = st.cws + e * st.cww;
+  st.cyy = (Py + a * Ps) + b * Pw;
+  st.csy = (Qy + a * Qs) + b * Qw;
+  st.cwy = Pw;
+  st.css = Qs + e * Qw;
+  st.cws = Qw;
+  // z-block
+  T Rz = st.czz + dS * st.ctz;
+  T Rt = st.ctz + dS * st.ctt;
+  st.czz = Rz + dS * Rt;
+  st.ctz = Rt;
+  // state
+  st.y = st.y + dy;
+  st.z = st.z + st.t * dS;
+  st.s = s1;
+  st.x = x1;
+  return true;
+}
+
+template <class T>
+T chi2_of(const State<T>& st, T my, T mz, const Consts<T>& c) {
+  T ry = my - st.y;
+  T rz = mz - st.z;
+  T Sy = st.cyy + c.sy2;
+  T Sz = st.czz + c.sz2;
+  return (ry * ry) / Sy + (rz * rz) / Sz;
+}
+
+// Kalman update with the cluster (my, mz); returns the cluster's chi2.
+template <class T>
+T update(State<T>& st, T my, T mz, const Consts<T>& c) {
+  T ry = my - st.y;
+  T rz = mz - st.z;
+  T Sy = st.cyy + c.sy2;
+  T Sz = st.czz + c.sz2;
+  T chi2 = (ry * ry) / Sy + (rz * rz) / Sz;
+  T k0 = st.cyy / Sy, k1 = st.csy / Sy, k2 = st.cwy / Sy;
+  st.y = st.y + k0 * ry;
+  st.s = st.s + k1 * ry;
+  st.w = st.w + k2 * ry;
+  T cyy = st.cyy, csy = st.csy, cwy = st.cwy;
+  st.cyy = cyy - k0 * cyy;
+  st.csy = csy - k1 * cyy;
+  st.cwy = cwy - k2 * cyy;
+  st.css = st.css - k1 * csy;
+  st.cws = st.cws - k2 * csy;
+  st.cww = st.cww - k2 * cwy;
+  T kz0 = st.czz / Sz, kz1 = st.ctz / Sz;
+  st.z = st.z + kz0 * rz;
+  st.t = st.t + kz1 * rz;
+  T czz = st.czz, ctz = st.ctz;
+  st.czz = czz - kz0 * czz;
+  st.ctz = ctz - kz1 * czz;
+  st.ctt = st.ctt - kz1 * ctz;
+  return chi2;
+}
+
+// ---------------------------------------------------------------------------
+// one unit (sector): rows with their clusters, and a z-sorted index per row
+// ---------------------------------------------------------------------------
+struct RowIndex {
+  std::vector<int64_t> by_z;  // cluster indices sorted by (z, index)
+};
+
+struct Unit {
+  int n_rows;
+  const int64_t* rb;  // rb[r] .. rb[r+1]
+  const float* y;
+  const float* z;
+  std::vector<RowIndex> idx;
+  void build() {
+    idx.resize(n_rows);
+    for (int r = 0; r < n_rows; ++r) {
+      auto& v = idx[r].by_z;
+      v.clear();
+      for (int64_t i = rb[r]; i < rb[r + 1]; ++i) v.push_back(i);
+      std::sort(v.begin(), v.end(), [&](int64_t a, int64_t b) {
+        return z[a] < z[b] || (z[a] == z[b] && a < b);
+      });
+    }
+  }
+  // Calls fn(i) for every cluster of row r whose z lies in [lo, hi] (exact,
+  // double) -- a superset of every cluster the caller's exact predicate can
+  // accept when the window was widened conservatively.  Brute mode visits the
+  // whole row.
+  template <class F>
+  void scan(int r, bool brute, double lo, double hi, F&& fn) const {
+    if (brute) {
+      for (int64_t i = rb[r]; i < rb[r + 1]; ++i) fn(i);
+      return;
+    }
+    const auto& v = idx[r].by_z;
+    auto it = std::lower_bound(v.begin(), v.end(), lo,
+                               [&](int64_t a, double val) { return double(z[a]) < val; });
+    for (; it != v.end() && double(z[*it]) <= hi; ++it) fn(*it);
+  }
+};
+
+// Widening of search windows: every cluster passing an exact predicate
+// computed in float or double lies inside the window widened by this much.
+constexpr double kPadAbs = 1e-3;   // cm
+constexpr double kPadRel = 1e-4;
+
+// ---------------------------------------------------------------------------
+// neighbour finder, cleaning, start hits
+// ---------------------------------------------------------------------------
+template <class T>
+void find_neighbours(const Unit& un, const std::vector<T>& xr, bool brute, const Consts<T>& c,
+                     int32_t* link_up, int32_t* link_down, int64_t* n_pairs) {
+  const int R = un.n_rows;
+  for (int r = 0; r < R; ++r)
+    for (int64_t h = un.rb[r]; h < un.rb[r + 1]; ++h) link_up[h] = link_down[h] = -1;
+  for (int r = 1; r + 1 < R; ++r) {
+    // fraction of the way from row r-1 to row r+1 at which row r lies
+    T f = (xr[r] - xr[r - 1]) / (xr[r + 1] - xr[r - 1]);
+    std::vector<int64_t> U, D;
+    for (int64_t h = un.rb[r]; h < un.rb[r + 1]; ++h) {
+      T yh = T(un.y[h]), zh = T(un.z[h]);
+      U.clear();
+      D.clear();
+      double lo = double(un.z[h]) - double(c.wz) - kPadAbs, hi = double(un.z[h]) + double(c.wz) + kPadAbs;
+      un.scan(r + 1, brute, lo, hi, [&](int64_t u) {
+        if (std::fabs(T(un.y[u]) - yh) <= c.wy && std::fabs(T(un.z[u]) - zh) <= c.wz) U.push_back(u);
+      });
+      un.scan(r - 1, brute, lo, hi, [&](int64_t d) {
+        if (std::fabs(T(un.y[d]) - yh) <= c.wy && std::fabs(T(un.z[d]) - zh) <= c.wz) D.push_back(d);
+      });
+      T bestD = T(0);
+      int64_t bu = -1, bd = -1;
+      for (int64_t u : U) {
+        for (int64_t d : D) {
+          T yu = T(un.y[u]), zu = T(un.z[u]), yd = T(un.y[d]), zd = T(un.z[d]);
+          T ey = yh - (yd + (yu - yd) * f);
+          T ez = zh - (zd + (zu - zd) * f);
+          T D2 = ey * ey + ez * ez;
+          ++*n_pairs;
+          if (!(D2 <= c.d2max)) continue;
+          bool better = bu < 0 || D2 < bestD || (D2 == bestD && (u < bu || (u == bu && d < bd)));
+          if (better) {
+            bestD = D2;
+            bu = u;
+            bd = d;
+          }
+        }
+      }
+      link_up[h] = int32_t(bu);
+      link_down[h] = int32_t(bd);
+    }
+  }
+}
+
+// Keep a link only when the linked cluster links back.
+void clean_links(int64_t b, int64_t e, const int32_t* up, const int32_t* down, int32_t* cup,
+                 int32_t* cdown) {
+  for (int64_t h = b; h < e; ++h) {
+    int32_t u = up[h], d = down[h];
+    cup[h] = (u >= 0 && down[u] == h) ? u : -1;
+    cdown[h] = (d >= 0 && up[d] == h) ? d : -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tracklet constructor
+// ---------------------------------------------------------------------------
+template <class T>
+struct Tracklet {
+  int64_t start;
+  int32_t unit, r0, n, flags, row_ref;
+  State<T> st;
+  T chi2;
+  std::vector<int32_t> hits;  // sorted by row
+  std::vector<uint8_t> rows;
+  // work counters
+  int64_t n_prop = 0, n_search = 0, n_box = 0;
+};
+
+template <class T>
+struct Searcher {
+  const Unit& un;
+  bool brute;
+  const Consts<T>& c;
+  // Best cluster of row r by (chi2, index) among those with chi2 <= chi2max.
+  int64_t best(const State<T>& st, int r, T* chi2_out, int64_t* n_box) const {
+    double sz = std::sqrt(double(c.chi2max) * double(st.czz + c.sz2));
+    double hw = sz * (1.0 + kPadRel) + kPadAbs;
+    double lo = double(st.z) - hw, hi = double(st.z) + hw;
+    int64_t bi = -1;
+    T bc = T(0);
+    un.scan(r, brute, lo, hi, [&](int64_t i) {
+      ++*n_box;
+      T ch = chi2_of(st, T(un.y[i]), T(un.z[i]), c);
+      if (!(ch <= c.chi2max)) return;
+      if (bi < 0 || ch < bc || (ch == bc && i < bi)) {
+        bi = i;
+        bc = ch;
+      }
+    });
+    *chi2_out = bc;
+    return bi;
+  }
+};
+
+template <class T>
+Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, const int32_t* cup,
+                      int64_t h0, int r0, bool brute, const Consts<T>& c, int max_misses) {
+  const int R = un.n_rows;
+  Tracklet<T> tk;
+  tk.start = h0;
+  tk.unit = unit_id;
+  tk.r0 = r0;
+  tk.flags = 0;
+  Searcher<T> se{un, brute, c};
+  std::vector<std::pair<int, int32_t>> att;  // (row, cluster)
+
+  std::vector<int64_t> chain{h0};
+  while (cup[chain.back()] >= 0) chain.push_back(cup[chain.back()]);
+
+  // 2-point seed at the second chain cluster
+  int64_t c0 = chain[0], c1 = chain[1];
+  State<T> st;
+  T dx = xr[r0 + 1] - xr[r0];
+  T dy = T(un.y[c1]) - T(un.y[c0]);
+  T dz = T(un.z[c1]) - T(un.z[c0]);
+  T dl = std::sqrt(dx * dx + dy * dy);
+  st.x = xr[r0 + 1];
+  st.y = T(un.y[c1]);
+  st.z = T(un.z[c1]);
+  st.s = dy / dl;
+  st.t = dz / dl;
+  st.w = T(0);
+  st.cyy = c.sy2;
+  st.csy = c.sy2 / dl;
+  st.css = (c.sy2 + c.sy2) / (dl * dl);
+  st.cwy = T(0);
+  st.cws = T(0);
+  st.cww = c.cww0;
+  st.czz = c.sz2;
+  st.ctz = c.sz2 / dl;
+  st.ctt = (c.sz2 + c.sz2) / (dl * dl);
+  T chi2 = T(0);
+  int n = 2;
+  att.push_back({r0, int32_t(c0)});
+  att.push_back({r0 + 1, int32_t(c1)});
+  int row = r0 + 1;
+
+  // the rest of the chain, attached without a cut
+  bool up_ok = true;
+  for (size_t j = 2; j < chain.size(); ++j) {
+    int rr = r0 + int(j);
+    ++tk.n_prop;
+    if (!propagate(st, xr[rr], c)) {
+      up_ok = false;
+      break;
+    }
+    chi2 = chi2 + update(st, T(un.y[chain[j]]), T(un.z[chain[j]]), c);
+    ++n;
+    att.push_back({rr, int32_t(chain[j])});
+    row = rr;
+  }
+  State<T> best = st;
+  int best_row = row;
+
+  // following outwards
+  if (up_ok) {
+    int misses = 0;
+    for (int rr = row + 1; rr < R; ++rr) {
+      ++tk.n_prop;
+      if (!propagate(st, xr[rr], c)) break;
+      ++tk.n_search;
+      T ch;
+      int64_t hi = se.best(st, rr, &ch, &tk.n_box);
+      if (hi >= 0) {
+        chi2 = chi2 + update(st, T(un.y[hi]), T(un.z[hi]), c);
+        ++n;
+        att.push_back({rr, int32_t(hi)});
+        best = st;
+        best_row = rr;
+        misses = 0;
+      } else if (++misses == max_misses) {
+        break;
+      }
+    }
+  }
+
+  // back to the start row, then following inwards
+  st = best;
+  bool down_ok = true;
+  for (int rr = best_row - 1; rr >= r0; --rr) {
+    ++tk.n_prop;
+    if (!propagate(st, xr[rr], c)) {
+      down_ok = false;
+      break;
+    }
+  }
+  State<T> out = best;
+  int out_row = best_row;
+  if (!down_ok) {
+    tk.flags |= kFlagDescentFailed;
+  } else {
+    out = st;
+    out_row = r0;
+    int misses = 0;
+    for (int rr = r0 - 1; rr >= 0; --rr) {
+      ++tk.n_prop;
+      if (!propagate(st, xr[rr], c)) break;
+      ++tk.n_search;
+      T ch;
+      int64_t hi = se.best(st, rr, &ch, &tk.n_box);
+      if (hi >= 0) {
+        chi2 = chi2 + update(st, T(un.y[hi]), T(un.z[hi]), c);
+        ++n;
+        att.push_back({rr, int32_t(hi)});
+        out = st;
+        out_row = rr;
+        misses = 0;
+      } else if (++misses == max_misses) {
+        break;
+      }
+    }
+  }
+
+  std::sort(att.begin(), att.end());
+  for (auto& a : att) {
+    tk.hits.push_back(a.second);
+    tk.rows.push_back(uint8_t(a.first));
+  }
+  tk.n = n;
+  tk.st = out;
+  tk.row_ref = out_row;
+  tk.chi2 = chi2;
+  return tk;
+}
+
+// Re-run the constructor's arithmetic with the attachment decisions forced:
+// hits sorted by row, the start row r0, and whether the descent failed.
+// Returns false when a propagation fails where the decisions say it did not.
+template <class T>
+bool replay(const std::vector<T>& xr, const float* y, const float* z, const int32_t* hits,
+            const uint8_t* rows, int n, int r0, int flags, const Consts<T>& c, State<T>* out_st,
+            int* out_row, T* out_chi2) {
+  int k0 = -1;  // first hit at or above r0
+  for (int i = 0; i < n; ++i)
+    if (rows[i] == r0) {
+      k0 = i;
+      break;
+    }
+  if (k0 < 0 || k0 + 1 >= n || rows[k0 + 1] != r0 + 1) return false;
+  int32_t c0 = hits[k0], c1 = hits[k0 + 1];
+  State<T> st;
+  T dx = xr[r0 + 1] - xr[r0];
+  T dy = T(y[c1]) - T(y[c0]);
+  T dz = T(z[c1]) - T(z[c0]);
+  T dl = std::sqrt(dx * dx + dy * dy);
+  st.x = xr[r0 + 1];
+  st.y = T(y[c1]);
+  st.z = T(z[c1]);
+  st.s = dy / dl;
+  st.t = dz / dl;
+  st.w = T(0);
+  st.cyy = c.sy2;
+  st.csy = c.sy2 / dl;
+  st.css = (c.sy2 + c.sy2) / (dl * dl);
+  st.cwy = T(0);
+  st.cws = T(0);
+  st.cww = c.cww0;
+  st.czz = c.sz2;
+  st.ctz = c.sz2 / dl;
+  st.ctt = (c.sz2 + c.sz2) / (dl * dl);
+  T chi2 = T(0);
+  int row = r0 + 1;
+  for (int i = k0 + 2; i < n; ++i) {
+    for (int rr = row + 1; rr <= rows[i]; ++rr)
+      if (!propagate(st, xr[rr], c)) return false;
+    chi2 = chi2 + update(st, T(y[hits[i]]), T(z[hits[i]]), c);
+    row = rows[i];
+  }
+  State<T> best = st;
+  int best_row = row;
+  if (flags & kFlagDescentFailed) {
+    *out_st = best;
+    *out_row = best_row;
+    *out_chi2 = chi2;
+    return k0 == 0;
+  }
+  for (int rr = best_row - 1; rr >= r0; --rr)
+    if (!propagate(st, xr[rr], c)) return false;
+  row = r0;
+  State<T> out = st;
+  int orow = r0;
+  for (int i = k0 - 1; i >= 0; --i) {
+    for (int rr = row - 1; rr >= rows[i]; --rr)
+      if (!propagate(st, xr[rr], c)) return false;
+    chi2 = chi2 + update(st, T(y[hits[i]]), T(z[hits[i]]), c);
+    row = rows[i];
+    out = st;
+    orow = row;
+  }
+  *out_st = out;
+  *out_row = orow;
+  *out_chi2 = chi2;
+  return true;
+}
+
+// 15 lower-triangle entries (row-major) of the 5x5 covariance of (y,z,s,t,w).
+template <class T>
+void cov15(const State<T>& s, double* o) {
+  const double v[15] = {double(s.cyy), 0.0, double(s.czz), double(s.csy), 0.0, double(s.css),
+                        0.0, double(s.ctz), 0.0, double(s.ctt), double(s.cwy), 0.0, double(s.cws),
+                        0.0, double(s.cww)};
+  std::memcpy(o, v, sizeof v);
+}
+
+// ---------------------------------------------------------------------------
+// whole-input driver
+// ---------------------------------------------------------------------------
+struct Result {
+  std::vector<int32_t> link_up, link_down, clean_up, clean_down;
+  std::vector<int64_t> starts;
+  // one entry per start hit
+  std::vector<int64_t> t_start, t_hit_begin;
+  std::vector<int32_t> t_unit, t_r0, t_n, t_flags, t_row_ref, t_ndf, t_hits;
+  std::vector<uint8_t> t_rows;
+  std::vector<double> t_param, t_cov, t_chi2, t_xref;
+  std::vector<int64_t> counters;  // n_pairs, n_prop, n_search, n_box, n_attached
+};
+
+template <class T>
+Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
+            const int64_t* row_begin, const float* y, const float* z, int unit_lo, int unit_hi,
+            int n_threads) {
+  Consts<T> c = make_consts<T>(p);
+  std::vector<T> xr(n_rows);
+  for (int r = 0; r < n_rows; ++r) xr[r] = T(row_x[r]);
+  const int64_t N = row_begin[int64_t(n_units) * n_rows];
+  auto* res = new Result;
+  res->link_up.assign(N, -1);
+  res->link_down.assign(N, -1);
+  res->clean_up.assign(N, -1);
+  res->clean_down.assign(N, -1);
+  if (unit_lo < 0) unit_lo = 0;
+  if (unit_hi > n_units || unit_hi < 0) unit_hi = n_units;
+  int nu = std::max(0, unit_hi - unit_lo);
+  std::vector<std::vector<int64_t>> starts(nu);
+  std::vector<std::vector<Tracklet<T>>> tks(nu);
+  std::vector<int64_t> pairs(nu, 0);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int k = 0; k < nu; ++k) {
+    int u = unit_lo + k;
+    Unit un;
+    un.n_rows = n_rows;
+    un.rb = row_begin + int64_t(u) * n_rows;
+    un.y = y;
+    un.z = z;
+    un.build();
+    find_neighbours<T>(un, xr, p.brute != 0, c, res->link_up.data(), res->link_down.data(), &pairs[k]);
+    clean_links(un.rb[0], un.rb[n_rows], res->link_up.data(), res->link_down.data(),
+                res->clean_up.data(), res->clean_down.data());
+    const int32_t* cup = res->clean_up.data();
+    const int32_t* cdn = res->clean_down.data();
+    for (int r = 0; r < n_rows; ++r)
+      for (int64_t h = un.rb[r]; h < un.rb[r + 1]; ++h) {
+        int32_t uu = cup[h];
+        if (cdn[h] < 0 && uu >= 0 && cup[uu] >= 0) starts[k].push_back(h);
+      }
+    for (int64_t h : starts[k]) {
+      int r0 = 0;
+      while (!(h >= un.rb[r0] && h < un.rb[r0 + 1])) ++r0;
+      tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses));
+    }
+  }
+  int64_t np = 0, nprop = 0, nsearch = 0, nbox = 0, natt = 0;
+  for (int k = 0; k < nu; ++k) {
+    np += pairs[k];
+    for (int64_t h : starts[k]) res->starts.push_back(h);
+    for (auto& tk : tks[k]) {
+      res->t_start.push_back(tk.start);
+      res->t_unit.push_back(tk.unit);
+      res->t_r0.push_back(tk.r0);
+      res->t_n.push_back(tk.n);
+      res->t_flags.push_back(tk.flags);
+      res->t_row_ref.push_back(tk.row_ref);
+      res->t_ndf.push_back(2 * tk.n - 5);
+      res->t_hit_begin.push_back(int64_t(res->t_hits.size()));
+      for (size_t i = 0; i < tk.hits.size(); ++i) {
+        res->t_hits.push_back(tk.hits[i]);
+        res->t_rows.push_back(tk.rows[i]);
+      }
+      const double pv[5] = {double(tk.st.y), double(tk.st.z), double(tk.st.s), double(tk.st.t),
+                            double(tk.st.w)};
+      res->t_param.insert(res->t_param.end(), pv, pv + 5);
+      double cv[15];
+      cov15(tk.st, cv);
+      res->t_cov.insert(res->t_cov.end(), cv, cv + 15);
+      res->t_chi2.push_back(double(tk.chi2));
+      res->t_xref.push_back(double(tk.st.x));
+      nprop += tk.n_prop;
+      nsearch += tk.n_search;
+      nbox += tk.n_box;
+      natt += tk.n;
+    }
+  }
+  res->t_hit_begin.push_back(int64_t(res->t_hits.size()));
+  res->counters = {np, nprop, nsearch, nbox, natt};
+  return res;
+}
+
+template <class V>
+int64_t vlen(const V& v) {
+  return int64_t(v.size());
+}
+
+}  // namespace
+
+extern "C" {
+
+// precision: 32 (float, decisions) or 64 (double).  Units [unit_lo, unit_hi)
+// are processed (-1 for all); links of other units stay -1.
+void* orc_track(int precision, const float* row_x, int n_rows, const OrcParams* p, int n_units,
+                const int64_t* row_begin, const float* y, const float* z, int unit_lo, int unit_hi,
+                int n_threads) {
+  if (precision == 64)
+    return run<double>(row_x, n_rows, *p, n_units, row_begin, y, z, unit_lo, unit_hi, n_threads);
+  return run<float>(row_x, n_rows, *p, n_units, row_begin, y, z, unit_lo, unit_hi, n_threads);
+}
+
+void orc_free(void* h) { delete static_cast<Result*>(h); }
+
+// Length (in elements) of a named result array, or -1.
+int64_t orc_len(void* h, const char* name) {
+  auto* r = static_cast<Result*>(h);
+  std::string n(name);
+  if (n == "link_up") return vlen(r->link_up);
+  if (n == "link_down") return vlen(r->link_down);
+  if (n == "clean_up") return vlen(r->clean_up);
+  if (n == "clean_down") return vlen(r->clean_down);
+  if (n == "starts") return vlen(r->starts);
+  if (n == "t_start") return vlen(r->t_start);
+  if (n == "t_hit_begin") return vlen(r->t_hit_begin);
+  if (n == "t_unit") return vlen(r->t_unit);
+  if (n == "t_r0") return vlen(r->t_r0);
+  if (n == "t_n") return vlen(r->t_n);
+  if (n == "t_flags") return vlen(r->t_flags);
+  if (n == "t_row_ref") return vlen(r->t_row_ref);
+  if (n == "t_ndf") return vlen(r->t_ndf);
+  if (n == "t_hits") return vlen(r->t_hits);
+  if (n == "t_rows") return vlen(r->t_rows);
+  if (n == "t_param") return vlen(r->t_param);
+  if (n == "t_cov") return vlen(r->t_cov);
+  if (n == "t_chi2") return vlen(r->t_chi2);
+  if (n == "t_xref") return vlen(r->t_xref);
+  if (n == "counters") return vlen(r->counters);
+  return -1;
+}
+
+// Copies a named result array into dst (caller sized it with orc_len).
+int orc_get(void* h, const char* name, void* dst) {
+  auto* r = static_cast<Result*>(h);
+  std::string n(name);
+  auto cp = [&](const auto& v) {
+    if (!v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    return 0;
+  };
+  if (n == "link_up") return cp(r->link_up);
+  if (n == "link_down") return cp(r->link_down);
+  if (n == "clean_up") return cp(r->clean_up);
+  if (n == "clean_down") return cp(r->clean_down);
+  if (n == "starts") return cp(r->starts);
+  if (n == "t_start") return cp(r->t_start);
+  if (n == "t_hit_begin") return cp(r->t_hit_begin);
+  if (n == "t_unit") return cp(r->t_unit);
+  if (n == "t_r0") return cp(r->t_r0);
+  if (n == "t_n") return cp(r->t_n);
+  if (n == "t_flags") return cp(r->t_flags);
+  if (n == "t_row_ref") return cp(r->t_row_ref);
+  if (n == "t_ndf") return cp(r->t_ndf);
+  if (n == "t_hits") return cp(r->t_hits);
+  if (n == "t_rows") return cp(r->t_rows);
+  if (n == "t_param") return cp(r->t_param);
+  if (n == "t_cov") return cp(r->t_cov);
+  if (n == "t_chi2") return cp(r->t_chi2);
+  if (n == "t_xref") return cp(r->t_xref);
+  if (n == "counters") return cp(r->counters);
+  return -1;
+}
+
+// FP64 (or float) replay of given tracklets.  hit_begin has n_tracks+1
+// entries into hits/rows.  Writes params [5], cov [15], chi2, x_ref and a
+// status (1 ok, 0 a propagation failed) per tracklet.
+void orc_replay(int precision, const float* row_x, int n_rows, const OrcParams* p, const float* y,
+                const float* z, int64_t n_tracks, const int64_t* hit_begin, const int32_t* hits,
+                const uint8_t* rows, const int32_t* r0, const int32_t* flags, double* param,
+                double* cov, double* chi2, double* xref, int32_t* ok) {
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    Consts<T> c = make_consts<T>(*p);
+    std::vector<T> xr(n_rows);
+    for (int r = 0; r < n_rows; ++r) xr[r] = T(row_x[r]);
+    for (int64_t i = 0; i < n_tracks; ++i) {
+      State<T> st{};
+      int orow = 0;
+      T ch = T(0);
+      int64_t b = hit_begin[i];
+      int n = int(hit_begin[i + 1] - b);
+      bool good = replay<T>(xr, y, z, hits + b, rows + b, n, r0[i], flags[i], c, &st, &orow, &ch);
+      ok[i] = good ? 1 : 0;
+      const double pv[5] = {double(st.y), double(st.z), double(st.s), double(st.t), double(st.w)};
+      std::memcpy(param + 5 * i, pv, sizeof pv);
+      cov15(st, cov + 15 * i);
+      chi2[i] = double(ch);
+      xref[i] = double(st.x);
+    }
+  };
+  if (precision == 64)
+    go(0.0);
+  else
+    go(0.0f);
+}
+
+// Single propagation step (for closed-form pins).  state: x,y,z,s,t,w then
+// the 9 covariance numbers (yy, sy, ss, wy, ws, ww, zz, tz, tt).  Returns 1 on
+// success, 0 when a guard stops it.
+int orc_propagate(int precision, const OrcParams* p, double* state, double x1) {
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    Consts<T> c = make_consts<T>(*p);
+    State<T> st{T(state[0]), T(state[1]), T(state[2]), T(state[3]), T(state[4]), T(state[5]),
+                T(state[6]), T(state[7]), T(state[8]), T(state[9]), T(state[10]), T(state[11]),
+                T(state[12]), T(state[13]), T(state[14])};
+    bool ok = propagate(st, T(x1), c);
+    const double v[15] = {double(st.x), double(st.y), double(st.z), double(st.s), double(st.t),
+                          double(st.w), double(st.cyy), double(st.csy), double(st.css),
+                          double(st.cwy), double(st.cws), double(st.cww), double(st.czz),
+                          double(st.ctz), double(st.ctt)};
+    std::memcpy(state, v, sizeof v);
+    return ok ? 1 : 0;
+  };
+  return precision == 64 ? go(0.0) : go(0.0f);
+}
+
+// Single Kalman update (for closed-form pins); same state layout.  Returns chi2.
+double orc_update(int precision, const OrcParams* p, double* state, double my, double mz) {
+  auto go = [&](auto tag) {
+    using T = decltype(tag);
+    Consts<T> c = make_consts<T>(*p);
+    State<T> st{T(state[0]), T(state[1]), T(state[2]), T(state[3]), T(state[4]), T(state[5]),
+                T(state[6]), T(state[7]), T(state[8]), T(state[9]), T(state[10]), T(state[11]),
+                T(state[12]), T(state[13]), T(state[14])};
+    T ch = update(st, T(my), T(mz), c);
+    const double v[15] = {double(st.x), double(st.y), double(st.z), double(st.s), double(st.t),
+                          double(st.w), double(st.cyy), double(st.csy), double(st.css),
+                          double(st.cwy), double(st.cws), double(st.cww), double(st.czz),
+                          double(st.ctz), double(st.ctt)};
+    std::memcpy(state, v, sizeof v);
+    return double(ch);
+  };
+  return precision == 64 ? go(0.0) : go(0.0f);
+}
+
+}  // extern "C"

@@ -1,0 +1,7 @@
+"""Seeded synthetic inputs: detector description and cluster sets."""
+from . import geometry
+from .events import (ClusterSet, RadialDistortion, Tracks, build_clusters, central_event,
+                     exact_tracks, helix_crossings, single_sector, timeframe_slice)
+
+__all__ = ["geometry", "ClusterSet", "RadialDistortion", "Tracks", "build_clusters",
+           "central_event", "exact_tracks", "helix_crossings", "single_sector", "timeframe_slice"]
