@@ -1,0 +1,165 @@
+/*
+ * tpcx -- per-sector TPC track finding on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the sector tracking of the ALICE TPC reconstruction
+ * (arXiv 2601.20569, Section 2): clusters organised by sector and pad row go
+ * in; a cellular-automaton seeding (neighbour finder over adjacent rows,
+ * mutual-link cleaning, start hits) is followed by a Kalman-filter track
+ * following that picks up clusters row by row under a chi2 cut; track
+ * candidates ("tracklets") with their cluster ids, helix parameters,
+ * covariances and chi2 come out.  As the paper states, one particle usually
+ * yields several candidates; all are returned (no ambiguity solving here).
+ *
+ * Conventions (the paper fixes none of them; they are this library's):
+ *   - a "unit" is one sector of one event or time-frame slice; units are
+ *     independent.  Each unit has n_rows pad rows, planes at local x = row_x[r].
+ *   - a cluster is (y, z) in the unit's local frame: y along the pad row, z the
+ *     drift coordinate.  Cluster id = its index in the caller's arrays.
+ *   - track state at plane x: (y, z, sin(phi), dz/ds_xy, q/pT [(GeV/c)^-1]);
+ *     sin(phi) changes by -kappa * q/pT per cm of x, kappa = 2.99792458e-3 * Bz.
+ *   - every floating-point operation that takes a decision is IEEE binary32,
+ *     round-to-nearest, without contraction, so that results are reproducible
+ *     bit for bit (the paper's deterministic mode, Section 5).
+ *
+ * Memory: every pointer is a device (HIP) address unless its name ends in
+ * _host.  The caller owns all inputs, outputs and the workspace; the context
+ * owns only immutable tables built at creation.  No call allocates device
+ * memory.  Calls enqueue work on the given stream and return; a context may be
+ * used by one stream at a time.
+ *
+ * Errors: argument errors are returned at once and nothing is enqueued.
+ * Conditions found on the device (a capacity too small) are written to
+ * counts[3] of the output (bit set) with the REQUIRED sizes in counts[0..2];
+ * outputs are then truncated but consistent, and the caller may resize and
+ * call again.  No C++ exception crosses this interface.
+ */
+#ifndef TPCX_H_
+#define TPCX_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tpcx_status;
+#define TPCX_OK 0
+#define TPCX_E_ARG (-1)      /* invalid argument; nothing enqueued */
+#define TPCX_E_CAPACITY (-2) /* reported by tpcx_poll: a device capacity was exceeded */
+#define TPCX_E_HIP (-3)      /* a HIP runtime call failed */
+#define TPCX_E_DEVICE (-4)   /* current device is not gfx950 */
+
+/* device status bits, counts[3] of tpcx_tracks */
+#define TPCX_ST_START_OVERFLOW 1 /* more start hits than cap_start */
+#define TPCX_ST_TRACK_OVERFLOW 2 /* more tracklets than cap_tracks */
+#define TPCX_ST_HIT_OVERFLOW 4   /* more attached clusters than cap_hits */
+
+typedef struct tpcx_ctx tpcx_ctx;
+
+/* Detector description: the pad-row planes of a sector (Section 2: two halves
+ * of 18 trapezoidal sectors, each with pad rows). */
+typedef struct {
+  int32_t n_rows;            /* 3 .. 255 */
+  const float* row_x_host;   /* [n_rows] strictly increasing plane distances, cm */
+  float tan_half_opening;    /* half-width of a row = row_x * tan_half_opening (tan 10 deg) */
+  float bz_tesla;            /* solenoid field */
+} tpcx_geometry;
+
+/* Method parameters (Section 2 describes the steps; the values are readings). */
+typedef struct {
+  float win_y, win_z;   /* neighbour finder: |dy|, |dz| window to the adjacent rows, cm */
+  float d2_max;         /* neighbour finder: cut on the squared chord deviation, cm^2 */
+  float chi2_max;       /* following: attach a cluster if its chi2 <= chi2_max */
+  float sinphi_max;     /* propagation stops when |sin(phi)| would reach this */
+  float u_max;          /* propagation stops when |curvature| * chord / 2 exceeds this */
+  float sigma_y, sigma_z; /* cluster errors, cm */
+  float cww0;           /* seed variance of q/pT, (GeV/c)^-2 */
+  int32_t min_hits;     /* tracklets with fewer clusters are dropped */
+  int32_t max_misses;   /* consecutive rows without a cluster that end following */
+} tpcx_params;
+
+/* Launch and search-grid tuning.  Never changes results. */
+typedef struct {
+  float bin_y;          /* search-grid bin width along the pad row, cm */
+  int32_t n_zbins;      /* search-grid bins along z per unit (z range taken from data) */
+  int32_t block;        /* threads per block of the per-cluster kernels (64..1024) */
+  int32_t construct_block; /* threads per block of the tracklet constructor */
+  int32_t construct_grid;  /* blocks of the tracklet constructor (work-queue driven) */
+} tpcx_tuning;
+
+/* Clusters grouped by (unit, row): those of unit u, row r are the index range
+ * [row_begin[u*n_rows + r], row_begin[u*n_rows + r + 1]).  Order inside a
+ * range is free.  n_clusters = row_begin[n_units*n_rows] < 2^31. */
+typedef struct {
+  int32_t n_units;
+  int64_t n_clusters;
+  const int64_t* row_begin; /* [n_units*n_rows + 1] */
+  const float* y;           /* [n_clusters] */
+  const float* z;           /* [n_clusters] */
+} tpcx_clusters;
+
+/* Tracklets, in the order of their start hits (ascending cluster index). */
+typedef struct {
+  int64_t cap_tracks;   /* capacity of the per-tracklet arrays */
+  int64_t cap_hits;     /* capacity of hit_id / hit_row */
+  int64_t* counts;      /* [4]: n_start, n_tracks, n_hits (required sizes), status bits */
+  int32_t* unit;        /* [cap_tracks] unit of the tracklet */
+  int32_t* start;       /* [cap_tracks] start-hit cluster id */
+  int32_t* n_hits;      /* [cap_tracks] clusters attached */
+  int64_t* hit_begin;   /* [cap_tracks] offset of the tracklet's clusters in hit_id */
+  int32_t* hit_id;      /* [cap_hits] cluster ids, sorted by row within a tracklet */
+  uint8_t* hit_row;     /* [cap_hits] their rows */
+  float* x_ref;         /* [cap_tracks] plane of the parameters: innermost attached row */
+  float* param;         /* [cap_tracks][5] y, z, sin(phi), dz/ds, q/pT */
+  float* cov;           /* [cap_tracks][15] lower triangle of the 5x5 covariance, row-major */
+  float* chi2;          /* [cap_tracks] */
+  int32_t* ndf;         /* [cap_tracks] 2*n_hits - 5 */
+} tpcx_tracks;
+
+/* Optional intermediate results (each pointer may be NULL). */
+typedef struct {
+  int32_t* link_up;     /* [n_clusters] neighbour finder: best cluster in row r+1, or -1 */
+  int32_t* link_down;   /* [n_clusters] best cluster in row r-1, or -1 */
+  int32_t* clean_up;    /* [n_clusters] after keeping only mutual links */
+  int32_t* clean_down;  /* [n_clusters] */
+  int32_t* starts;      /* [cap_start] start hits, ascending */
+} tpcx_debug;
+
+/* Fill *t with the default tuning for a workload of this size. */
+void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t);
+
+/* Create a context on the current HIP device.  tuning may be NULL (defaults
+ * chosen per call from the input size).  Returns TPCX_E_DEVICE on a device
+ * that is not gfx950. */
+tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx_tuning* tuning,
+                        tpcx_ctx** out);
+void tpcx_destroy(tpcx_ctx* ctx);
+
+/* Bytes of workspace tpcx_track needs for this input size and start-hit
+ * capacity (cap_start <= n_clusters/3 + 1 can never overflow: every start hit
+ * owns a chain of at least three clusters). */
+size_t tpcx_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters,
+                            int64_t cap_start);
+
+/* Sector tracking of every unit of `in` (Section 2: seeding by the cellular
+ * automaton, then track following with the Kalman filter).  ws must hold
+ * tpcx_workspace_bytes(ctx, in->n_units, in->n_clusters, cap_start) bytes,
+ * 256-byte aligned.  out->counts is written on the device. */
+tpcx_status tpcx_track(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                       int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
+                       hipStream_t stream);
+
+/* Waits for the stream and returns TPCX_E_CAPACITY if the last tpcx_track on
+ * it overflowed a capacity, TPCX_E_HIP on a runtime error, else TPCX_OK. */
+tpcx_status tpcx_poll(tpcx_ctx* ctx, const tpcx_tracks* out, hipStream_t stream);
+
+const char* tpcx_strerror(tpcx_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCX_H_ */

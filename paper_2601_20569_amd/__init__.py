@@ -1,0 +1,269 @@
+"""MI355X-native per-sector TPC track finding (arXiv 2601.20569, Section 2).
+
+A thin ctypes binding of ``libtpcx.so`` (the C interface in include/tpcx.h).
+PyTorch provides device memory and the stream; every step of the tracking
+runs in the library's HIP kernels.  There is no CPU fallback: without the
+built library on a gfx950 device the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+from .build import LIB
+
+TPCX_OK = 0
+TPCX_E_ARG = -1
+TPCX_E_CAPACITY = -2
+TPCX_E_HIP = -3
+TPCX_E_DEVICE = -4
+ST_START_OVERFLOW, ST_TRACK_OVERFLOW, ST_HIT_OVERFLOW = 1, 2, 4
+
+
+class TpcxError(RuntimeError):
+    pass
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("row_x_host", ctypes.POINTER(ctypes.c_float)),
+                ("tan_half_opening", ctypes.c_float), ("bz_tesla", ctypes.c_float)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("win_y", ctypes.c_float), ("win_z", ctypes.c_float), ("d2_max", ctypes.c_float),
+                ("chi2_max", ctypes.c_float), ("sinphi_max", ctypes.c_float),
+                ("u_max", ctypes.c_float), ("sigma_y", ctypes.c_float),
+                ("sigma_z", ctypes.c_float), ("cww0", ctypes.c_float),
+                ("min_hits", ctypes.c_int32), ("max_misses", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("bin_y", ctypes.c_float), ("n_zbins", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("construct_block", ctypes.c_int32), ("construct_grid", ctypes.c_int32)]
+
+
+class Clusters(ctypes.Structure):
+    _fields_ = [("n_units", ctypes.c_int32), ("n_clusters", ctypes.c_int64),
+                ("row_begin", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class Tracks(ctypes.Structure):
+    _fields_ = [("cap_tracks", ctypes.c_int64), ("cap_hits", ctypes.c_int64),
+                ("counts", ctypes.c_void_p), ("unit", ctypes.c_void_p), ("start", ctypes.c_void_p),
+                ("n_hits", ctypes.c_void_p), ("hit_begin", ctypes.c_void_p),
+                ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p),
+                ("x_ref", ctypes.c_void_p), ("param", ctypes.c_void_p), ("cov", ctypes.c_void_p),
+                ("chi2", ctypes.c_void_p), ("ndf", ctypes.c_void_p)]
+
+
+class Debug(ctypes.Structure):
+    _fields_ = [("link_up", ctypes.c_void_p), ("link_down", ctypes.c_void_p),
+                ("clean_up", ctypes.c_void_p), ("clean_down", ctypes.c_void_p),
+                ("starts", ctypes.c_void_p)]
+
+
+EXPORTS = ("tpcx_default_tuning", "tpcx_create", "tpcx_destroy", "tpcx_workspace_bytes",
+           "tpcx_track", "tpcx_poll", "tpcx_strerror")
+
+_lib = None
+
+
+def lib():
+    """Load libtpcx.so (built by paper_2601_20569_amd.build.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise TpcxError(f"{LIB} is missing: build it with paper_2601_20569_amd.build.build()")
+        L = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        L.tpcx_default_tuning.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Tuning)]
+        L.tpcx_default_tuning.restype = None
+        L.tpcx_create.argtypes = [ctypes.POINTER(Geometry), ctypes.POINTER(Params),
+                                  ctypes.POINTER(Tuning), ctypes.POINTER(P)]
+        L.tpcx_create.restype = ctypes.c_int32
+        L.tpcx_destroy.argtypes = [P]
+        L.tpcx_destroy.restype = None
+        L.tpcx_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+        L.tpcx_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_track.argtypes = [P, ctypes.POINTER(Clusters), P, ctypes.c_size_t, ctypes.c_int64,
+                                 ctypes.POINTER(Tracks), ctypes.POINTER(Debug), P]
+        L.tpcx_track.restype = ctypes.c_int32
+        L.tpcx_poll.argtypes = [P, ctypes.POINTER(Tracks), P]
+        L.tpcx_poll.restype = ctypes.c_int32
+        L.tpcx_strerror.argtypes = [ctypes.c_int32]
+        L.tpcx_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != TPCX_OK:
+        raise TpcxError(f"{what}: {lib().tpcx_strerror(st).decode()} ({st})")
+
+
+def default_tuning(n_units, n_clusters):
+    t = Tuning()
+    lib().tpcx_default_tuning(n_units, n_clusters, ctypes.byref(t))
+    return t
+
+
+@dataclass
+class MethodParams:
+    """Values of the method's cuts (cm, GeV/c)."""
+    win_y: float = 2.0
+    win_z: float = 2.0
+    d2_max: float = 0.36
+    chi2_max: float = 16.0
+    sinphi_max: float = 0.99
+    u_max: float = 0.1
+    sigma_y: float = 0.1
+    sigma_z: float = 0.1
+    cww0: float = 100.0
+    min_hits: int = 10
+    max_misses: int = 8
+
+    def c_struct(self):
+        return Params(self.win_y, self.win_z, self.d2_max, self.chi2_max, self.sinphi_max,
+                      self.u_max, self.sigma_y, self.sigma_z, self.cww0, self.min_hits,
+                      self.max_misses)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+class SectorTracker:
+    """A tpcx context: geometry and parameters fixed, many calls.
+
+    ``row_x``: pad-row plane distances (cm); ``tan_half_opening``: tan of the
+    sector half-angle; ``bz``: field in T.  ``tuning`` (a Tuning) fixes the
+    search grid and launch shapes; None chooses them per call.
+    """
+
+    def __init__(self, row_x, tan_half_opening, bz, params: MethodParams | None = None,
+                 tuning: Tuning | None = None):
+        import numpy as np
+        import torch
+        if not torch.cuda.is_available():
+            raise TpcxError("no HIP device visible")
+        self.params = params or MethodParams()
+        self.row_x = np.ascontiguousarray(row_x, dtype=np.float32)
+        self.n_rows = len(self.row_x)
+        g = Geometry(self.n_rows, self.row_x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                     float(tan_half_opening), float(bz))
+        p = self.params.c_struct()
+        h = ctypes.c_void_p()
+        _check(lib().tpcx_create(ctypes.byref(g), ctypes.byref(p),
+                                 ctypes.byref(tuning) if tuning is not None else None,
+                                 ctypes.byref(h)), "tpcx_create")
+        self._h = h
+        self.device = torch.cuda.current_device()
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tpcx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, n_units, n_clusters, cap_start):
+        return int(lib().tpcx_workspace_bytes(self._h, n_units, n_clusters, cap_start))
+
+    def allocate(self, n_units, n_clusters, cap_start=None, cap_tracks=None, cap_hits=None):
+        """Device buffers for one call shape (workspace and outputs)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        cap_start = int(n_clusters // 3 + 1) if cap_start is None else int(cap_start)
+        cap_tracks = cap_start if cap_tracks is None else int(cap_tracks)
+        cap_hits = int(max(1024, 2 * n_clusters)) if cap_hits is None else int(cap_hits)
+        nb = self.workspace_bytes(n_units, n_clusters, cap_start)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        i32, i64, f32 = torch.int32, torch.int64, torch.float32
+        out = dict(
+            counts=torch.zeros(4, dtype=i64, device=dev),
+            unit=torch.empty(cap_tracks, dtype=i32, device=dev),
+            start=torch.empty(cap_tracks, dtype=i32, device=dev),
+            n_hits=torch.empty(cap_tracks, dtype=i32, device=dev),
+            hit_begin=torch.empty(cap_tracks, dtype=i64, device=dev),
+            hit_id=torch.empty(cap_hits, dtype=i32, device=dev),
+            hit_row=torch.empty(cap_hits, dtype=torch.uint8, device=dev),
+            x_ref=torch.empty(cap_tracks, dtype=f32, device=dev),
+            param=torch.empty((cap_tracks, 5), dtype=f32, device=dev),
+            cov=torch.empty((cap_tracks, 15), dtype=f32, device=dev),
+            chi2=torch.empty(cap_tracks, dtype=f32, device=dev),
+            ndf=torch.empty(cap_tracks, dtype=i32, device=dev),
+        )
+        return dict(ws=ws, ws_off=off, ws_bytes=nb, cap_start=cap_start, cap_tracks=cap_tracks,
+                    cap_hits=cap_hits, out=out)
+
+    def track_into(self, row_begin, y, z, n_units, bufs, debug=None, stream=None):
+        """Enqueue one tpcx_track call into preallocated buffers (no sync)."""
+        import torch
+        n = int(y.numel())
+        for t, dt in ((row_begin, torch.int64), (y, torch.float32), (z, torch.float32)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise TpcxError("inputs must be contiguous device tensors: row_begin int64, y/z float32")
+        if row_begin.numel() != n_units * self.n_rows + 1 or z.numel() != n:
+            raise TpcxError("row_begin must have n_units*n_rows+1 entries and y, z the same length")
+        cl = Clusters(n_units, n, _ptr(row_begin), _ptr(y), _ptr(z))
+        o = bufs["out"]
+        tr = Tracks(bufs["cap_tracks"], bufs["cap_hits"], _ptr(o["counts"]), _ptr(o["unit"]),
+                    _ptr(o["start"]), _ptr(o["n_hits"]), _ptr(o["hit_begin"]), _ptr(o["hit_id"]),
+                    _ptr(o["hit_row"]), _ptr(o["x_ref"]), _ptr(o["param"]), _ptr(o["cov"]),
+                    _ptr(o["chi2"]), _ptr(o["ndf"]))
+        dbg = None
+        if debug is not None:
+            dbg = Debug(*[_ptr(debug.get(k)) for k in ("link_up", "link_down", "clean_up",
+                                                        "clean_down", "starts")])
+        s = stream if stream is not None else torch.cuda.current_stream()
+        ws = bufs["ws"]
+        st = lib().tpcx_track(self._h, ctypes.byref(cl), ctypes.c_void_p(ws.data_ptr() + bufs["ws_off"]),
+                              bufs["ws_bytes"], bufs["cap_start"], ctypes.byref(tr),
+                              ctypes.byref(dbg) if dbg is not None else None,
+                              ctypes.c_void_p(s.cuda_stream))
+        _check(st, "tpcx_track")
+        self._last = (tr, s)
+        return tr
+
+    def track(self, row_begin, y, z, n_units, debug=False, cap_start=None, cap_tracks=None,
+              cap_hits=None):
+        """Track and return host-sized device tensors.  Retries once with the
+        required sizes when a capacity was too small."""
+        import torch
+        n = int(y.numel())
+        for _attempt in range(2):
+            bufs = self.allocate(n_units, n, cap_start, cap_tracks, cap_hits)
+            dev = bufs["out"]["counts"].device
+            dbg = None
+            if debug:
+                dbg = {k: torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+                       for k in ("link_up", "link_down", "clean_up", "clean_down")}
+                dbg["starts"] = torch.empty(max(bufs["cap_start"], 1), dtype=torch.int32, device=dev)
+            self.track_into(row_begin, y, z, n_units, bufs, dbg)
+            counts = bufs["out"]["counts"].cpu().tolist()
+            n_start, n_tr, n_hits, status = counts
+            if status == 0:
+                break
+            cap_start = max(bufs["cap_start"], n_start)
+            cap_tracks = max(bufs["cap_tracks"], n_tr)
+            cap_hits = max(bufs["cap_hits"], n_hits)
+        else:
+            raise TpcxError(f"capacity still exceeded after resizing: counts={counts}")
+        o = bufs["out"]
+        res = {k: v[:n_tr] for k, v in o.items() if k not in ("counts", "hit_id", "hit_row")}
+        res["hit_id"] = o["hit_id"][:n_hits]
+        res["hit_row"] = o["hit_row"][:n_hits]
+        res["n_start"] = n_start
+        res["status"] = status
+        if debug:
+            for k in ("link_up", "link_down", "clean_up", "clean_down"):
+                res[k] = dbg[k][:n]
+            res["starts"] = dbg["starts"][:min(n_start, bufs["cap_start"])]
+        return res

@@ -1,0 +1,382 @@
+// tpcx: host side of the C interface declared in include/tpcx.h, and the
+// single translation unit that holds every kernel.
+#include "../../include/tpcx.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "grid.h"
+#include "links.h"
+#include "tpcx_common.h"
+#include "tracklet.h"
+
+using namespace tpcx;
+
+struct tpcx_ctx {
+  int device = 0;
+  int n_rows = 0;
+  std::vector<float> row_x;       // host copy
+  std::vector<float> frac;        // neighbour-finder interpolation fractions
+  float tan_half = 0.0f;
+  DevParams dp{};
+  tpcx_params params{};
+  tpcx_tuning tuning{};
+  bool tuning_fixed = false;
+  std::vector<RowInfo> rows_host;
+  int32_t sum_ny = 0;
+  // device tables (immutable between set-ups)
+  float* d_row_x = nullptr;
+  float* d_frac = nullptr;
+  RowInfo* d_rows = nullptr;
+  int n_cu = 256;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Sub-allocator over the caller's workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t n) {
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += align_up(size_t(std::max<int64_t>(n, 1)) * sizeof(T));
+    return p;
+  }
+};
+
+struct Layout {
+  UnitZ* unit_z;
+  int32_t* bins;
+  int32_t* key;
+  int32_t* slot;
+  float* sy;
+  float* sz;
+  int32_t* sid;
+  int32_t* up;
+  int32_t* down;
+  int32_t* cup;
+  int32_t* cdown;
+  uint8_t* flag;
+  int32_t* blk_cnt;
+  int32_t* blk_off;
+  int32_t* starts;
+  int32_t* queue;
+  int64_t* part;
+  TrackletTmp tmp;
+  size_t bytes;
+};
+
+constexpr int kKeepBlocks = 512;
+
+int blocks_for(int64_t n, int b) { return int((n + b - 1) / b); }
+
+int64_t bins_per_unit(const tpcx_ctx* c, int nz) { return int64_t(nz) * c->sum_ny + c->n_rows; }
+
+Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t cap_start, int nz,
+             int block) {
+  Carver cv{static_cast<char*>(ws)};
+  Layout L{};
+  const int64_t nb = blocks_for(n, block);
+  L.unit_z = cv.take<UnitZ>(n_units);
+  L.bins = cv.take<int32_t>(int64_t(n_units) * bins_per_unit(c, nz));
+  L.key = cv.take<int32_t>(n);
+  L.slot = cv.take<int32_t>(n);
+  L.sy = cv.take<float>(n);
+  L.sz = cv.take<float>(n);
+  L.sid = cv.take<int32_t>(n);
+  L.up = cv.take<int32_t>(n);
+  L.down = cv.take<int32_t>(n);
+  L.cup = cv.take<int32_t>(n);
+  L.cdown = cv.take<int32_t>(n);
+  L.flag = cv.take<uint8_t>(n);
+  L.blk_cnt = cv.take<int32_t>(nb);
+  L.blk_off = cv.take<int32_t>(nb);
+  L.starts = cv.take<int32_t>(cap_start);
+  L.queue = cv.take<int32_t>(1);
+  L.part = cv.take<int64_t>(2 * kKeepBlocks);
+  L.tmp.cap = std::max<int64_t>(cap_start, 1);
+  L.tmp.n = cv.take<int32_t>(cap_start);
+  L.tmp.n_up = cv.take<int32_t>(cap_start);
+  L.tmp.flags = cv.take<int32_t>(cap_start);
+  L.tmp.unit = cv.take<int32_t>(cap_start);
+  L.tmp.f = cv.take<float>(16 * L.tmp.cap);
+  L.tmp.hit = cv.take<int32_t>(L.tmp.cap * c->n_rows);
+  L.tmp.hrow = cv.take<uint8_t>(L.tmp.cap * c->n_rows);
+  L.bytes = cv.off;
+  return L;
+}
+
+tpcx_tuning effective_tuning(const tpcx_ctx* c, int32_t n_units, int64_t n) {
+  if (c->tuning_fixed) return c->tuning;
+  tpcx_tuning t;
+  tpcx_default_tuning(n_units, n, &t);
+  t.bin_y = c->tuning.bin_y;  // the row table is built for this width
+  return t;
+}
+
+bool valid_tuning(const tpcx_tuning& t) {
+  return t.bin_y > 0.0f && std::isfinite(t.bin_y) && t.n_zbins >= 1 && t.n_zbins <= 65536 &&
+         t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 && t.construct_block >= 64 &&
+         t.construct_block <= 1024 && t.construct_block % 64 == 0 && t.construct_grid >= 1;
+}
+
+tpcx_status build_rows(tpcx_ctx* c) {
+  c->rows_host.resize(c->n_rows);
+  int32_t cum = 0;
+  for (int r = 0; r < c->n_rows; ++r) {
+    const double half = double(c->row_x[r]) * double(c->tan_half);
+    int ny = int(std::ceil(2.0 * half / double(c->tuning.bin_y)));
+    ny = std::max(1, std::min(ny, 4096));
+    RowInfo ri;
+    ri.ny = ny;
+    ri.cum_ny = cum;
+    ri.y0 = float(-half);
+    ri.inv_by = float(double(ny) / (2.0 * half));
+    c->rows_host[r] = ri;
+    cum += ny;
+  }
+  c->sum_ny = cum;
+  if (hipMemcpy(c->d_rows, c->rows_host.data(), sizeof(RowInfo) * c->n_rows, hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return TPCX_E_HIP;
+  return TPCX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t) {
+  if (!t) return;
+  t->bin_y = 2.0f;
+  // about one cluster per bin for rows ~30 y-bins wide
+  const double per_row = double(n_clusters) / std::max(1.0, double(n_units) * 152.0);
+  int nz = int(per_row / 30.0);
+  t->n_zbins = std::max(4, std::min(nz, 4096));
+  t->block = 256;
+  t->construct_block = 256;
+  t->construct_grid = 2048;
+}
+
+tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx_tuning* tuning,
+                        tpcx_ctx** out) {
+  if (!g || !p || !out || !g->row_x_host || g->n_rows < 3 || g->n_rows > 255) return TPCX_E_ARG;
+  for (int r = 0; r < g->n_rows; ++r) {
+    if (!std::isfinite(g->row_x_host[r]) || (r > 0 && !(g->row_x_host[r] > g->row_x_host[r - 1])))
+      return TPCX_E_ARG;
+  }
+  if (!(g->tan_half_opening > 0.0f) || !std::isfinite(g->bz_tesla)) return TPCX_E_ARG;
+  if (!(p->win_y >= 0.0f) || !(p->win_z >= 0.0f) || !(p->d2_max >= 0.0f) || !(p->chi2_max > 0.0f) ||
+      !(p->sinphi_max > 0.0f && p->sinphi_max < 1.0f) || !(p->u_max > 0.0f && p->u_max < 1.0f) ||
+      !(p->sigma_y > 0.0f) || !(p->sigma_z > 0.0f) || !(p->cww0 > 0.0f) || p->min_hits < 2 ||
+      p->max_misses < 1)
+    return TPCX_E_ARG;
+  if (tuning && !valid_tuning(*tuning)) return TPCX_E_ARG;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return TPCX_E_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return TPCX_E_HIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TPCX_E_DEVICE;
+
+  auto* c = new (std::nothrow) tpcx_ctx;
+  if (!c) return TPCX_E_HIP;
+  c->device = dev;
+  c->n_cu = prop.multiProcessorCount;
+  c->n_rows = g->n_rows;
+  c->row_x.assign(g->row_x_host, g->row_x_host + g->n_rows);
+  c->tan_half = g->tan_half_opening;
+  c->params = *p;
+  // constants in the kernels' precision; kappa rounded once from double
+  c->dp.kappa = float(2.99792458e-3 * double(g->bz_tesla));
+  c->dp.sy2 = p->sigma_y * p->sigma_y;
+  c->dp.sz2 = p->sigma_z * p->sigma_z;
+  c->dp.wy = p->win_y;
+  c->dp.wz = p->win_z;
+  c->dp.d2max = p->d2_max;
+  c->dp.chi2max = p->chi2_max;
+  c->dp.smax = p->sinphi_max;
+  c->dp.umax = p->u_max;
+  c->dp.cww0 = p->cww0;
+  c->dp.min_hits = p->min_hits;
+  c->dp.max_misses = p->max_misses;
+  c->frac.assign(g->n_rows, 0.0f);
+  for (int r = 1; r + 1 < g->n_rows; ++r) {
+    const float a = c->row_x[r] - c->row_x[r - 1];
+    const float b = c->row_x[r + 1] - c->row_x[r - 1];
+    c->frac[r] = a / b;
+  }
+  if (tuning) {
+    c->tuning = *tuning;
+    c->tuning_fixed = true;
+  } else {
+    tpcx_default_tuning(36, 1, &c->tuning);
+  }
+  bool ok = hipMalloc(&c->d_row_x, sizeof(float) * c->n_rows) == hipSuccess &&
+            hipMalloc(&c->d_frac, sizeof(float) * c->n_rows) == hipSuccess &&
+            hipMalloc(&c->d_rows, sizeof(RowInfo) * c->n_rows) == hipSuccess &&
+            hipMemcpy(c->d_row_x, c->row_x.data(), sizeof(float) * c->n_rows,
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(c->d_frac, c->frac.data(), sizeof(float) * c->n_rows,
+                      hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok || build_rows(c) != TPCX_OK) {
+    tpcx_destroy(c);
+    return TPCX_E_HIP;
+  }
+  *out = c;
+  return TPCX_OK;
+}
+
+void tpcx_destroy(tpcx_ctx* c) {
+  if (!c) return;
+  if (c->d_row_x) (void)hipFree(c->d_row_x);
+  if (c->d_frac) (void)hipFree(c->d_frac);
+  if (c->d_rows) (void)hipFree(c->d_rows);
+  delete c;
+}
+
+size_t tpcx_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_clusters,
+                            int64_t cap_start) {
+  if (!c || n_units < 1 || n_clusters < 0 || cap_start < 0) return 0;
+  const tpcx_tuning t = effective_tuning(c, n_units, n_clusters);
+  return carve(c, nullptr, n_units, n_clusters, cap_start, t.n_zbins, t.block).bytes;
+}
+
+tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                       int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
+                       hipStream_t stream) {
+  if (!c || !in || !out || !out->counts || in->n_units < 1 || in->n_clusters < 0 ||
+      in->n_clusters >= (int64_t(1) << 31) || cap_start < 0 || cap_start >= (int64_t(1) << 31) ||
+      out->cap_tracks < 0 || out->cap_hits < 0)
+    return TPCX_E_ARG;
+  if (in->n_clusters > 0 && (!in->row_begin || !in->y || !in->z)) return TPCX_E_ARG;
+  if (!in->row_begin) return TPCX_E_ARG;
+  if ((out->cap_tracks > 0 && (!out->unit || !out->start || !out->n_hits || !out->hit_begin ||
+                               !out->x_ref || !out->param || !out->cov || !out->chi2 || !out->ndf)) ||
+      (out->cap_hits > 0 && (!out->hit_id || !out->hit_row)))
+    return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
+
+  const int32_t U = in->n_units;
+  const int64_t N = in->n_clusters;
+  const int R = c->n_rows;
+  const tpcx_tuning t = effective_tuning(c, U, N);
+  const Layout L = carve(c, ws, U, N, cap_start, t.n_zbins, t.block);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
+  const int B = t.block;
+  const int64_t nb = blocks_for(N, B);
+  const int64_t nbins = int64_t(U) * bins_per_unit(c, t.n_zbins);
+
+  Grid g;
+  g.rows = c->d_rows;
+  g.unit_z = L.unit_z;
+  g.bin_start = L.bins;
+  g.sy = L.sy;
+  g.sz = L.sz;
+  g.sid = L.sid;
+  g.n_rows = R;
+  g.nz = t.n_zbins;
+  g.btot = bins_per_unit(c, t.n_zbins);
+
+  const int fill_grid = 1024;
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, out->counts, int64_t(4), int64_t(0));
+  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid), dim3(256), 0, stream, L.bins, nbins, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(1), 0);
+  const int UR = U * R;
+  hipLaunchKernelGGL(k_unit_zrange, dim3(U), dim3(256), 0, stream, in->row_begin, in->z, R,
+                     t.n_zbins, L.unit_z);
+  hipLaunchKernelGGL(k_grid_count, dim3(UR), dim3(B), 0, stream, in->row_begin, in->y, in->z, g,
+                     L.bins, L.key, L.slot);
+  hipLaunchKernelGGL(k_grid_scan, dim3(UR), dim3(B), 0, stream, in->row_begin, g, L.bins);
+  hipLaunchKernelGGL(k_grid_scatter, dim3(UR), dim3(B), 0, stream, in->row_begin, in->y, in->z,
+                     L.key, L.slot, g, L.sy, L.sz, L.sid);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_neighbours, dim3(nb), dim3(B), 0, stream, in->row_begin, U, g, c->d_frac,
+                       c->dp, L.up, L.down);
+    hipLaunchKernelGGL(k_clean_flags, dim3(nb), dim3(B), 0, stream, N, L.up, L.down, L.cup,
+                       L.cdown, L.flag, L.blk_cnt);
+  }
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, L.blk_cnt, N > 0 ? nb : 0,
+                     L.blk_off, out->counts, cap_start, out->counts + 3,
+                     int64_t(TPCX_ST_START_OVERFLOW));
+  if (N > 0)
+    hipLaunchKernelGGL(k_write_starts, dim3(nb), dim3(B), 0, stream, N, L.flag, L.blk_off,
+                       cap_start, L.starts);
+
+  TrackInputs ti;
+  ti.row_begin = in->row_begin;
+  ti.n_units = U;
+  ti.y = in->y;
+  ti.z = in->z;
+  ti.clean_up = L.cup;
+  ti.starts = L.starts;
+  ti.row_x = c->d_row_x;
+  hipLaunchKernelGGL(k_construct, dim3(t.construct_grid), dim3(t.construct_block), 0, stream,
+                     out->counts, cap_start, L.queue, ti, g, c->dp, L.tmp);
+
+  TrackOut o;
+  o.cap_tracks = out->cap_tracks;
+  o.cap_hits = out->cap_hits;
+  o.unit = out->unit;
+  o.start = out->start;
+  o.n_hits = out->n_hits;
+  o.hit_begin = out->hit_begin;
+  o.hit_id = out->hit_id;
+  o.hit_row = out->hit_row;
+  o.x_ref = out->x_ref;
+  o.param = out->param;
+  o.cov = out->cov;
+  o.chi2 = out->chi2;
+  o.ndf = out->ndf;
+  hipLaunchKernelGGL(k_keep_count, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
+                     L.tmp.n, c->dp.min_hits, L.part);
+  hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(64), 0, stream, L.part, kKeepBlocks, out->counts,
+                     out->cap_tracks, out->cap_hits);
+  hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
+                     L.starts, L.tmp, R, c->dp.min_hits, L.part, o);
+
+  if (dbg) {
+    const size_t nbytes = size_t(N) * sizeof(int32_t);
+    if (dbg->link_up && N) (void)hipMemcpyAsync(dbg->link_up, L.up, nbytes, hipMemcpyDeviceToDevice, stream);
+    if (dbg->link_down && N) (void)hipMemcpyAsync(dbg->link_down, L.down, nbytes, hipMemcpyDeviceToDevice, stream);
+    if (dbg->clean_up && N) (void)hipMemcpyAsync(dbg->clean_up, L.cup, nbytes, hipMemcpyDeviceToDevice, stream);
+    if (dbg->clean_down && N) (void)hipMemcpyAsync(dbg->clean_down, L.cdown, nbytes, hipMemcpyDeviceToDevice, stream);
+    if (dbg->starts && cap_start)
+      (void)hipMemcpyAsync(dbg->starts, L.starts, size_t(cap_start) * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, stream);
+  }
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
+tpcx_status tpcx_poll(tpcx_ctx* c, const tpcx_tracks* out, hipStream_t stream) {
+  if (!c || !out || !out->counts) return TPCX_E_ARG;
+  if (hipStreamSynchronize(stream) != hipSuccess) return TPCX_E_HIP;
+  int64_t st = 0;
+  if (hipMemcpy(&st, out->counts + 3, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return TPCX_E_HIP;
+  return st ? TPCX_E_CAPACITY : TPCX_OK;
+}
+
+const char* tpcx_strerror(tpcx_status s) {
+  switch (s) {
+    case TPCX_OK: return "ok";
+    case TPCX_E_ARG: return "invalid argument";
+    case TPCX_E_CAPACITY: return "a device capacity was exceeded; counts hold the required sizes";
+    case TPCX_E_HIP: return "HIP runtime error";
+    case TPCX_E_DEVICE: return "device is not gfx950";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

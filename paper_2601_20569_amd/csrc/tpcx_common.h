@@ -1,0 +1,116 @@
+// Shared device-side definitions of the tpcx kernels (one translation unit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpcx {
+
+constexpr int kWave = 64;
+
+// Method constants in the precision the kernels compute in.
+struct DevParams {
+  float kappa;   // d sin(phi) / dx per unit of q/pT
+  float sy2, sz2;
+  float wy, wz, d2max, chi2max, smax, umax, cww0;
+  int32_t min_hits, max_misses;
+};
+
+// Search-grid description of one pad row (identical for every unit).
+struct RowInfo {
+  int32_t ny;      // bins along y
+  int32_t cum_ny;  // sum of ny over the rows below
+  float y0;        // lower y edge of bin 0
+  float inv_by;    // bins per cm along y
+};
+
+// Per-unit z range of the search grid.
+struct UnitZ {
+  float zmin;
+  float inv_bz;  // bins per cm along z
+};
+
+// Read-only view of the sorted, binned clusters.
+struct Grid {
+  const RowInfo* rows;
+  const UnitZ* unit_z;
+  const int32_t* bin_start;  // [n_units * btot]; absolute sorted positions
+  const float* sy;
+  const float* sz;
+  const int32_t* sid;  // sorted position -> caller index
+  int32_t n_rows, nz;
+  int64_t btot;  // bins (+1 sentinel per row) of one unit
+
+  __device__ __forceinline__ int64_t row_base(int u, int r) const {
+    return int64_t(u) * btot + int64_t(nz) * rows[r].cum_ny + r;
+  }
+  __device__ __forceinline__ int zbin(int u, float z) const {
+    UnitZ g = unit_z[u];
+    float v = (z - g.zmin) * g.inv_bz;
+    v = fminf(fmaxf(v, 0.0f), float(nz - 1));
+    return int(v);
+  }
+  __device__ __forceinline__ int ybin(int r, float y) const {
+    RowInfo ri = rows[r];
+    float v = (y - ri.y0) * ri.inv_by;
+    v = fminf(fmaxf(v, 0.0f), float(ri.ny - 1));
+    return int(v);
+  }
+};
+
+// Widening of a search box so that it covers every cluster an exact float
+// predicate can accept (absolute plus relative slack on the coordinate).
+__device__ __forceinline__ float box_pad(float v) { return 1e-3f + 1e-6f * fabsf(v); }
+
+// Largest k in [0, n) with a[k] <= v (a non-decreasing, a[0] <= v).
+__device__ __forceinline__ int upper_row(const int64_t* a, int n, int64_t v) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= v)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Exclusive block-wide prefix sum of one int64 per thread; returns this
+// thread's prefix and writes the block total to *total.  `lds` holds one
+// entry per wave.  All threads of the block must call it.
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* lds, int64_t* total) {
+  const int lane = lane_id();
+  const int wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  int64_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int64_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) lds[wid] = x;
+  __syncthreads();
+  if (wid == 0) {
+    int64_t w = lane < nw ? lds[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      int64_t y = __shfl_up(w, d, kWave);
+      if (lane >= d) w += y;
+    }
+    if (lane < nw) lds[lane] = w;
+  }
+  __syncthreads();
+  int64_t wave_off = wid > 0 ? lds[wid - 1] : 0;
+  *total = lds[nw - 1];
+  __syncthreads();
+  return wave_off + x - v;
+}
+
+}  // namespace tpcx
