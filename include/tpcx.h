@@ -158,6 +158,24 @@ tpcx_status tpcx_poll(tpcx_ctx* ctx, const tpcx_tracks* out, hipStream_t stream)
 
 const char* tpcx_strerror(tpcx_status s);
 
+/* Stage timing (profiling aid).  Stages of one tpcx_track call, in order. */
+#define TPCX_STAGE_GRID 0       /* search-grid build */
+#define TPCX_STAGE_NEIGHBOURS 1 /* neighbour finder */
+#define TPCX_STAGE_STARTS 2     /* cleaning, start flags, ordered compaction */
+#define TPCX_STAGE_CONSTRUCT 3  /* tracklet constructor */
+#define TPCX_STAGE_COMPACT 4    /* ordered compaction of the kept tracklets */
+#define TPCX_N_STAGES 5
+
+/* Record HIP events on the call's stream around every stage of the next
+ * max_calls tpcx_track calls (max_calls = 0 switches timing off).  Creates the
+ * events; call it outside timed or captured regions. */
+tpcx_status tpcx_timing_enable(tpcx_ctx* ctx, int32_t max_calls);
+
+/* Waits for the recorded events and writes, per stage, the summed elapsed
+ * milliseconds over the recorded calls to ms_host[TPCX_N_STAGES] and their
+ * number to *n_calls; then starts a new recording. */
+tpcx_status tpcx_timing_read(tpcx_ctx* ctx, float* ms_host, int32_t* n_calls);
+
 #ifdef __cplusplus
 }
 #endif

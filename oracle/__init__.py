@@ -138,7 +138,8 @@ def track(cs, params: Params | None = None, precision=32, brute=False, units=Non
     out["kept"] = out["t_n"] >= params.min_hits
     c = out.pop("counters")
     out["counters"] = dict(nf_pairs=int(c[0]), propagations=int(c[1]), searches=int(c[2]),
-                           window_candidates=int(c[3]), attached=int(c[4]))
+                           window_candidates=int(c[3]), attached=int(c[4]), chain=int(c[5]),
+                           box_candidates=int(c[6]))
     return out
 
 

@@ -305,7 +305,7 @@ struct Tracklet {
   std::vector<int32_t> hits;  // sorted by row
   std::vector<uint8_t> rows;
   // work counters
-  int64_t n_prop = 0, n_search = 0, n_box = 0;
+  int64_t n_prop = 0, n_search = 0, n_box = 0, n_chain = 0, n_cand = 0;
 };
 
 template <class T>
@@ -314,14 +314,20 @@ struct Searcher {
   bool brute;
   const Consts<T>& c;
   // Best cluster of row r by (chi2, index) among those with chi2 <= chi2max.
-  int64_t best(const State<T>& st, int r, T* chi2_out, int64_t* n_box) const {
+  // n_box counts the clusters scanned; n_cand those inside the chi2 box
+  // |dy| <= sqrt(chi2max Sy), |dz| <= sqrt(chi2max Sz), which any
+  // implementation must examine (a work measure, not part of the result).
+  int64_t best(const State<T>& st, int r, T* chi2_out, int64_t* n_box, int64_t* n_cand) const {
     double sz = std::sqrt(double(c.chi2max) * double(st.czz + c.sz2));
+    double sy = std::sqrt(double(c.chi2max) * double(st.cyy + c.sy2));
     double hw = sz * (1.0 + kPadRel) + kPadAbs;
     double lo = double(st.z) - hw, hi = double(st.z) + hw;
     int64_t bi = -1;
     T bc = T(0);
     un.scan(r, brute, lo, hi, [&](int64_t i) {
       ++*n_box;
+      if (std::fabs(double(un.y[i]) - double(st.y)) <= sy && std::fabs(double(un.z[i]) - double(st.z)) <= sz)
+        ++*n_cand;
       T ch = chi2_of(st, T(un.y[i]), T(un.z[i]), c);
       if (!(ch <= c.chi2max)) return;
       if (bi < 0 || ch < bc || (ch == bc && i < bi)) {
@@ -348,6 +354,7 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
 
   std::vector<int64_t> chain{h0};
   while (cup[chain.back()] >= 0) chain.push_back(cup[chain.back()]);
+  tk.n_chain = int64_t(chain.size());
 
   // 2-point seed at the second chain cluster
   int64_t c0 = chain[0], c1 = chain[1];
@@ -402,7 +409,7 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
       if (!propagate(st, xr[rr], c)) break;
       ++tk.n_search;
       T ch;
-      int64_t hi = se.best(st, rr, &ch, &tk.n_box);
+      int64_t hi = se.best(st, rr, &ch, &tk.n_box, &tk.n_cand);
       if (hi >= 0) {
         chi2 = chi2 + update(st, T(un.y[hi]), T(un.z[hi]), c);
         ++n;
@@ -439,7 +446,7 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
       if (!propagate(st, xr[rr], c)) break;
       ++tk.n_search;
       T ch;
-      int64_t hi = se.best(st, rr, &ch, &tk.n_box);
+      int64_t hi = se.best(st, rr, &ch, &tk.n_box, &tk.n_cand);
       if (hi >= 0) {
         chi2 = chi2 + update(st, T(un.y[hi]), T(un.z[hi]), c);
         ++n;
@@ -555,7 +562,7 @@ struct Result {
   std::vector<int32_t> t_unit, t_r0, t_n, t_flags, t_row_ref, t_ndf, t_hits;
   std::vector<uint8_t> t_rows;
   std::vector<double> t_param, t_cov, t_chi2, t_xref;
-  std::vector<int64_t> counters;  // n_pairs, n_prop, n_search, n_box, n_attached
+  std::vector<int64_t> counters;  // n_pairs, n_prop, n_search, n_box, n_attached, n_chain, n_cand
 };
 
 template <class T>
@@ -605,7 +612,7 @@ Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
       tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses));
     }
   }
-  int64_t np = 0, nprop = 0, nsearch = 0, nbox = 0, natt = 0;
+  int64_t np = 0, nprop = 0, nsearch = 0, nbox = 0, natt = 0, nchain = 0, ncand = 0;
   for (int k = 0; k < nu; ++k) {
     np += pairs[k];
     for (int64_t h : starts[k]) res->starts.push_back(h);
@@ -634,10 +641,12 @@ Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
       nsearch += tk.n_search;
       nbox += tk.n_box;
       natt += tk.n;
+      nchain += tk.n_chain;
+      ncand += tk.n_cand;
     }
   }
   res->t_hit_begin.push_back(int64_t(res->t_hits.size()));
-  res->counters = {np, nprop, nsearch, nbox, natt};
+  res->counters = {np, nprop, nsearch, nbox, natt, nchain, ncand};
   return res;
 }
 

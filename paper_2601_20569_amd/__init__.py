@@ -63,8 +63,7 @@ class Debug(ctypes.Structure):
                 ("starts", ctypes.c_void_p)]
 
 
-EXPORTS = ("tpcx_default_tuning", "tpcx_create", "tpcx_destroy", "tpcx_workspace_bytes",
-           "tpcx_track", "tpcx_poll", "tpcx_strerror")
+STAGES = ("grid", "neighbours", "starts", "construct", "compact")
 
 _lib = None
 
@@ -93,6 +92,10 @@ def lib():
         L.tpcx_poll.restype = ctypes.c_int32
         L.tpcx_strerror.argtypes = [ctypes.c_int32]
         L.tpcx_strerror.restype = ctypes.c_char_p
+        L.tpcx_timing_enable.argtypes = [P, ctypes.c_int32]
+        L.tpcx_timing_enable.restype = ctypes.c_int32
+        L.tpcx_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
+        L.tpcx_timing_read.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -172,6 +175,17 @@ class SectorTracker:
         except Exception:
             pass
 
+    def timing_enable(self, max_calls):
+        """Record per-stage HIP events for the next max_calls track calls."""
+        _check(lib().tpcx_timing_enable(self._h, int(max_calls)), "tpcx_timing_enable")
+
+    def timing_read(self):
+        """(summed ms per stage as a dict, number of recorded calls)."""
+        ms = (ctypes.c_float * len(STAGES))()
+        n = ctypes.c_int32()
+        _check(lib().tpcx_timing_read(self._h, ms, ctypes.byref(n)), "tpcx_timing_read")
+        return dict(zip(STAGES, list(ms))), int(n.value)
+
     def workspace_bytes(self, n_units, n_clusters, cap_start):
         return int(lib().tpcx_workspace_bytes(self._h, n_units, n_clusters, cap_start))
 
@@ -234,11 +248,12 @@ class SectorTracker:
 
     def track(self, row_begin, y, z, n_units, debug=False, cap_start=None, cap_tracks=None,
               cap_hits=None):
-        """Track and return host-sized device tensors.  Retries once with the
-        required sizes when a capacity was too small."""
+        """Track and return device tensors cut to the produced sizes.  When a
+        capacity was too small the call is repeated with the required sizes
+        (a larger start capacity can reveal more tracklets, hence 3 tries)."""
         import torch
         n = int(y.numel())
-        for _attempt in range(2):
+        for _attempt in range(3):
             bufs = self.allocate(n_units, n, cap_start, cap_tracks, cap_hits)
             dev = bufs["out"]["counts"].device
             dbg = None

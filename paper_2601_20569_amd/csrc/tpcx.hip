@@ -34,6 +34,9 @@ struct tpcx_ctx {
   float* d_frac = nullptr;
   RowInfo* d_rows = nullptr;
   int n_cu = 256;
+  // stage timing: (TPCX_N_STAGES + 1) events per recorded call
+  std::vector<hipEvent_t> events;
+  int32_t timing_max = 0, timing_used = 0;
 };
 
 namespace {
@@ -239,6 +242,7 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
 
 void tpcx_destroy(tpcx_ctx* c) {
   if (!c) return;
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->d_row_x) (void)hipFree(c->d_row_x);
   if (c->d_frac) (void)hipFree(c->d_frac);
   if (c->d_rows) (void)hipFree(c->d_rows);
@@ -290,6 +294,15 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   g.nz = t.n_zbins;
   g.btot = bins_per_unit(c, t.n_zbins);
 
+  hipEvent_t* ev = nullptr;
+  if (c->timing_used < c->timing_max) {
+    ev = &c->events[size_t(c->timing_used) * (TPCX_N_STAGES + 1)];
+    ++c->timing_used;
+  }
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], stream);
+  };
+  mark(0);
   const int fill_grid = 1024;
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, out->counts, int64_t(4), int64_t(0));
   hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid), dim3(256), 0, stream, L.bins, nbins, 0);
@@ -302,9 +315,13 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   hipLaunchKernelGGL(k_grid_scan, dim3(UR), dim3(B), 0, stream, in->row_begin, g, L.bins);
   hipLaunchKernelGGL(k_grid_scatter, dim3(UR), dim3(B), 0, stream, in->row_begin, in->y, in->z,
                      L.key, L.slot, g, L.sy, L.sz, L.sid);
+  mark(1);
   if (N > 0) {
     hipLaunchKernelGGL(k_neighbours, dim3(nb), dim3(B), 0, stream, in->row_begin, U, g, c->d_frac,
                        c->dp, L.up, L.down);
+  }
+  mark(2);
+  if (N > 0) {
     hipLaunchKernelGGL(k_clean_flags, dim3(nb), dim3(B), 0, stream, N, L.up, L.down, L.cup,
                        L.cdown, L.flag, L.blk_cnt);
   }
@@ -323,6 +340,7 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   ti.clean_up = L.cup;
   ti.starts = L.starts;
   ti.row_x = c->d_row_x;
+  mark(3);
   hipLaunchKernelGGL(k_construct, dim3(t.construct_grid), dim3(t.construct_block), 0, stream,
                      out->counts, cap_start, L.queue, ti, g, c->dp, L.tmp);
 
@@ -340,12 +358,14 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   o.cov = out->cov;
   o.chi2 = out->chi2;
   o.ndf = out->ndf;
+  mark(4);
   hipLaunchKernelGGL(k_keep_count, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
                      L.tmp.n, c->dp.min_hits, L.part);
   hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(64), 0, stream, L.part, kKeepBlocks, out->counts,
                      out->cap_tracks, out->cap_hits);
   hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
                      L.starts, L.tmp, R, c->dp.min_hits, L.part, o);
+  mark(5);
 
   if (dbg) {
     const size_t nbytes = size_t(N) * sizeof(int32_t);
@@ -366,6 +386,41 @@ tpcx_status tpcx_poll(tpcx_ctx* c, const tpcx_tracks* out, hipStream_t stream) {
   int64_t st = 0;
   if (hipMemcpy(&st, out->counts + 3, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return TPCX_E_HIP;
   return st ? TPCX_E_CAPACITY : TPCX_OK;
+}
+
+tpcx_status tpcx_timing_enable(tpcx_ctx* c, int32_t max_calls) {
+  if (!c || max_calls < 0) return TPCX_E_ARG;
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  c->events.clear();
+  c->timing_max = 0;
+  c->timing_used = 0;
+  const size_t n = size_t(max_calls) * (TPCX_N_STAGES + 1);
+  c->events.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (hipEventCreate(&c->events[i]) != hipSuccess) {
+      c->events.resize(i);
+      return TPCX_E_HIP;
+    }
+  }
+  c->timing_max = max_calls;
+  return TPCX_OK;
+}
+
+tpcx_status tpcx_timing_read(tpcx_ctx* c, float* ms_host, int32_t* n_calls) {
+  if (!c || !ms_host || !n_calls) return TPCX_E_ARG;
+  for (int s = 0; s < TPCX_N_STAGES; ++s) ms_host[s] = 0.0f;
+  for (int32_t i = 0; i < c->timing_used; ++i) {
+    hipEvent_t* ev = &c->events[size_t(i) * (TPCX_N_STAGES + 1)];
+    if (hipEventSynchronize(ev[TPCX_N_STAGES]) != hipSuccess) return TPCX_E_HIP;
+    for (int s = 0; s < TPCX_N_STAGES; ++s) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[s], ev[s + 1]) != hipSuccess) return TPCX_E_HIP;
+      ms_host[s] += ms;
+    }
+  }
+  *n_calls = c->timing_used;
+  c->timing_used = 0;
+  return TPCX_OK;
 }
 
 const char* tpcx_strerror(tpcx_status s) {

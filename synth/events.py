@@ -101,13 +101,14 @@ def _psi_exit(cx, cy, R, q, theta0, r_out):
 
 
 def helix_crossings(tr: Tracks, distortion: RadialDistortion | None = None,
-                    device="cpu", chunk=2048):
+                    device="cpu", chunk=2048, as_numpy=True):
     """All crossings of the helices with the pad-row planes of every sector.
 
     A helix is followed for at most one full turn in the transverse plane
     (outgoing and returning leg), until it reaches the outer radius, and while
-    |z| <= z_max.  Returns a dict of numpy arrays over crossings:
-    track, sector, row, y (local), z, psi (turning angle from the vertex).
+    |z| <= z_max.  Returns a dict of arrays over crossings (numpy, or torch
+    tensors on ``device``): track, sector, row, y (local), z, psi (turning
+    angle from the vertex).
     """
     dt = torch.float64
     xr = torch.tensor(G.row_x_f64(), dtype=dt, device=device)          # [152]
@@ -167,15 +168,20 @@ def helix_crossings(tr: Tracks, distortion: RadialDistortion | None = None,
                 Yv, zv, pv = Yd[sel], zd[sel], psid[sel]
             else:
                 Yv, zv, pv = Y[idx], z[idx], psi[idx]
-            out["track"].append((ti + c0).cpu().numpy().astype(np.int64))
-            out["sector"].append(sec[ti, si].cpu().numpy().astype(np.int32))
-            out["row"].append(ri.cpu().numpy().astype(np.int32))
-            out["y"].append(Yv.cpu().numpy())
-            out["z"].append(zv.cpu().numpy())
-            out["psi"].append(pv.cpu().numpy())
+            out["track"].append(ti + c0)
+            out["sector"].append(sec[ti, si])
+            out["row"].append(ri)
+            out["y"].append(Yv)
+            out["z"].append(zv)
+            out["psi"].append(pv)
     res = {}
     for k, v in out.items():
-        res[k] = np.concatenate(v) if v else np.zeros(0, dtype=np.float64 if k in ("y", "z", "psi") else np.int64)
+        if v:
+            res[k] = torch.cat(v)
+        else:
+            res[k] = torch.zeros(0, dtype=dt if k in ("y", "z", "psi") else torch.int64, device=device)
+    if as_numpy:
+        res = {k: v.cpu().numpy() for k, v in res.items()}
     return res
 
 
@@ -245,58 +251,75 @@ class ClusterSet:
 
 def build_clusters(tracks: Tracks, sectors, rng_seed, smear_sigma=0.1, noise_frac=0.0,
                    distortion=None, drift_offsets=False, device="cpu", meta=None):
-    """Turn particles into a ClusterSet over the given sectors (one unit each)."""
-    ss = np.random.SeedSequence(rng_seed)
-    rng_smear, rng_noise, rng_order = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
-    sectors = np.asarray(sectors, dtype=np.int32)
-    unit_of_sector = np.full(G.N_SECTORS, -1, dtype=np.int64)
-    unit_of_sector[sectors] = np.arange(len(sectors))
+    """Turn particles into a ClusterSet over the given sectors (one unit each).
 
-    cr = helix_crossings(tracks, distortion, device=device)
-    keep = unit_of_sector[cr["sector"]] >= 0
+    Random numbers for smearing, noise and the in-row order come from a torch
+    generator on ``device`` seeded from ``rng_seed``: a seed reproduces the same
+    set on the same kind of device.
+    """
+    dev = torch.device(device)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(rng_seed) % (2**63))
+    dt = torch.float64
+    sectors = np.asarray(sectors, dtype=np.int32)
+    unit_of_sector = torch.full((G.N_SECTORS,), -1, dtype=torch.int64, device=dev)
+    unit_of_sector[torch.as_tensor(sectors, dtype=torch.int64, device=dev)] = torch.arange(
+        len(sectors), device=dev)
+
+    cr = helix_crossings(tracks, distortion, device=dev, as_numpy=False)
+    unit = unit_of_sector[cr["sector"]]
+    keep = unit >= 0
     trk = cr["track"][keep]
-    unit = unit_of_sector[cr["sector"][keep]]
-    row = cr["row"][keep].astype(np.int64)
+    unit = unit[keep]
+    row = cr["row"][keep].to(torch.int64)
     ty = cr["y"][keep]
     tz = cr["z"][keep]
     tpsi = cr["psi"][keep]
     if drift_offsets:
         # continuous read-out: the drift coordinate of a cluster is shifted by
         # the collision time, towards the read-out plane of its own side
-        sgn = np.where(tz >= 0.0, 1.0, -1.0)
-        tz = tz - sgn * G.DRIFT_CM_PER_US * tracks.t_us[trk]
-    n_sig = len(trk)
-    my = ty + rng_smear.normal(0.0, smear_sigma, n_sig) if smear_sigma > 0 else ty.copy()
-    mz = tz + rng_smear.normal(0.0, smear_sigma, n_sig) if smear_sigma > 0 else tz.copy()
+        t_us = torch.as_tensor(tracks.t_us, dtype=dt, device=dev)
+        sgn = torch.where(tz >= 0.0, 1.0, -1.0)
+        tz = tz - sgn * G.DRIFT_CM_PER_US * t_us[trk]
+    n_sig = int(trk.numel())
+    if smear_sigma > 0:
+        my = ty + smear_sigma * torch.randn(n_sig, generator=gen, device=dev, dtype=dt)
+        mz = tz + smear_sigma * torch.randn(n_sig, generator=gen, device=dev, dtype=dt)
+    else:
+        my, mz = ty.clone(), tz.clone()
 
     n_noise = int(round(noise_frac * n_sig))
     if n_noise:
-        nu = rng_noise.integers(0, len(sectors), n_noise)
-        nr = rng_noise.integers(0, G.N_ROWS, n_noise)
-        xr = G.row_x_f64()[nr]
-        ny = rng_noise.uniform(-1.0, 1.0, n_noise) * xr * G.tan_half_opening()
-        side_a = G.sector_side_is_a(sectors[nu])
+        nu = torch.randint(0, len(sectors), (n_noise,), generator=gen, device=dev)
+        nr = torch.randint(0, G.N_ROWS, (n_noise,), generator=gen, device=dev)
+        xr = torch.as_tensor(G.row_x_f64(), dtype=dt, device=dev)[nr]
+        ny = (torch.rand(n_noise, generator=gen, device=dev, dtype=dt) * 2.0 - 1.0) * xr * G.tan_half_opening()
+        side_a = torch.as_tensor(G.sector_side_is_a(sectors), device=dev)[nu]
         t_max = float(tracks.t_us.max()) if (drift_offsets and len(tracks)) else 0.0
         span = G.DRIFT_CM_PER_US * t_max
-        u01 = rng_noise.uniform(0.0, 1.0, n_noise)
-        nz = np.where(side_a, -span + u01 * (G.Z_MAX_CM + span), -G.Z_MAX_CM + u01 * (G.Z_MAX_CM + span))
-        trk = np.concatenate([trk, np.full(n_noise, -1, dtype=np.int64)])
-        unit = np.concatenate([unit, nu.astype(np.int64)])
-        row = np.concatenate([row, nr.astype(np.int64)])
-        ty = np.concatenate([ty, ny])
-        tz = np.concatenate([tz, nz])
-        my = np.concatenate([my, ny])
-        mz = np.concatenate([mz, nz])
-        tpsi = np.concatenate([tpsi, np.full(n_noise, np.nan)])
+        u01 = torch.rand(n_noise, generator=gen, device=dev, dtype=dt)
+        nz = torch.where(side_a, -span + u01 * (G.Z_MAX_CM + span),
+                         -G.Z_MAX_CM + u01 * (G.Z_MAX_CM + span))
+        trk = torch.cat([trk, torch.full((n_noise,), -1, dtype=torch.int64, device=dev)])
+        unit = torch.cat([unit, nu])
+        row = torch.cat([row, nr])
+        ty = torch.cat([ty, ny])
+        tz = torch.cat([tz, nz])
+        my = torch.cat([my, ny])
+        mz = torch.cat([mz, nz])
+        tpsi = torch.cat([tpsi, torch.full((n_noise,), float("nan"), dtype=dt, device=dev)])
 
+    # group by (unit, row); seeded shuffle inside each group
     key = unit * G.N_ROWS + row
-    order = np.lexsort((rng_order.random(len(key)), key))
-    counts = np.bincount(key, minlength=len(sectors) * G.N_ROWS)
+    perm = torch.randperm(key.numel(), generator=gen, device=dev)
+    order = perm[torch.argsort(key[perm], stable=True)]
+    counts = torch.bincount(key, minlength=len(sectors) * G.N_ROWS)
     row_begin = np.zeros(len(sectors) * G.N_ROWS + 1, dtype=np.int64)
-    np.cumsum(counts, out=row_begin[1:])
-    return ClusterSet(len(sectors), sectors, row_begin,
-                      my[order].astype(np.float32), mz[order].astype(np.float32),
-                      trk[order], ty[order], tz[order], tpsi[order], tracks, dict(meta or {}))
+    np.cumsum(counts.cpu().numpy(), out=row_begin[1:])
+    h = lambda t: t[order].cpu().numpy()
+    return ClusterSet(len(sectors), sectors, row_begin, h(my.to(torch.float32)),
+                      h(mz.to(torch.float32)), h(trk), h(ty), h(tz), h(tpsi), tracks,
+                      dict(meta or {}))
 
 
 # ----------------------------------------------------------------------------
