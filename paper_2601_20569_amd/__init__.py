@@ -195,7 +195,7 @@ class SectorTracker:
         dev = torch.device("cuda", self.device)
         cap_start = int(n_clusters // 3 + 1) if cap_start is None else int(cap_start)
         cap_tracks = cap_start if cap_tracks is None else int(cap_tracks)
-        cap_hits = int(max(1024, 2 * n_clusters)) if cap_hits is None else int(cap_hits)
+        cap_hits = int(max(1024, 4 * n_clusters)) if cap_hits is None else int(cap_hits)
         nb = self.workspace_bytes(n_units, n_clusters, cap_start)
         ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         off = (-ws.data_ptr()) % 256

@@ -5,6 +5,10 @@
 // every query is widened so that it covers all clusters its exact predicate
 // can accept, and every selection breaks ties by the caller's cluster index,
 // so results do not depend on binning or on the order inside a bin.
+//
+// One block builds one row: z range (block reduction), histogram of bin keys
+// in LDS, block-wide scan, then a scatter through LDS cursors.  Rows are read
+// three times (the passes hit the last-level cache); no global atomics.
 #pragma once
 
 #include "tpcx_common.h"
@@ -23,96 +27,99 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
     p[i] = v;
 }
 
-// One block per unit: z range of its clusters -> bin origin and scale.
-__global__ void k_unit_zrange(const int64_t* __restrict__ row_begin, const float* __restrict__ z,
-                              int n_rows, int nz, UnitZ* __restrict__ unit_z) {
-  __shared__ float smin[1024 / kWave], smax[1024 / kWave];
-  const int u = blockIdx.x;
-  const int64_t b = row_begin[int64_t(u) * n_rows], e = row_begin[int64_t(u + 1) * n_rows];
+__device__ __forceinline__ float block_reduce_min(float v, float* lds) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, kWave));
+  const int wid = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (lane_id() == 0) lds[wid] = v;
+  __syncthreads();
+  float r = lds[0];
+  for (int w = 1; w < nw; ++w) r = fminf(r, lds[w]);
+  return r;
+}
+
+__device__ __forceinline__ float block_reduce_max(float v, float* lds) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, kWave));
+  const int wid = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (lane_id() == 0) lds[wid] = v;
+  __syncthreads();
+  float r = lds[0];
+  for (int w = 1; w < nw; ++w) r = fmaxf(r, lds[w]);
+  return r;
+}
+
+// Dynamic LDS: nz * ny + 1 int32 bin counters of the row.
+__global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float* __restrict__ y,
+                             const float* __restrict__ z, Grid g, UnitZ* __restrict__ row_z,
+                             int32_t* __restrict__ bins, float* __restrict__ sy,
+                             float* __restrict__ sz, int32_t* __restrict__ sid) {
+  extern __shared__ int32_t hist[];
+  __shared__ float red[1024 / kWave];
+  __shared__ int64_t scan_lds[1024 / kWave];
+  const int k = blockIdx.x;
+  const int r = k % g.n_rows;
+  const int64_t b = row_begin[k], e = row_begin[k + 1];
+  const int ny = g.rows[r].ny;
+  const int nb = g.nz * ny;
+  const int64_t base = g.row_base(k);
+
+  // z range of the row
   float lo = INFINITY, hi = -INFINITY;
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    float v = z[i];
+    const float v = z[i];
     lo = fminf(lo, v);
     hi = fmaxf(hi, v);
   }
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, d, kWave));
-    hi = fmaxf(hi, __shfl_xor(hi, d, kWave));
+  lo = block_reduce_min(lo, red);
+  hi = block_reduce_max(hi, red);
+  UnitZ rz;
+  const float span = hi - lo;
+  if (!(span > 0.0f) || !isfinite(span)) {
+    rz.zmin = isfinite(lo) ? lo : 0.0f;
+    rz.inv_bz = 0.0f;
+  } else {
+    rz.zmin = lo;
+    rz.inv_bz = float(g.nz) / span;
   }
-  const int wid = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
-  if (lane_id() == 0) {
-    smin[wid] = lo;
-    smax[wid] = hi;
-  }
+  if (threadIdx.x == 0) row_z[k] = rz;
+
+  // histogram
+  for (int t = threadIdx.x; t <= nb; t += blockDim.x) hist[t] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < nw; ++w) {
-      lo = fminf(lo, smin[w]);
-      hi = fmaxf(hi, smax[w]);
-    }
-    UnitZ g;
-    float span = hi - lo;
-    if (!(span > 0.0f) || !isfinite(span)) {
-      g.zmin = isfinite(lo) ? lo : 0.0f;
-      g.inv_bz = 0.0f;
-    } else {
-      g.zmin = lo;
-      g.inv_bz = float(nz) / span;
-    }
-    unit_z[u] = g;
-  }
-}
+  const RowInfo ri = g.rows[r];
+  auto key_of = [&](float yy, float zz) {
+    float vz = (zz - rz.zmin) * rz.inv_bz;
+    vz = fminf(fmaxf(vz, 0.0f), float(g.nz - 1));
+    float vy = (yy - ri.y0) * ri.inv_by;
+    vy = fminf(fmaxf(vy, 0.0f), float(ny - 1));
+    return int(vz) * ny + int(vy);
+  };
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) atomicAdd(&hist[key_of(y[i], z[i])], 1);
+  __syncthreads();
 
-// One block per (unit, row): bin key of every cluster and its slot in the bin.
-__global__ void k_grid_count(const int64_t* __restrict__ row_begin, const float* __restrict__ y,
-                             const float* __restrict__ z, Grid g, int32_t* __restrict__ bin_cnt,
-                             int32_t* __restrict__ key, int32_t* __restrict__ slot) {
-  const int k = blockIdx.x;
-  const int u = k / g.n_rows, r = k % g.n_rows;
-  const int64_t b = row_begin[k], e = row_begin[k + 1];
-  const int64_t base = g.row_base(u, r);
-  const int ny = g.rows[r].ny;
+  // exclusive scan of the counters: each thread a contiguous chunk
+  const int per = (nb + blockDim.x - 1) / blockDim.x;
+  const int t0 = min(nb, int(threadIdx.x) * per), t1 = min(nb, t0 + per);
+  int64_t s = 0;
+  for (int t = t0; t < t1; ++t) s += hist[t];
+  int64_t tot;
+  int64_t run = block_exclusive_scan(s, scan_lds, &tot) + b;
+  for (int t = t0; t < t1; ++t) {
+    const int32_t c = hist[t];
+    hist[t] = int32_t(run);
+    bins[base + t] = int32_t(run);
+    run += c;
+  }
+  if (threadIdx.x == 0) bins[base + nb] = int32_t(e);
+  __syncthreads();
+
+  // scatter through the LDS cursors (order inside a bin is free)
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    int kk = g.zbin(u, z[i]) * ny + g.ybin(r, y[i]);
-    key[i] = kk;
-    slot[i] = atomicAdd(&bin_cnt[base + kk], 1);
-  }
-}
-
-// One block per (unit, row): bin counts -> absolute start positions, in place,
-// with the row end in the sentinel entry after the last bin.
-__global__ void k_grid_scan(const int64_t* __restrict__ row_begin, Grid g,
-                            int32_t* __restrict__ bins) {
-  __shared__ int64_t lds[1024 / kWave];
-  const int k = blockIdx.x;
-  const int u = k / g.n_rows, r = k % g.n_rows;
-  const int64_t base = g.row_base(u, r);
-  const int nb = g.nz * g.rows[r].ny;
-  int64_t run = row_begin[k];
-  for (int t0 = 0; t0 < nb; t0 += blockDim.x) {
-    int t = t0 + threadIdx.x;
-    int64_t c = t < nb ? bins[base + t] : 0;
-    int64_t tot;
-    int64_t ex = block_exclusive_scan(c, lds, &tot);
-    if (t < nb) bins[base + t] = int32_t(run + ex);
-    run += tot;
-  }
-  if (threadIdx.x == 0) bins[base + nb] = int32_t(run);
-}
-
-// One block per (unit, row): move every cluster to its sorted position.
-__global__ void k_grid_scatter(const int64_t* __restrict__ row_begin, const float* __restrict__ y,
-                               const float* __restrict__ z, const int32_t* __restrict__ key,
-                               const int32_t* __restrict__ slot, Grid g, float* __restrict__ sy,
-                               float* __restrict__ sz, int32_t* __restrict__ sid) {
-  const int k = blockIdx.x;
-  const int u = k / g.n_rows, r = k % g.n_rows;
-  const int64_t b = row_begin[k], e = row_begin[k + 1];
-  const int64_t base = g.row_base(u, r);
-  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-    int64_t pos = g.bin_start[base + key[i]] + slot[i];
-    sy[pos] = y[i];
-    sz[pos] = z[i];
+    const float yy = y[i], zz = z[i];
+    const int32_t pos = atomicAdd(&hist[key_of(yy, zz)], 1);
+    sy[pos] = yy;
+    sz[pos] = zz;
     sid[pos] = int32_t(i);
   }
 }

@@ -8,65 +8,105 @@
 
 namespace tpcx {
 
-// Neighbour finder.  One thread per cluster (sorted order).  For cluster h in
-// row r (1 <= r <= n_rows-2) consider every u in row r+1 and d in row r-1
-// within |dy| <= wy and |dz| <= wz of h; the deviation of h from the chord d-u
-// at row r is e = h - (d + (u - d) * f_r), D = ey^2 + ez^2.  The pair with the
+// Neighbour finder.  One block per (unit, row); threads walk the row's
+// clusters in sorted order, so a wavefront works on neighbouring clusters and
+// its reads of rows r-1 and r+1 hit the caches.  For cluster h in row r
+// (1 <= r <= n_rows-2) every u in row r+1 and d in row r-1 within |dy| <= wy
+// and |dz| <= wz of h is considered; the deviation of h from the chord d-u at
+// row r is e = h - (d + (u - d) * f_r), D = ey^2 + ez^2.  The pair with the
 // smallest (D, id_u, id_d) among D <= d2max gives link_up/link_down (caller
 // ids), -1 if none.  f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.
-__global__ void k_neighbours(const int64_t* __restrict__ row_begin, int n_units, Grid g,
-                             const float* __restrict__ frac, DevParams p,
-                             int32_t* __restrict__ link_up, int32_t* __restrict__ link_down) {
-  const int64_t n = row_begin[int64_t(n_units) * g.n_rows];
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int k = upper_row(row_begin, n_units * g.n_rows + 1, i);
-  const int u = k / g.n_rows, r = k % g.n_rows;
-  const int32_t h = g.sid[i];
+// The down candidates of a cluster are collected once in LDS (up to kNfD;
+// more fall back to re-reading them for every up candidate).
+constexpr int kNfD = 8;
+constexpr int kNfBlock = 256;
+
+__global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restrict__ row_begin, Grid g,
+                                                         const float* __restrict__ frac, DevParams p,
+                                                         int32_t* __restrict__ link_up,
+                                                         int32_t* __restrict__ link_down) {
+  __shared__ float dy_l[kNfD][kNfBlock];
+  __shared__ float dz_l[kNfD][kNfBlock];
+  __shared__ int32_t did_l[kNfD][kNfBlock];
+  const int k = blockIdx.x;
+  const int r = k % g.n_rows;
+  const int64_t b = row_begin[k], e = row_begin[k + 1];
+  const int t = threadIdx.x;
   if (r == 0 || r == g.n_rows - 1) {
-    link_up[h] = -1;
-    link_down[h] = -1;
+    for (int64_t i = b + t; i < e; i += blockDim.x) {
+      const int32_t h = g.sid[i];
+      link_up[h] = -1;
+      link_down[h] = -1;
+    }
     return;
   }
-  const float yh = g.sy[i], zh = g.sz[i];
   const float f = frac[r];
   const float wy = p.wy, wz = p.wz;
-  const float pz = wz + box_pad(zh), py = wy + box_pad(yh);
-  const int zb0 = g.zbin(u, zh - pz), zb1 = g.zbin(u, zh + pz);
-  const int64_t bu = g.row_base(u, r + 1), bd = g.row_base(u, r - 1);
+  const int ku = k + 1, kd = k - 1;
+  const int64_t bu = g.row_base(ku), bd = g.row_base(kd);
   const int nyu = g.rows[r + 1].ny, nyd = g.rows[r - 1].ny;
-  const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
-  const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
+  for (int64_t i = b + t; i < e; i += blockDim.x) {
+    const int32_t h = g.sid[i];
+    const float yh = g.sy[i], zh = g.sz[i];
+    const float pz = wz + box_pad(zh), py = wy + box_pad(yh);
+    const int zu0 = g.zbin(ku, zh - pz), zu1 = g.zbin(ku, zh + pz);
+    const int zd0 = g.zbin(kd, zh - pz), zd1 = g.zbin(kd, zh + pz);
+    const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
+    const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
 
-  float bestD = 0.0f;
-  int32_t best_u = -1, best_d = -1;
-  for (int zu = zb0; zu <= zb1; ++zu) {
-    const int32_t ju0 = g.bin_start[bu + zu * nyu + yu0], ju1 = g.bin_start[bu + zu * nyu + yu1 + 1];
-    for (int32_t ju = ju0; ju < ju1; ++ju) {
-      const float yu = g.sy[ju], zuu = g.sz[ju];
-      if (!(fabsf(yu - yh) <= wy && fabsf(zuu - zh) <= wz)) continue;
-      const int32_t cu = g.sid[ju];
-      for (int zd = zb0; zd <= zb1; ++zd) {
-        const int32_t jd0 = g.bin_start[bd + zd * nyd + yd0], jd1 = g.bin_start[bd + zd * nyd + yd1 + 1];
-        for (int32_t jd = jd0; jd < jd1; ++jd) {
-          const float yd = g.sy[jd], zdd = g.sz[jd];
-          if (!(fabsf(yd - yh) <= wy && fabsf(zdd - zh) <= wz)) continue;
-          const float ey = yh - (yd + (yu - yd) * f);
-          const float ez = zh - (zdd + (zuu - zdd) * f);
-          const float D = ey * ey + ez * ez;
-          if (!(D <= p.d2max)) continue;
-          const int32_t cd = g.sid[jd];
-          if (best_u < 0 || D < bestD || (D == bestD && (cu < best_u || (cu == best_u && cd < best_d)))) {
-            bestD = D;
-            best_u = cu;
-            best_d = cd;
+    // down candidates inside the window
+    int nd = 0;
+    for (int zb = zd0; zb <= zd1; ++zb) {
+      const int32_t j0 = g.bin_start[bd + zb * nyd + yd0], j1 = g.bin_start[bd + zb * nyd + yd1 + 1];
+      for (int32_t j = j0; j < j1; ++j) {
+        const float yd = g.sy[j], zd = g.sz[j];
+        if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+        if (nd < kNfD) {
+          dy_l[nd][t] = yd;
+          dz_l[nd][t] = zd;
+          did_l[nd][t] = g.sid[j];
+        }
+        ++nd;
+      }
+    }
+    float bestD = 0.0f;
+    int32_t best_u = -1, best_d = -1;
+    if (nd > 0) {
+      for (int zb = zu0; zb <= zu1; ++zb) {
+        const int32_t j0 = g.bin_start[bu + zb * nyu + yu0], j1 = g.bin_start[bu + zb * nyu + yu1 + 1];
+        for (int32_t ju = j0; ju < j1; ++ju) {
+          const float yu = g.sy[ju], zu = g.sz[ju];
+          if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
+          const int32_t cu = g.sid[ju];
+          auto consider = [&](float yd, float zd, int32_t cd) {
+            const float ey = yh - (yd + (yu - yd) * f);
+            const float ez = zh - (zd + (zu - zd) * f);
+            const float D = ey * ey + ez * ez;
+            if (!(D <= p.d2max)) return;
+            if (best_u < 0 || D < bestD || (D == bestD && (cu < best_u || (cu == best_u && cd < best_d)))) {
+              bestD = D;
+              best_u = cu;
+              best_d = cd;
+            }
+          };
+          if (nd <= kNfD) {
+            for (int q = 0; q < nd; ++q) consider(dy_l[q][t], dz_l[q][t], did_l[q][t]);
+          } else {
+            for (int zb2 = zd0; zb2 <= zd1; ++zb2) {
+              const int32_t k0 = g.bin_start[bd + zb2 * nyd + yd0], k1 = g.bin_start[bd + zb2 * nyd + yd1 + 1];
+              for (int32_t jd = k0; jd < k1; ++jd) {
+                const float yd = g.sy[jd], zd = g.sz[jd];
+                if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+                consider(yd, zd, g.sid[jd]);
+              }
+            }
           }
         }
       }
     }
+    link_up[h] = best_u;
+    link_down[h] = best_d;
   }
-  link_up[h] = best_u;
-  link_down[h] = best_d;
 }
 
 // Mutual-link cleaning and start-hit flags, one thread per cluster (caller

@@ -58,10 +58,8 @@ struct Carver {
 };
 
 struct Layout {
-  UnitZ* unit_z;
+  UnitZ* row_z;
   int32_t* bins;
-  int32_t* key;
-  int32_t* slot;
   float* sy;
   float* sz;
   int32_t* sid;
@@ -90,10 +88,8 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   Carver cv{static_cast<char*>(ws)};
   Layout L{};
   const int64_t nb = blocks_for(n, block);
-  L.unit_z = cv.take<UnitZ>(n_units);
+  L.row_z = cv.take<UnitZ>(int64_t(n_units) * c->n_rows);
   L.bins = cv.take<int32_t>(int64_t(n_units) * bins_per_unit(c, nz));
-  L.key = cv.take<int32_t>(n);
-  L.slot = cv.take<int32_t>(n);
   L.sy = cv.take<float>(n);
   L.sz = cv.take<float>(n);
   L.sid = cv.take<int32_t>(n);
@@ -119,11 +115,22 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   return L;
 }
 
+// The bin counters of one row live in LDS during the grid build.
+constexpr int kMaxRowBins = 16384;
+
+int max_row_ny(const tpcx_ctx* c) {
+  int m = 1;
+  for (const RowInfo& r : c->rows_host) m = std::max(m, r.ny);
+  return m;
+}
+
 tpcx_tuning effective_tuning(const tpcx_ctx* c, int32_t n_units, int64_t n) {
-  if (c->tuning_fixed) return c->tuning;
-  tpcx_tuning t;
-  tpcx_default_tuning(n_units, n, &t);
-  t.bin_y = c->tuning.bin_y;  // the row table is built for this width
+  tpcx_tuning t = c->tuning;
+  if (!c->tuning_fixed) {
+    tpcx_default_tuning(n_units, n, &t);
+    t.bin_y = c->tuning.bin_y;  // the row table is built for this width
+  }
+  t.n_zbins = std::max(1, std::min(t.n_zbins, (kMaxRowBins - 1) / max_row_ny(c)));
   return t;
 }
 
@@ -281,11 +288,10 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   const int B = t.block;
   const int64_t nb = blocks_for(N, B);
-  const int64_t nbins = int64_t(U) * bins_per_unit(c, t.n_zbins);
 
   Grid g;
   g.rows = c->d_rows;
-  g.unit_z = L.unit_z;
+  g.row_z = L.row_z;
   g.bin_start = L.bins;
   g.sy = L.sy;
   g.sz = L.sz;
@@ -303,23 +309,16 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
     if (ev) (void)hipEventRecord(ev[i], stream);
   };
   mark(0);
-  const int fill_grid = 1024;
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, out->counts, int64_t(4), int64_t(0));
-  hipLaunchKernelGGL(k_fill_i32, dim3(fill_grid), dim3(256), 0, stream, L.bins, nbins, 0);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(1), 0);
   const int UR = U * R;
-  hipLaunchKernelGGL(k_unit_zrange, dim3(U), dim3(256), 0, stream, in->row_begin, in->z, R,
-                     t.n_zbins, L.unit_z);
-  hipLaunchKernelGGL(k_grid_count, dim3(UR), dim3(B), 0, stream, in->row_begin, in->y, in->z, g,
-                     L.bins, L.key, L.slot);
-  hipLaunchKernelGGL(k_grid_scan, dim3(UR), dim3(B), 0, stream, in->row_begin, g, L.bins);
-  hipLaunchKernelGGL(k_grid_scatter, dim3(UR), dim3(B), 0, stream, in->row_begin, in->y, in->z,
-                     L.key, L.slot, g, L.sy, L.sz, L.sid);
+  const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
+  hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,
+                     in->z, g, L.row_z, L.bins, L.sy, L.sz, L.sid);
   mark(1);
-  if (N > 0) {
-    hipLaunchKernelGGL(k_neighbours, dim3(nb), dim3(B), 0, stream, in->row_begin, U, g, c->d_frac,
-                       c->dp, L.up, L.down);
-  }
+  if (N > 0)
+    hipLaunchKernelGGL(k_neighbours, dim3(UR), dim3(kNfBlock), 0, stream, in->row_begin, g,
+                       c->d_frac, c->dp, L.up, L.down);
   mark(2);
   if (N > 0) {
     hipLaunchKernelGGL(k_clean_flags, dim3(nb), dim3(B), 0, stream, N, L.up, L.down, L.cup,
@@ -363,7 +362,7 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
                      L.tmp.n, c->dp.min_hits, L.part);
   hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(64), 0, stream, L.part, kKeepBlocks, out->counts,
                      out->cap_tracks, out->cap_hits);
-  hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
+  hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(kKeepBlock), 0, stream, out->counts, cap_start,
                      L.starts, L.tmp, R, c->dp.min_hits, L.part, o);
   mark(5);
 

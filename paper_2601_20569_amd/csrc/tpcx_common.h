@@ -24,16 +24,16 @@ struct RowInfo {
   float inv_by;    // bins per cm along y
 };
 
-// Per-unit z range of the search grid.
+// z binning of one (unit, row) of the search grid.
 struct UnitZ {
   float zmin;
   float inv_bz;  // bins per cm along z
 };
 
-// Read-only view of the sorted, binned clusters.
+// Read-only view of the sorted, binned clusters.  k = unit * n_rows + row.
 struct Grid {
   const RowInfo* rows;
-  const UnitZ* unit_z;
+  const UnitZ* row_z;        // [n_units * n_rows]
   const int32_t* bin_start;  // [n_units * btot]; absolute sorted positions
   const float* sy;
   const float* sz;
@@ -41,11 +41,12 @@ struct Grid {
   int32_t n_rows, nz;
   int64_t btot;  // bins (+1 sentinel per row) of one unit
 
-  __device__ __forceinline__ int64_t row_base(int u, int r) const {
+  __device__ __forceinline__ int64_t row_base(int k) const {
+    const int u = k / n_rows, r = k - u * n_rows;
     return int64_t(u) * btot + int64_t(nz) * rows[r].cum_ny + r;
   }
-  __device__ __forceinline__ int zbin(int u, float z) const {
-    UnitZ g = unit_z[u];
+  __device__ __forceinline__ int zbin(int k, float z) const {
+    UnitZ g = row_z[k];
     float v = (z - g.zmin) * g.inv_bz;
     v = fminf(fmaxf(v, 0.0f), float(nz - 1));
     return int(v);

@@ -115,13 +115,14 @@ __device__ __forceinline__ float kf_update(KState& q, float my, float mz, const 
 // The grid box is |dy| <= 4 sqrt(Sy) (and z alike), widened to be exact.
 __device__ __forceinline__ int32_t kf_search(const Grid& g, int u, int r, const KState& q,
                                              const DevParams& p, float* out_my, float* out_mz) {
+  const int k = u * g.n_rows + r;
   const float Sy = q.cyy + p.sy2;
   const float Sz = q.czz + p.sz2;
   const float hy = sqrtf(p.chi2max * Sy) * 1.0001f + box_pad(q.y);
   const float hz = sqrtf(p.chi2max * Sz) * 1.0001f + box_pad(q.z);
-  const int zb0 = g.zbin(u, q.z - hz), zb1 = g.zbin(u, q.z + hz);
+  const int zb0 = g.zbin(k, q.z - hz), zb1 = g.zbin(k, q.z + hz);
   const int yb0 = g.ybin(r, q.y - hy), yb1 = g.ybin(r, q.y + hy);
-  const int64_t base = g.row_base(u, r);
+  const int64_t base = g.row_base(k);
   const int ny = g.rows[r].ny;
   int32_t best = -1;
   float bch = 0.0f, bmy = 0.0f, bmz = 0.0f;
@@ -370,16 +371,27 @@ struct TrackOut {
   int32_t* ndf;
 };
 
-__global__ void k_keep_write(const int64_t* __restrict__ counts, int64_t cap_start,
-                             const int32_t* __restrict__ starts, TrackletTmp tmp, int n_rows,
-                             int min_hits, const int64_t* __restrict__ part, TrackOut o) {
-  __shared__ int64_t lds[1024 / kWave];
+// Writes the kept tracklets in start-hit order.  Per tile of 256 slots a
+// block scan gives every kept tracklet its output index and hit offset; one
+// thread writes each record, then the wavefronts copy the hit lists, one
+// tracklet per wavefront at a time, lanes over the hits (coalesced).
+constexpr int kKeepBlock = 256;
+
+__global__ void __launch_bounds__(kKeepBlock) k_keep_write(
+    const int64_t* __restrict__ counts, int64_t cap_start, const int32_t* __restrict__ starts,
+    TrackletTmp tmp, int n_rows, int min_hits, const int64_t* __restrict__ part, TrackOut o) {
+  __shared__ int64_t lds[kKeepBlock / kWave];
+  __shared__ int64_t s_hb[kKeepBlock];
+  __shared__ int32_t s_slot[kKeepBlock];
+  __shared__ int32_t s_n[kKeepBlock];
+  __shared__ int32_t s_nu[kKeepBlock];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
   int64_t b, e;
   chunk_of(n_start, &b, &e);
   int64_t t_run = part[2 * blockIdx.x], h_run = part[2 * blockIdx.x + 1];
   const int64_t C = tmp.cap;
-  for (int64_t s0 = b; s0 < e; s0 += blockDim.x) {
+  const int wid = threadIdx.x / kWave, nw = kKeepBlock / kWave;
+  for (int64_t s0 = b; s0 < e; s0 += kKeepBlock) {
     const int64_t s = s0 + threadIdx.x;
     int32_t n = 0;
     bool keep = false;
@@ -390,9 +402,11 @@ __global__ void k_keep_write(const int64_t* __restrict__ counts, int64_t cap_sta
     int64_t tt, th;
     const int64_t pt = block_exclusive_scan(keep ? 1 : 0, lds, &tt);
     const int64_t ph = block_exclusive_scan(keep ? n : 0, lds, &th);
+    bool fits = false;
     if (keep) {
       const int64_t ti = t_run + pt, hb = h_run + ph;
-      if (ti < o.cap_tracks && hb + n <= o.cap_hits) {
+      fits = ti < o.cap_tracks && hb + n <= o.cap_hits;
+      if (fits) {
         o.unit[ti] = tmp.unit[s];
         o.start[ti] = starts[s];
         o.n_hits[ti] = n;
@@ -407,21 +421,30 @@ __global__ void k_keep_write(const int64_t* __restrict__ counts, int64_t cap_sta
                               0.0f, ctt, cwy, 0.0f, cws, 0.0f, cww};
         for (int j = 0; j < 15; ++j) o.cov[ti * 15 + j] = cv[j];
         o.chi2[ti] = tmp.f[15 * C + s];
-        // down-phase clusters sit at the end of the slot in ascending row order
-        const int nu = tmp.n_up[s], nd = n - nu;
-        const int32_t* hs = tmp.hit + s * n_rows;
-        const uint8_t* rs = tmp.hrow + s * n_rows;
-        int64_t w = hb;
-        for (int j = n_rows - nd; j < n_rows; ++j, ++w) {
-          o.hit_id[w] = hs[j];
-          o.hit_row[w] = rs[j];
-        }
-        for (int j = 0; j < nu; ++j, ++w) {
-          o.hit_id[w] = hs[j];
-          o.hit_row[w] = rs[j];
-        }
+      }
+      s_slot[pt] = fits ? int32_t(s - s0) : -1;
+      s_hb[pt] = hb;
+      s_n[pt] = n;
+      s_nu[pt] = tmp.n_up[s];
+    }
+    __syncthreads();
+    // hit lists: down-phase clusters sit at the end of the slot in ascending
+    // row order, up-phase clusters at its start
+    for (int q = wid; q < int(tt); q += nw) {
+      const int32_t sl = s_slot[q];
+      if (sl < 0) continue;
+      const int64_t ss = s0 + sl;
+      const int nn = s_n[q], nu = s_nu[q], nd = nn - nu;
+      const int64_t hb = s_hb[q];
+      const int32_t* hs = tmp.hit + ss * n_rows;
+      const uint8_t* rs = tmp.hrow + ss * n_rows;
+      for (int j = lane_id(); j < nn; j += kWave) {
+        const int src = j < nd ? n_rows - nd + j : j - nd;
+        o.hit_id[hb + j] = hs[src];
+        o.hit_row[hb + j] = rs[src];
       }
     }
+    __syncthreads();
     t_run += tt;
     h_run += th;
   }
