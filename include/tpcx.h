@@ -62,7 +62,7 @@ typedef struct tpcx_ctx tpcx_ctx;
 /* Detector description: the pad-row planes of a sector (Section 2: two halves
  * of 18 trapezoidal sectors, each with pad rows). */
 typedef struct {
-  int32_t n_rows;            /* 3 .. 255 */
+  int32_t n_rows;            /* 3 .. 160 */
   const float* row_x_host;   /* [n_rows] strictly increasing plane distances, cm */
   float tan_half_opening;    /* half-width of a row = row_x * tan_half_opening (tan 10 deg) */
   float bz_tesla;            /* solenoid field */
@@ -79,6 +79,7 @@ typedef struct {
   float cww0;           /* seed variance of q/pT, (GeV/c)^-2 */
   int32_t min_hits;     /* tracklets with fewer clusters are dropped */
   int32_t max_misses;   /* consecutive rows without a cluster that end following */
+  int32_t descent_rows; /* longest step (rows) of the walk back to the start row */
 } tpcx_params;
 
 /* Launch and search-grid tuning.  Never changes results. */
@@ -86,8 +87,7 @@ typedef struct {
   float bin_y;          /* search-grid bin width along the pad row, cm */
   int32_t n_zbins;      /* search-grid bins along z per unit (z range taken from data) */
   int32_t block;        /* threads per block of the per-cluster kernels (64..1024) */
-  int32_t construct_block; /* threads per block of the tracklet constructor */
-  int32_t construct_grid;  /* blocks of the tracklet constructor (work-queue driven) */
+  int32_t construct_grid;  /* blocks of 256 lanes of the persistent tracklet constructor */
 } tpcx_tuning;
 
 /* Clusters grouped by (unit, row): those of unit u, row r are the index range
@@ -157,6 +157,85 @@ tpcx_status tpcx_track(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t 
 tpcx_status tpcx_poll(tpcx_ctx* ctx, const tpcx_tracks* out, hipStream_t stream);
 
 const char* tpcx_strerror(tpcx_status s);
+
+/* ------------------------------------------------------------------------
+ * Track refit through a space-charge-distortion correction map, and its
+ * gradient with respect to the map (paper: correction maps for the TPC
+ * space-charge distortions, Abstract and Section 2; the track fit is a Kalman
+ * filter over the attached clusters, Section 2).
+ *
+ * Map: three components (delta r, delta r*phi, delta z) [cm], each a
+ * tensor-product uniform cubic B-spline over 36 phi nodes (every 10 deg,
+ * periodic, node 0 at phi = 0), 17 r nodes (85 + 10 j cm) and 20 z nodes
+ * (-250 + k 500/19 cm); theta[((c*36 + i)*17 + j)*20 + k], float32.  A cluster
+ * measured at (x, y, z) in its sector frame (radius r, azimuth
+ * alpha_unit + atan2(y, x)) moves by delta r along (x, y)/r, by delta r*phi
+ * along (-y, x)/r and by delta z along z.
+ * Refit: outwards from the track's innermost cluster; y, z from that cluster,
+ * sin(phi), dz/ds, q/pT from `seed`, covariance diag(sy^2, sz^2, 1e-2, 1e-2,
+ * 1); propagate to every further cluster's own corrected x and update, no
+ * rejection; chi2 = sum of the updates' chi2.  A track whose propagation is
+ * stopped by a guard gets ok = 0, chi2 = 0 and no gradient.
+ * ------------------------------------------------------------------------ */
+#define TPCX_MAP_NCOEF 36720
+
+typedef struct {
+  int64_t n_tracks;
+  const int64_t* hit_begin;  /* [n_tracks + 1] offsets into hit_id / hit_row */
+  const int32_t* hit_id;     /* cluster ids (indices into y, z), ascending rows per track */
+  const uint8_t* hit_row;    /* rows of those clusters */
+  const int32_t* unit;       /* [n_tracks] unit of each track */
+  const float* seed;         /* [n_tracks][5] y, z, sin(phi), dz/ds, q/pT (tracking result) */
+  const float* y;            /* clusters, as given to tpcx_track */
+  const float* z;
+  const float* unit_alpha;   /* [n_units] azimuth of each unit's sector centre line, rad */
+} tpcx_refit_in;
+
+/* Workspace of tpcx_refit + tpcx_refit_backward (shared by the pair). */
+size_t tpcx_refit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_tracks, int64_t n_hits);
+
+/* Forward refit: chi2[n_tracks], ok[n_tracks].  theta may be NULL (no
+ * correction).  Keeps the corrected clusters and the filter state every 16
+ * clusters in ws for tpcx_refit_backward. */
+tpcx_status tpcx_refit(tpcx_ctx* ctx, const tpcx_refit_in* in, const float* theta, float* chi2,
+                       int32_t* ok, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Backward: grad_theta[TPCX_MAP_NCOEF] (overwritten) = d(sum_t dL_dchi2[t] *
+ * chi2[t]) / d theta, at the theta of the preceding tpcx_refit with the same
+ * `in` and ws.  Recomputes the filter states one 16-cluster segment at a
+ * time from the stored states and runs the reverse sweep; sums in 64-bit fixed
+ * point (2^-32), so the result does not depend on scheduling. */
+tpcx_status tpcx_refit_backward(tpcx_ctx* ctx, const tpcx_refit_in* in, const float* dL_dchi2,
+                                float* grad_theta, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many events or time-frame slices at once.  Their units are
+ * packed unit-major into one tpcx_clusters (tracklets carry their unit, so a
+ * slice's tracklets are those of its unit range).  The whole tracking sequence
+ * and the refit of every tracklet with at least refit->min_hits clusters run
+ * as one HIP graph: captured on the first call with a given set of arguments,
+ * replayed by later calls with the same arguments.  The stream must be one
+ * that can be captured (not the legacy default stream).  The persistent
+ * kernels (tracklet constructor, refit) take their work counts from the
+ * device, so a replay needs no host synchronisation.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t min_hits;         /* refit tracklets with at least this many clusters (>= 2) */
+  const float* theta;       /* map coefficients [TPCX_MAP_NCOEF], or NULL for no correction */
+  const float* unit_alpha;  /* [n_units] azimuth of each unit's sector centre line, rad */
+  float* chi2;              /* [cap_tracks] refit chi2 (0 when not refitted) */
+  int32_t* ok;              /* [cap_tracks] 1 when refitted */
+} tpcx_batch_refit;
+
+size_t tpcx_batched_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters,
+                                    int64_t cap_start, int64_t cap_tracks, int64_t cap_hits);
+
+/* Tracking of every unit of `in` plus the refit (refit may be NULL).  Outputs
+ * as tpcx_track; out->counts[3] non-zero means an overflow, and then no
+ * tracklet is refitted. */
+tpcx_status tpcx_track_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                               int64_t cap_start, const tpcx_tracks* out,
+                               const tpcx_batch_refit* refit, hipStream_t stream);
 
 /* Stage timing (profiling aid).  Stages of one tpcx_track call, in order. */
 #define TPCX_STAGE_GRID 0       /* search-grid build */

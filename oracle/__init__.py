@@ -21,6 +21,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tpc_oracle.cpp")
+SOURCES = [SRC, os.path.join(HERE, "tpc_refit.cpp")]
+HEADERS = [os.path.join(HERE, "kalman.h")]
 LIB = os.path.join(HERE, "libtpc_oracle.so")
 
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
@@ -29,7 +31,7 @@ CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fopenm
 
 def build(extra_flags=(), out=LIB):
     """Compile the oracle with g++ (strict IEEE, no FMA contraction)."""
-    cmd = ["g++", *CXXFLAGS, *extra_flags, SRC, "-o", out]
+    cmd = ["g++", *CXXFLAGS, *extra_flags, *SOURCES, "-o", out]
     subprocess.run(cmd, check=True)
     return out
 
@@ -40,7 +42,7 @@ class OrcParams(ctypes.Structure):
                 ("u_max", ctypes.c_float), ("sigma_y", ctypes.c_float),
                 ("sigma_z", ctypes.c_float), ("cww0", ctypes.c_float), ("bz", ctypes.c_float),
                 ("min_hits", ctypes.c_int32), ("max_misses", ctypes.c_int32),
-                ("brute", ctypes.c_int32)]
+                ("descent_rows", ctypes.c_int32), ("brute", ctypes.c_int32)]
 
 
 @dataclass
@@ -58,11 +60,12 @@ class Params:
     bz: float = 0.5
     min_hits: int = 10
     max_misses: int = 8
+    descent_rows: int = 8
 
     def c_struct(self, brute=False):
         return OrcParams(self.win_y, self.win_z, self.d2_max, self.chi2_max, self.sinphi_max,
                          self.u_max, self.sigma_y, self.sigma_z, self.cww0, self.bz,
-                         self.min_hits, self.max_misses, 1 if brute else 0)
+                         self.min_hits, self.max_misses, self.descent_rows, 1 if brute else 0)
 
 
 _lib = None
@@ -71,7 +74,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+                os.path.getmtime(f) for f in SOURCES + HEADERS):
             build()
         L = ctypes.CDLL(LIB)
         P = ctypes.c_void_p
@@ -89,6 +93,12 @@ def lib():
         L.orc_propagate.argtypes = [ctypes.c_int, P, P, ctypes.c_double]
         L.orc_update.restype = ctypes.c_double
         L.orc_update.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double]
+        L.orc_map_ncoef.restype = ctypes.c_int
+        L.orc_map_eval.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.orc_map_basis.restype = ctypes.c_int
+        L.orc_map_basis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
+        L.orc_refit.argtypes = [P, P, ctypes.c_int64] + [P] * 11
+        L.orc_refit_grad.argtypes = [P, P, ctypes.c_int64] + [P] * 12
         _lib = L
     return _lib
 
@@ -208,3 +218,89 @@ def update(state, my, mz, params: Params | None = None, precision=64):
     ps = params.c_struct()
     ch = lib().orc_update(precision, ctypes.byref(ps), _p(st), float(my), float(mz))
     return st, ch
+
+
+# ---------------------------------------------------------------------------
+# refit through the distortion-correction map
+# ---------------------------------------------------------------------------
+def map_ncoef():
+    return int(lib().orc_map_ncoef())
+
+
+def map_eval(theta, r, phi, z):
+    """(delta r, delta r*phi, delta z) of the map at one point."""
+    out = np.zeros(3)
+    th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+    lib().orc_map_eval(_p(th) if th is not None else None, float(r), float(phi), float(z), _p(out))
+    return out
+
+
+def map_basis(r, phi, z):
+    """Non-zero basis terms at a point: (node indices [n,3] (phi, r, z), weights [n])."""
+    idx = np.zeros(3 * 64, np.int32)
+    w = np.zeros(64)
+    n = lib().orc_map_basis(float(r), float(phi), float(z), _p(idx), _p(w))
+    return idx[:3 * n].reshape(n, 3), w[:n]
+
+
+def _refit_args(cs, tk, params, row_x, unit_alpha):
+    from synth import geometry as G
+    params = params or Params()
+    xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
+    hb = np.ascontiguousarray(tk["hit_begin"], dtype=np.int64)
+    hits = np.ascontiguousarray(tk["hits"], dtype=np.int32)
+    rows = np.ascontiguousarray(tk["rows"], dtype=np.uint8)
+    unit = np.ascontiguousarray(tk["unit"], dtype=np.int32)
+    if unit_alpha is None:
+        unit_alpha = G.sector_alpha(cs.unit_sector)
+    ua = np.ascontiguousarray(unit_alpha, dtype=np.float32)
+    seed = np.ascontiguousarray(tk["param"], dtype=np.float32)
+    y = np.ascontiguousarray(cs.y, dtype=np.float32)
+    z = np.ascontiguousarray(cs.z, dtype=np.float32)
+    keep = [xr, hb, hits, rows, unit, ua, seed, y, z]
+    return params.c_struct(), keep
+
+
+def refit(cs, tk, theta=None, params: Params | None = None, row_x=None, unit_alpha=None):
+    """FP64 refit chi2 of every track in tk (hit lists sorted by row; seeds from
+    tk["param"]).  Returns (chi2 [n], ok [n])."""
+    ps, (xr, hb, hits, rows, unit, ua, seed, y, z) = _refit_args(cs, tk, params, row_x, unit_alpha)
+    n = len(hb) - 1
+    th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+    chi2 = np.zeros(n)
+    ok = np.zeros(n, np.int32)
+    lib().orc_refit(_p(xr), ctypes.byref(ps), n, _p(hb), _p(hits), _p(rows), _p(unit), _p(ua),
+                    _p(seed), _p(y), _p(z), _p(th) if th is not None else None, _p(chi2), _p(ok))
+    return chi2, ok.astype(bool)
+
+
+def refit_grad(cs, tk, theta=None, dL_dchi2=None, params: Params | None = None, row_x=None,
+               unit_alpha=None, hit_grad=False):
+    """FP64 gradient of sum(dL_dchi2 * chi2) with respect to the map
+    coefficients (and, optionally, to every corrected cluster coordinate)."""
+    ps, (xr, hb, hits, rows, unit, ua, seed, y, z) = _refit_args(cs, tk, params, row_x, unit_alpha)
+    n = len(hb) - 1
+    th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+    w = np.ones(n) if dL_dchi2 is None else np.ascontiguousarray(dL_dchi2, dtype=np.float64)
+    g = np.zeros(map_ncoef())
+    hgrad = np.zeros((int(hb[-1]), 3)) if hit_grad else None
+    lib().orc_refit_grad(_p(xr), ctypes.byref(ps), n, _p(hb), _p(hits), _p(rows), _p(unit), _p(ua),
+                         _p(seed), _p(y), _p(z), _p(th) if th is not None else None, _p(w), _p(g),
+                         _p(hgrad) if hit_grad else None)
+    return (g, hgrad) if hit_grad else g
+
+
+def select_tracks(tk, min_hits=20, index=None):
+    """Sub-list of tracklets (kept_tracklets layout) with at least min_hits
+    clusters, optionally restricted to the given positions."""
+    sel = np.nonzero(tk["n"] >= min_hits)[0]
+    if index is not None:
+        sel = sel[np.asarray(index)]
+    hb = tk["hit_begin"]
+    n = tk["n"][sel].astype(np.int64)
+    nb = np.zeros(len(sel) + 1, np.int64)
+    np.cumsum(n, out=nb[1:])
+    hits = np.concatenate([tk["hits"][hb[i]:hb[i + 1]] for i in sel]) if len(sel) else np.zeros(0, np.int32)
+    rows = np.concatenate([tk["rows"][hb[i]:hb[i + 1]] for i in sel]) if len(sel) else np.zeros(0, np.uint8)
+    return dict(index=sel, unit=tk["unit"][sel], n=tk["n"][sel], hit_begin=nb, hits=hits, rows=rows,
+                param=tk["param"][sel])

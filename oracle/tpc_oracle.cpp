@@ -38,156 +38,13 @@
 #include <omp.h>
 #endif
 
-extern "C" {
-struct OrcParams {
-  float win_y, win_z;      // neighbour-finder windows per row step [cm]
-  float d2_max;            // neighbour-finder cut on the chord deviation [cm^2]
-  float chi2_max;          // attachment cut (2 degrees of freedom)
-  float sinphi_max;        // propagation guard on |sin(phi)|
-  float u_max;             // propagation guard on |C| * chord / 2
-  float sigma_y, sigma_z;  // cluster errors [cm]
-  float cww0;              // seed variance of q/pT [(GeV/c)^-2]
-  float bz;                // field [T]
-  int32_t min_hits;        // tracklets with fewer hits are dropped
-  int32_t max_misses;      // consecutive rows without attachment that stop following
-  int32_t brute;           // 1: brute-force candidate scans
-};
-}
+#include "kalman.h"
 
 namespace {
 
+using namespace orc;
+
 constexpr int kFlagDescentFailed = 1;
-
-template <class T>
-struct Consts {
-  T kappa, sy2, sz2, wy, wz, d2max, chi2max, smax, umax, cww0;
-};
-
-template <class T>
-Consts<T> make_consts(const OrcParams& p) {
-  Consts<T> c;
-  // kappa = c[GeV/(T cm)] * Bz: the rate of change of sin(phi) per cm and per
-  // unit of q/pT.  Computed in double, then rounded once to T.
-  c.kappa = T(2.99792458e-3 * double(p.bz));
-  c.sy2 = T(p.sigma_y) * T(p.sigma_y);
-  c.sz2 = T(p.sigma_z) * T(p.sigma_z);
-  c.wy = T(p.win_y);
-  c.wz = T(p.win_z);
-  c.d2max = T(p.d2_max);
-  c.chi2max = T(p.chi2_max);
-  c.smax = T(p.sinphi_max);
-  c.umax = T(p.u_max);
-  c.cww0 = T(p.cww0);
-  return c;
-}
-
-// asin(u)/u: the ratio of arc length to chord for a chord of half-length u*R.
-inline float arc_over_chord(float u) {
-  const float a1 = float(1.0 / 6.0);
-  const float a2 = float(3.0 / 40.0);
-  float u2 = u * u;
-  return 1.0f + u2 * (a1 + u2 * a2);
-}
-inline double arc_over_chord(double u) { return u > 0.0 ? std::asin(u) / u : 1.0; }
-
-// Track state at the plane x: (y, z, s = sin(phi), t = dz/ds_xy, w = q/pT) and
-// the two diagonal blocks of the covariance, (y, s, w) and (z, t).
-template <class T>
-struct State {
-  T x, y, z, s, t, w;
-  T cyy, csy, css, cwy, cws, cww;
-  T czz, ctz, ctt;
-};
-
-// Propagate to the plane x1 along the circle of curvature -kappa*w.  Returns
-// false (state untouched) when |sin(phi)| would reach smax or the chord is too
-// long for the arc-length series.
-template <class T>
-bool propagate(State<T>& st, T x1, const Consts<T>& c) {
-  T dx = x1 - st.x;
-  T k = c.kappa * st.w;
-  T s1 = st.s - k * dx;
-  if (!(std::fabs(s1) < c.smax)) return false;
-  T c0 = std::sqrt(T(1) - st.s * st.s);
-  T c1 = std::sqrt(T(1) - s1 * s1);
-  T cc = c0 + c1;
-  T ss = st.s + s1;
-  T tg = ss / cc;
-  T dy = dx * tg;
-  T dl = std::sqrt(dx * dx + dy * dy);
-  T u = (std::fabs(k) * dl) * T(0.5);
-  if (!(u <= c.umax)) return false;
-  T dS = dl * arc_over_chord(u);
-  if (dx < T(0)) dS = -dS;
-  // Jacobian of (y, s) with respect to (s, w); z couples to t only.
-  T r0 = st.s / c0;
-  T r1 = s1 / c1;
-  T cc2 = cc * cc;
-  T a = dx * ((T(2) * cc + ss * (r0 + r1)) / cc2);
-  T e = -(c.kappa * dx);
-  T b = (dx * e) * ((cc + ss * r1) / cc2);
-  // C' = J C J^T, y-block
-  T Py = (st.cyy + a * st.csy) + b * st.cwy;
-  T Ps = (st.csy + a * st.css) + b * st.cws;
-  T Pw = (st.cwy + a * st.cws) + b * st.cww;
-  T Qy = st.csy + e * st.cwy;
-  T Qs = st.css + e * st.cws;
-  T Qw = st.cws + e * st.cww;
-  st.cyy = (Py + a * Ps) + b * Pw;
-  st.csy = (Qy + a * Qs) + b * Qw;
-  st.cwy = Pw;
-  st.css = Qs + e * Qw;
-  st.cws = Qw;
-  // z-block
-  T Rz = st.czz + dS * st.ctz;
-  T Rt = st.ctz + dS * st.ctt;
-  st.czz = Rz + dS * Rt;
-  st.ctz = Rt;
-  // state
-  st.y = st.y + dy;
-  st.z = st.z + st.t * dS;
-  st.s = s1;
-  st.x = x1;
-  return true;
-}
-
-template <class T>
-T chi2_of(const State<T>& st, T my, T mz, const Consts<T>& c) {
-  T ry = my - st.y;
-  T rz = mz - st.z;
-  T Sy = st.cyy + c.sy2;
-  T Sz = st.czz + c.sz2;
-  return (ry * ry) / Sy + (rz * rz) / Sz;
-}
-
-// Kalman update with the cluster (my, mz); returns the cluster's chi2.
-template <class T>
-T update(State<T>& st, T my, T mz, const Consts<T>& c) {
-  T ry = my - st.y;
-  T rz = mz - st.z;
-  T Sy = st.cyy + c.sy2;
-  T Sz = st.czz + c.sz2;
-  T chi2 = (ry * ry) / Sy + (rz * rz) / Sz;
-  T k0 = st.cyy / Sy, k1 = st.csy / Sy, k2 = st.cwy / Sy;
-  st.y = st.y + k0 * ry;
-  st.s = st.s + k1 * ry;
-  st.w = st.w + k2 * ry;
-  T cyy = st.cyy, csy = st.csy, cwy = st.cwy;
-  st.cyy = cyy - k0 * cyy;
-  st.csy = csy - k1 * cyy;
-  st.cwy = cwy - k2 * cyy;
-  st.css = st.css - k1 * csy;
-  st.cws = st.cws - k2 * csy;
-  st.cww = st.cww - k2 * cwy;
-  T kz0 = st.czz / Sz, kz1 = st.ctz / Sz;
-  st.z = st.z + kz0 * rz;
-  st.t = st.t + kz1 * rz;
-  T czz = st.czz, ctz = st.ctz;
-  st.czz = czz - kz0 * czz;
-  st.ctz = ctz - kz1 * czz;
-  st.ctt = st.ctt - kz1 * ctz;
-  return chi2;
-}
 
 // ---------------------------------------------------------------------------
 // one unit (sector): rows with their clusters, and a z-sorted index per row
@@ -340,9 +197,24 @@ struct Searcher {
   }
 };
 
+// Propagate from row `from` down to row `to` (< from) in steps of at most
+// `step` rows.  False if a step fails.
+template <class T>
+bool descend(State<T>& st, const std::vector<T>& xr, int from, int to, int step, const Consts<T>& c,
+             int64_t* n_prop) {
+  for (int rr = from; rr > to;) {
+    const int next = std::max(to, rr - step);
+    ++*n_prop;
+    if (!propagate(st, xr[next], c)) return false;
+    rr = next;
+  }
+  return true;
+}
+
 template <class T>
 Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, const int32_t* cup,
-                      int64_t h0, int r0, bool brute, const Consts<T>& c, int max_misses) {
+                      int64_t h0, int r0, bool brute, const Consts<T>& c, int max_misses,
+                      int descent_rows) {
   const int R = un.n_rows;
   Tracklet<T> tk;
   tk.start = h0;
@@ -362,22 +234,23 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
   T dx = xr[r0 + 1] - xr[r0];
   T dy = T(un.y[c1]) - T(un.y[c0]);
   T dz = T(un.z[c1]) - T(un.z[c0]);
-  T dl = std::sqrt(dx * dx + dy * dy);
+  T idl = T(1) / std::sqrt(dx * dx + dy * dy);
+  T idl2 = idl * idl;
   st.x = xr[r0 + 1];
   st.y = T(un.y[c1]);
   st.z = T(un.z[c1]);
-  st.s = dy / dl;
-  st.t = dz / dl;
+  st.s = dy * idl;
+  st.t = dz * idl;
   st.w = T(0);
   st.cyy = c.sy2;
-  st.csy = c.sy2 / dl;
-  st.css = (c.sy2 + c.sy2) / (dl * dl);
+  st.csy = c.sy2 * idl;
+  st.css = (c.sy2 + c.sy2) * idl2;
   st.cwy = T(0);
   st.cws = T(0);
   st.cww = c.cww0;
   st.czz = c.sz2;
-  st.ctz = c.sz2 / dl;
-  st.ctt = (c.sz2 + c.sz2) / (dl * dl);
+  st.ctz = c.sz2 * idl;
+  st.ctt = (c.sz2 + c.sz2) * idl2;
   T chi2 = T(0);
   int n = 2;
   att.push_back({r0, int32_t(c0)});
@@ -423,16 +296,10 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
     }
   }
 
-  // back to the start row, then following inwards
+  // back to the start row (no search, steps of at most descent_rows rows),
+  // then following inwards
   st = best;
-  bool down_ok = true;
-  for (int rr = best_row - 1; rr >= r0; --rr) {
-    ++tk.n_prop;
-    if (!propagate(st, xr[rr], c)) {
-      down_ok = false;
-      break;
-    }
-  }
+  bool down_ok = descend(st, xr, best_row, r0, descent_rows, c, &tk.n_prop);
   State<T> out = best;
   int out_row = best_row;
   if (!down_ok) {
@@ -477,8 +344,8 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
 // Returns false when a propagation fails where the decisions say it did not.
 template <class T>
 bool replay(const std::vector<T>& xr, const float* y, const float* z, const int32_t* hits,
-            const uint8_t* rows, int n, int r0, int flags, const Consts<T>& c, State<T>* out_st,
-            int* out_row, T* out_chi2) {
+            const uint8_t* rows, int n, int r0, int flags, int descent_rows, const Consts<T>& c,
+            State<T>* out_st, int* out_row, T* out_chi2) {
   int k0 = -1;  // first hit at or above r0
   for (int i = 0; i < n; ++i)
     if (rows[i] == r0) {
@@ -491,22 +358,23 @@ bool replay(const std::vector<T>& xr, const float* y, const float* z, const int3
   T dx = xr[r0 + 1] - xr[r0];
   T dy = T(y[c1]) - T(y[c0]);
   T dz = T(z[c1]) - T(z[c0]);
-  T dl = std::sqrt(dx * dx + dy * dy);
+  T idl = T(1) / std::sqrt(dx * dx + dy * dy);
+  T idl2 = idl * idl;
   st.x = xr[r0 + 1];
   st.y = T(y[c1]);
   st.z = T(z[c1]);
-  st.s = dy / dl;
-  st.t = dz / dl;
+  st.s = dy * idl;
+  st.t = dz * idl;
   st.w = T(0);
   st.cyy = c.sy2;
-  st.csy = c.sy2 / dl;
-  st.css = (c.sy2 + c.sy2) / (dl * dl);
+  st.csy = c.sy2 * idl;
+  st.css = (c.sy2 + c.sy2) * idl2;
   st.cwy = T(0);
   st.cws = T(0);
   st.cww = c.cww0;
   st.czz = c.sz2;
-  st.ctz = c.sz2 / dl;
-  st.ctt = (c.sz2 + c.sz2) / (dl * dl);
+  st.ctz = c.sz2 * idl;
+  st.ctt = (c.sz2 + c.sz2) * idl2;
   T chi2 = T(0);
   int row = r0 + 1;
   for (int i = k0 + 2; i < n; ++i) {
@@ -523,8 +391,8 @@ bool replay(const std::vector<T>& xr, const float* y, const float* z, const int3
     *out_chi2 = chi2;
     return k0 == 0;
   }
-  for (int rr = best_row - 1; rr >= r0; --rr)
-    if (!propagate(st, xr[rr], c)) return false;
+  int64_t np = 0;
+  if (!descend(st, xr, best_row, r0, descent_rows, c, &np)) return false;
   row = r0;
   State<T> out = st;
   int orow = r0;
@@ -609,7 +477,7 @@ Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
     for (int64_t h : starts[k]) {
       int r0 = 0;
       while (!(h >= un.rb[r0] && h < un.rb[r0 + 1])) ++r0;
-      tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses));
+      tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses, p.descent_rows));
     }
   }
   int64_t np = 0, nprop = 0, nsearch = 0, nbox = 0, natt = 0, nchain = 0, ncand = 0;
@@ -747,7 +615,8 @@ void orc_replay(int precision, const float* row_x, int n_rows, const OrcParams* 
       T ch = T(0);
       int64_t b = hit_begin[i];
       int n = int(hit_begin[i + 1] - b);
-      bool good = replay<T>(xr, y, z, hits + b, rows + b, n, r0[i], flags[i], c, &st, &orow, &ch);
+      bool good = replay<T>(xr, y, z, hits + b, rows + b, n, r0[i], flags[i], p->descent_rows, c, &st,
+                             &orow, &ch);
       ok[i] = good ? 1 : 0;
       const double pv[5] = {double(st.y), double(st.z), double(st.s), double(st.t), double(st.w)};
       std::memcpy(param + 5 * i, pv, sizeof pv);

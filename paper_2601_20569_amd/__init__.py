@@ -35,12 +35,13 @@ class Params(ctypes.Structure):
                 ("chi2_max", ctypes.c_float), ("sinphi_max", ctypes.c_float),
                 ("u_max", ctypes.c_float), ("sigma_y", ctypes.c_float),
                 ("sigma_z", ctypes.c_float), ("cww0", ctypes.c_float),
-                ("min_hits", ctypes.c_int32), ("max_misses", ctypes.c_int32)]
+                ("min_hits", ctypes.c_int32), ("max_misses", ctypes.c_int32),
+                ("descent_rows", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_y", ctypes.c_float), ("n_zbins", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("construct_block", ctypes.c_int32), ("construct_grid", ctypes.c_int32)]
+                ("construct_grid", ctypes.c_int32)]
 
 
 class Clusters(ctypes.Structure):
@@ -55,6 +56,21 @@ class Tracks(ctypes.Structure):
                 ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p),
                 ("x_ref", ctypes.c_void_p), ("param", ctypes.c_void_p), ("cov", ctypes.c_void_p),
                 ("chi2", ctypes.c_void_p), ("ndf", ctypes.c_void_p)]
+
+
+class RefitInput(ctypes.Structure):
+    _fields_ = [("n_tracks", ctypes.c_int64), ("hit_begin", ctypes.c_void_p),
+                ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p),
+                ("unit", ctypes.c_void_p), ("seed", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("unit_alpha", ctypes.c_void_p)]
+
+
+MAP_NCOEF = 36720
+
+
+class BatchRefit(ctypes.Structure):
+    _fields_ = [("min_hits", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("unit_alpha", ctypes.c_void_p), ("chi2", ctypes.c_void_p), ("ok", ctypes.c_void_p)]
 
 
 class Debug(ctypes.Structure):
@@ -92,6 +108,19 @@ def lib():
         L.tpcx_poll.restype = ctypes.c_int32
         L.tpcx_strerror.argtypes = [ctypes.c_int32]
         L.tpcx_strerror.restype = ctypes.c_char_p
+        L.tpcx_refit_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.c_int64]
+        L.tpcx_refit_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_refit.argtypes = [P, ctypes.POINTER(RefitInput), P, P, P, P, ctypes.c_size_t, P]
+        L.tpcx_refit.restype = ctypes.c_int32
+        L.tpcx_refit_backward.argtypes = [P, ctypes.POINTER(RefitInput), P, P, P, ctypes.c_size_t, P]
+        L.tpcx_refit_backward.restype = ctypes.c_int32
+        L.tpcx_batched_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                   ctypes.c_int64, ctypes.c_int64]
+        L.tpcx_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_track_batched.argtypes = [P, ctypes.POINTER(Clusters), P, ctypes.c_size_t,
+                                         ctypes.c_int64, ctypes.POINTER(Tracks),
+                                         ctypes.POINTER(BatchRefit), P]
+        L.tpcx_track_batched.restype = ctypes.c_int32
         L.tpcx_timing_enable.argtypes = [P, ctypes.c_int32]
         L.tpcx_timing_enable.restype = ctypes.c_int32
         L.tpcx_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
@@ -125,11 +154,12 @@ class MethodParams:
     cww0: float = 100.0
     min_hits: int = 10
     max_misses: int = 8
+    descent_rows: int = 8
 
     def c_struct(self):
         return Params(self.win_y, self.win_z, self.d2_max, self.chi2_max, self.sinphi_max,
                       self.u_max, self.sigma_y, self.sigma_z, self.cww0, self.min_hits,
-                      self.max_misses)
+                      self.max_misses, self.descent_rows)
 
 
 def _ptr(t):
@@ -246,6 +276,54 @@ class SectorTracker:
         self._last = (tr, s)
         return tr
 
+    def allocate_batched(self, n_units, n_clusters, cap_start, cap_tracks, cap_hits, refit=True):
+        """Buffers for tpcx_track_batched: workspace (tracking + refit), outputs
+        and the refit results."""
+        import torch
+        bufs = self.allocate(n_units, n_clusters, cap_start, cap_tracks, cap_hits)
+        nb = int(lib().tpcx_batched_workspace_bytes(self._h, n_units, n_clusters, bufs["cap_start"],
+                                                    bufs["cap_tracks"], bufs["cap_hits"]))
+        dev = bufs["ws"].device
+        bufs["ws"] = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        bufs["ws_off"] = (-bufs["ws"].data_ptr()) % 256
+        bufs["ws_bytes"] = nb
+        if refit:
+            bufs["refit_chi2"] = torch.zeros(max(bufs["cap_tracks"], 1), dtype=torch.float32, device=dev)
+            bufs["refit_ok"] = torch.zeros(max(bufs["cap_tracks"], 1), dtype=torch.int32, device=dev)
+        return bufs
+
+    def track_batched_into(self, row_begin, y, z, n_units, bufs, stream, unit_alpha=None,
+                           theta=None, refit_min_hits=20):
+        """Enqueue tpcx_track_batched (graph captured on the first call with
+        these buffers, replayed afterwards).  ``stream`` must be a non-default
+        torch stream.  With ``unit_alpha`` the tracklets with at least
+        ``refit_min_hits`` clusters are refitted (results in bufs["refit_chi2"],
+        bufs["refit_ok"])."""
+        import torch
+        n = int(y.numel())
+        cl = Clusters(n_units, n, _ptr(row_begin), _ptr(y), _ptr(z))
+        o = bufs["out"]
+        tr = Tracks(bufs["cap_tracks"], bufs["cap_hits"], _ptr(o["counts"]), _ptr(o["unit"]),
+                    _ptr(o["start"]), _ptr(o["n_hits"]), _ptr(o["hit_begin"]), _ptr(o["hit_id"]),
+                    _ptr(o["hit_row"]), _ptr(o["x_ref"]), _ptr(o["param"]), _ptr(o["cov"]),
+                    _ptr(o["chi2"]), _ptr(o["ndf"]))
+        rf = None
+        if unit_alpha is not None:
+            if theta is not None and (theta.dtype != torch.float32 or theta.numel() != MAP_NCOEF):
+                raise TpcxError("theta must be float32 with 36720 coefficients")
+            rf = BatchRefit(int(refit_min_hits), _ptr(theta) if theta is not None else None,
+                            _ptr(unit_alpha), _ptr(bufs["refit_chi2"]), _ptr(bufs["refit_ok"]))
+            bufs["_refit_keep"] = (theta, unit_alpha)
+        if stream is None or stream.cuda_stream == 0:
+            raise TpcxError("the batched form needs a non-default stream (graph capture)")
+        ws = bufs["ws"]
+        st = lib().tpcx_track_batched(self._h, ctypes.byref(cl),
+                                      ctypes.c_void_p(ws.data_ptr() + bufs["ws_off"]), bufs["ws_bytes"],
+                                      bufs["cap_start"], ctypes.byref(tr),
+                                      ctypes.byref(rf) if rf is not None else None,
+                                      ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "tpcx_track_batched")
+
     def track(self, row_begin, y, z, n_units, debug=False, cap_start=None, cap_tracks=None,
               cap_hits=None):
         """Track and return device tensors cut to the produced sizes.  When a
@@ -282,3 +360,95 @@ class SectorTracker:
                 res[k] = dbg[k][:n]
             res["starts"] = dbg["starts"][:min(n_start, bufs["cap_start"])]
         return res
+
+
+class RefitJob:
+    """Refit of a fixed track list through the distortion-correction map.
+
+    Tensors (device): hit_begin int64 [n+1], hit_id int32, hit_row uint8,
+    unit int32 [n], seed float32 [n,5], y/z float32 (clusters), unit_alpha
+    float32 [n_units].  The workspace holds the corrected clusters and the
+    filter-state checkpoints between forward() and backward().
+    """
+
+    def __init__(self, tracker: "SectorTracker", hit_begin, hit_id, hit_row, unit, seed, y, z,
+                 unit_alpha):
+        import torch
+        self.tracker = tracker
+        self.t = dict(hit_begin=hit_begin, hit_id=hit_id, hit_row=hit_row, unit=unit, seed=seed,
+                      y=y, z=z, unit_alpha=unit_alpha)
+        for k, dt in (("hit_begin", torch.int64), ("hit_id", torch.int32), ("hit_row", torch.uint8),
+                      ("unit", torch.int32), ("seed", torch.float32), ("y", torch.float32),
+                      ("z", torch.float32), ("unit_alpha", torch.float32)):
+            v = self.t[k]
+            if v.dtype != dt or not v.is_cuda or not v.is_contiguous():
+                raise TpcxError(f"refit input {k} must be a contiguous device {dt} tensor")
+        self.n_tracks = int(hit_begin.numel()) - 1
+        self.n_hits = int(hit_id.numel())
+        self.c = RefitInput(self.n_tracks, _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(unit),
+                            _ptr(seed), _ptr(y), _ptr(z), _ptr(unit_alpha))
+        nb = int(lib().tpcx_refit_workspace_bytes(tracker._h, self.n_tracks, self.n_hits))
+        dev = hit_begin.device
+        self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        self.ws_off = (-self.ws.data_ptr()) % 256
+        self.ws_bytes = nb
+        self.chi2 = torch.zeros(max(self.n_tracks, 1), dtype=torch.float32, device=dev)
+        self.ok = torch.zeros(max(self.n_tracks, 1), dtype=torch.int32, device=dev)
+
+    def _ws(self):
+        return ctypes.c_void_p(self.ws.data_ptr() + self.ws_off)
+
+    def forward(self, theta=None, stream=None):
+        """chi2 per track (float32 [n]); ok flags in self.ok."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        th = None
+        if theta is not None:
+            if theta.dtype != torch.float32 or theta.numel() != MAP_NCOEF or not theta.is_cuda:
+                raise TpcxError("theta must be a float32 device tensor of 36720 coefficients")
+            th = theta.contiguous()
+        _check(lib().tpcx_refit(self.tracker._h, ctypes.byref(self.c), _ptr(th) if th is not None else None,
+                                _ptr(self.chi2), _ptr(self.ok), self._ws(), self.ws_bytes,
+                                ctypes.c_void_p(s.cuda_stream)), "tpcx_refit")
+        return self.chi2[:self.n_tracks]
+
+    def backward(self, dL_dchi2, stream=None):
+        """d(sum dL_dchi2 * chi2)/d theta (float32 [36720]) at the last forward's theta."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        g = dL_dchi2.to(torch.float32).contiguous()
+        out = torch.empty(MAP_NCOEF, dtype=torch.float32, device=g.device)
+        _check(lib().tpcx_refit_backward(self.tracker._h, ctypes.byref(self.c), _ptr(g), _ptr(out),
+                                         self._ws(), self.ws_bytes, ctypes.c_void_p(s.cuda_stream)),
+               "tpcx_refit_backward")
+        return out
+
+
+def _make_refit_chi2():
+    import torch
+
+    class RefitChi2(torch.autograd.Function):
+        """chi2 per track of the map-corrected refit; differentiable in theta.
+
+        forward(theta [36720] float32, job: RefitJob) -> chi2 [n_tracks]
+        backward uses the library's hand-written adjoint (tpcx_refit_backward).
+        """
+
+        @staticmethod
+        def forward(ctx, theta, job):
+            ctx.job = job
+            return job.forward(theta.detach()).clone()
+
+        @staticmethod
+        def backward(ctx, grad_chi2):
+            return ctx.job.backward(grad_chi2), None
+
+    return RefitChi2
+
+
+def refit_chi2(theta, job):
+    """Differentiable chi2 per track: RefitChi2.apply(theta, job)."""
+    global _RefitChi2
+    if "_RefitChi2" not in globals():
+        _RefitChi2 = _make_refit_chi2()
+    return _RefitChi2.apply(theta, job)

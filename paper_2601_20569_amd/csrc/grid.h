@@ -6,9 +6,13 @@
 // can accept, and every selection breaks ties by the caller's cluster index,
 // so results do not depend on binning or on the order inside a bin.
 //
+// Every later stage works on sorted positions.  A sorted cluster is one
+// 16-byte record (y, z, caller id, cleaned up-link), so a candidate test or a
+// chain step reads a single line.  A row keeps the same index range in both
+// orders.
+//
 // One block builds one row: z range (block reduction), histogram of bin keys
-// in LDS, block-wide scan, then a scatter through LDS cursors.  Rows are read
-// three times (the passes hit the last-level cache); no global atomics.
+// in LDS, block-wide scan, then a scatter through LDS cursors.
 #pragma once
 
 #include "tpcx_common.h"
@@ -52,8 +56,7 @@ __device__ __forceinline__ float block_reduce_max(float v, float* lds) {
 // Dynamic LDS: nz * ny + 1 int32 bin counters of the row.
 __global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float* __restrict__ y,
                              const float* __restrict__ z, Grid g, UnitZ* __restrict__ row_z,
-                             int32_t* __restrict__ bins, float* __restrict__ sy,
-                             float* __restrict__ sz, int32_t* __restrict__ sid) {
+                             int32_t* __restrict__ bins, float4* __restrict__ pts) {
   extern __shared__ int32_t hist[];
   __shared__ float red[1024 / kWave];
   __shared__ int64_t scan_lds[1024 / kWave];
@@ -118,9 +121,7 @@ __global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float*
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
     const float yy = y[i], zz = z[i];
     const int32_t pos = atomicAdd(&hist[key_of(yy, zz)], 1);
-    sy[pos] = yy;
-    sz[pos] = zz;
-    sid[pos] = int32_t(i);
+    pts[pos] = make_float4(yy, zz, __int_as_float(int32_t(i)), __int_as_float(-1));
   }
 }
 

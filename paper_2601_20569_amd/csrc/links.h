@@ -9,34 +9,38 @@
 namespace tpcx {
 
 // Neighbour finder.  One block per (unit, row); threads walk the row's
-// clusters in sorted order, so a wavefront works on neighbouring clusters and
-// its reads of rows r-1 and r+1 hit the caches.  For cluster h in row r
-// (1 <= r <= n_rows-2) every u in row r+1 and d in row r-1 within |dy| <= wy
-// and |dz| <= wz of h is considered; the deviation of h from the chord d-u at
-// row r is e = h - (d + (u - d) * f_r), D = ey^2 + ez^2.  The pair with the
-// smallest (D, id_u, id_d) among D <= d2max gives link_up/link_down (caller
-// ids), -1 if none.  f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.
-// The down candidates of a cluster are collected once in LDS (up to kNfD;
-// more fall back to re-reading them for every up candidate).
+// clusters in sorted order, so a wavefront works on neighbouring clusters, its
+// reads of rows r-1 and r+1 hit the caches and its link writes are coalesced.
+// For cluster h in row r (1 <= r <= n_rows-2) every u in row r+1 and d in row
+// r-1 within |dy| <= wy and |dz| <= wz of h is considered; the deviation of h
+// from the chord d-u at row r is e = h - (d + (u - d) * f_r), D = ey^2 + ez^2.
+// The pair with the smallest (D, id_u, id_d) (caller ids) among D <= d2max
+// gives the links (sorted positions), -1 if none.
+// f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.  The down candidates
+// of a cluster are collected once in LDS (up to kNfD; more fall back to
+// re-reading them for every up candidate).
 constexpr int kNfD = 8;
 constexpr int kNfBlock = 256;
 
+__device__ __forceinline__ int32_t id_of(const float4& p) { return __float_as_int(p.z); }
+__device__ __forceinline__ int32_t cup_of(const float4& p) { return __float_as_int(p.w); }
+
 __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restrict__ row_begin, Grid g,
                                                          const float* __restrict__ frac, DevParams p,
-                                                         int32_t* __restrict__ link_up,
-                                                         int32_t* __restrict__ link_down) {
+                                                         int32_t* __restrict__ up_s,
+                                                         int32_t* __restrict__ down_s) {
   __shared__ float dy_l[kNfD][kNfBlock];
   __shared__ float dz_l[kNfD][kNfBlock];
   __shared__ int32_t did_l[kNfD][kNfBlock];
+  __shared__ int32_t dpos_l[kNfD][kNfBlock];
   const int k = blockIdx.x;
   const int r = k % g.n_rows;
   const int64_t b = row_begin[k], e = row_begin[k + 1];
   const int t = threadIdx.x;
   if (r == 0 || r == g.n_rows - 1) {
     for (int64_t i = b + t; i < e; i += blockDim.x) {
-      const int32_t h = g.sid[i];
-      link_up[h] = -1;
-      link_down[h] = -1;
+      up_s[i] = -1;
+      down_s[i] = -1;
     }
     return;
   }
@@ -46,8 +50,8 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
   const int64_t bu = g.row_base(ku), bd = g.row_base(kd);
   const int nyu = g.rows[r + 1].ny, nyd = g.rows[r - 1].ny;
   for (int64_t i = b + t; i < e; i += blockDim.x) {
-    const int32_t h = g.sid[i];
-    const float yh = g.sy[i], zh = g.sz[i];
+    const float4 ph = g.pts[i];
+    const float yh = ph.x, zh = ph.y;
     const float pz = wz + box_pad(zh), py = wy + box_pad(yh);
     const int zu0 = g.zbin(ku, zh - pz), zu1 = g.zbin(ku, zh + pz);
     const int zd0 = g.zbin(kd, zh - pz), zd1 = g.zbin(kd, zh + pz);
@@ -59,26 +63,28 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
     for (int zb = zd0; zb <= zd1; ++zb) {
       const int32_t j0 = g.bin_start[bd + zb * nyd + yd0], j1 = g.bin_start[bd + zb * nyd + yd1 + 1];
       for (int32_t j = j0; j < j1; ++j) {
-        const float yd = g.sy[j], zd = g.sz[j];
-        if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
+        const float4 pd = g.pts[j];
+        if (!(fabsf(pd.x - yh) <= wy && fabsf(pd.y - zh) <= wz)) continue;
         if (nd < kNfD) {
-          dy_l[nd][t] = yd;
-          dz_l[nd][t] = zd;
-          did_l[nd][t] = g.sid[j];
+          dy_l[nd][t] = pd.x;
+          dz_l[nd][t] = pd.y;
+          did_l[nd][t] = id_of(pd);
+          dpos_l[nd][t] = j;
         }
         ++nd;
       }
     }
     float bestD = 0.0f;
-    int32_t best_u = -1, best_d = -1;
+    int32_t best_u = -1, best_d = -1, best_ju = -1, best_jd = -1;
     if (nd > 0) {
       for (int zb = zu0; zb <= zu1; ++zb) {
         const int32_t j0 = g.bin_start[bu + zb * nyu + yu0], j1 = g.bin_start[bu + zb * nyu + yu1 + 1];
         for (int32_t ju = j0; ju < j1; ++ju) {
-          const float yu = g.sy[ju], zu = g.sz[ju];
+          const float4 pu = g.pts[ju];
+          const float yu = pu.x, zu = pu.y;
           if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
-          const int32_t cu = g.sid[ju];
-          auto consider = [&](float yd, float zd, int32_t cd) {
+          const int32_t cu = id_of(pu);
+          auto consider = [&](float yd, float zd, int32_t cd, int32_t jd) {
             const float ey = yh - (yd + (yu - yd) * f);
             const float ez = zh - (zd + (zu - zd) * f);
             const float D = ey * ey + ez * ez;
@@ -87,63 +93,69 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
               bestD = D;
               best_u = cu;
               best_d = cd;
+              best_ju = ju;
+              best_jd = jd;
             }
           };
           if (nd <= kNfD) {
-            for (int q = 0; q < nd; ++q) consider(dy_l[q][t], dz_l[q][t], did_l[q][t]);
+            for (int q = 0; q < nd; ++q) consider(dy_l[q][t], dz_l[q][t], did_l[q][t], dpos_l[q][t]);
           } else {
             for (int zb2 = zd0; zb2 <= zd1; ++zb2) {
               const int32_t k0 = g.bin_start[bd + zb2 * nyd + yd0], k1 = g.bin_start[bd + zb2 * nyd + yd1 + 1];
               for (int32_t jd = k0; jd < k1; ++jd) {
-                const float yd = g.sy[jd], zd = g.sz[jd];
-                if (!(fabsf(yd - yh) <= wy && fabsf(zd - zh) <= wz)) continue;
-                consider(yd, zd, g.sid[jd]);
+                const float4 pd = g.pts[jd];
+                if (!(fabsf(pd.x - yh) <= wy && fabsf(pd.y - zh) <= wz)) continue;
+                consider(pd.x, pd.y, id_of(pd), jd);
               }
             }
           }
         }
       }
     }
-    link_up[h] = best_u;
-    link_down[h] = best_d;
+    up_s[i] = best_ju;
+    down_s[i] = best_jd;
   }
 }
 
-// Mutual-link cleaning and start-hit flags, one thread per cluster (caller
-// order).  A start hit has no cleaned down link, a cleaned up link u, and u has
-// a cleaned up link itself (chain of >= 3).  Writes per-block start counts.
-__global__ void k_clean_flags(int64_t n, const int32_t* __restrict__ up,
-                              const int32_t* __restrict__ down, int32_t* __restrict__ cup,
-                              int32_t* __restrict__ cdown, uint8_t* __restrict__ flag,
-                              int32_t* __restrict__ blk_cnt) {
+// Mutual-link cleaning and start-hit flags, one block per (unit, row), in
+// sorted positions.  The cleaned up-link goes into the cluster record.  A start
+// hit has no cleaned down link, a cleaned up link u, and u has a cleaned up
+// link itself (chain of >= 3).  Writes the row's number of start hits.
+__global__ void k_clean_starts(const int64_t* __restrict__ row_begin, const int32_t* __restrict__ up,
+                               const int32_t* __restrict__ down, float4* __restrict__ pts,
+                               int32_t* __restrict__ cdown, uint8_t* __restrict__ flag,
+                               int32_t* __restrict__ row_cnt) {
   __shared__ int32_t wcnt[1024 / kWave];
-  const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  bool st = false;
-  if (h < n) {
-    const int32_t u = up[h], d = down[h];
-    const int32_t cu = (u >= 0 && down[u] == h) ? u : -1;
-    const int32_t cd = (d >= 0 && up[d] == h) ? d : -1;
-    cup[h] = cu;
-    cdown[h] = cd;
+  const int k = blockIdx.x;
+  const int64_t b = row_begin[k], e = row_begin[k + 1];
+  int32_t cnt = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const int32_t u = up[i], d = down[i];
+    const int32_t cu = (u >= 0 && down[u] == i) ? u : -1;
+    const int32_t cd = (d >= 0 && up[d] == i) ? d : -1;
+    pts[i].w = __int_as_float(cu);
+    cdown[i] = cd;
+    bool st = false;
     if (cd < 0 && cu >= 0) {
       const int32_t uu = up[cu];
       st = uu >= 0 && down[uu] == cu;
     }
-    flag[h] = st ? 1 : 0;
+    flag[i] = st ? 1 : 0;
+    cnt += st ? 1 : 0;
   }
-  const uint64_t m = __ballot(st);
+  for (int d = kWave / 2; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, kWave);
   const int wid = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
-  if (lane_id() == 0) wcnt[wid] = __popcll(m);
+  if (lane_id() == 0) wcnt[wid] = cnt;
   __syncthreads();
   if (threadIdx.x == 0) {
     int32_t s = 0;
     for (int w = 0; w < nw; ++w) s += wcnt[w];
-    blk_cnt[blockIdx.x] = s;
+    row_cnt[k] = s;
   }
 }
 
-// Exclusive scan of per-block counts (one block).  total -> *total_out, and
-// the status bit when it exceeds cap.
+// Exclusive scan of per-row (or per-block) counts in one block.  total ->
+// *total_out, and the status bit when it exceeds cap.
 __global__ void k_scan_counts(const int32_t* __restrict__ cnt, int64_t nb, int32_t* __restrict__ off,
                               int64_t* __restrict__ total_out, int64_t cap,
                               int64_t* __restrict__ status, int64_t status_bit) {
@@ -163,24 +175,78 @@ __global__ void k_scan_counts(const int32_t* __restrict__ cnt, int64_t nb, int32
   }
 }
 
-// Ordered compaction of the start flags: block offsets + wave ballot ranks.
-__global__ void k_write_starts(int64_t n, const uint8_t* __restrict__ flag,
-                               const int32_t* __restrict__ blk_off, int64_t cap,
-                               int32_t* __restrict__ starts) {
-  __shared__ int32_t wcnt[1024 / kWave];
-  const int64_t h = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const bool st = h < n && flag[h] != 0;
-  const uint64_t m = __ballot(st);
-  const int wid = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
-  if (lane_id() == 0) wcnt[wid] = __popcll(m);
-  __syncthreads();
-  int32_t woff = 0;
-  for (int w = 0; w < wid; ++w) woff += wcnt[w];
-  (void)nw;
-  if (st) {
-    int64_t pos = int64_t(blk_off[blockIdx.x]) + woff + __popcll(m & lanes_below());
-    if (pos < cap) starts[pos] = int32_t(h);
+// Start hits of one row in ascending caller id: the row's flagged clusters
+// mark their caller id in an LDS bitmap over the row's id range, and each one's
+// rank is the number of marked ids below it.  Ranges longer than the bitmap
+// are done in segments.
+constexpr int kSegBits = 65536;
+constexpr int kSegWords = kSegBits / 32;
+
+__global__ void k_write_starts(const int64_t* __restrict__ row_begin, const float4* __restrict__ pts,
+                               const uint8_t* __restrict__ flag, const int32_t* __restrict__ row_off,
+                               int64_t cap, int32_t* __restrict__ starts,
+                               int32_t* __restrict__ start_pos, int32_t* __restrict__ start_k) {
+  __shared__ uint32_t bits[kSegWords];
+  __shared__ int32_t wpre[kSegWords];
+  __shared__ int64_t scan_lds[1024 / kWave];
+  const int k = blockIdx.x;
+  const int64_t b = row_begin[k], e = row_begin[k + 1];
+  int64_t seg_base = row_off[k];
+  for (int64_t lo = b; lo < e; lo += kSegBits) {
+    const int64_t hi = min(e, lo + kSegBits);
+    const int nw = int((hi - lo + 31) / 32);
+    for (int w = threadIdx.x; w < nw; w += blockDim.x) bits[w] = 0u;
+    __syncthreads();
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      if (!flag[i]) continue;
+      const int64_t h = id_of(pts[i]);
+      if (h < lo || h >= hi) continue;
+      atomicOr(&bits[(h - lo) >> 5], 1u << ((h - lo) & 31));
+    }
+    __syncthreads();
+    const int per = (nw + blockDim.x - 1) / blockDim.x;
+    const int w0 = min(nw, int(threadIdx.x) * per), w1 = min(nw, w0 + per);
+    int64_t c = 0;
+    for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
+    int64_t tot;
+    int64_t run = block_exclusive_scan(c, scan_lds, &tot);
+    for (int w = w0; w < w1; ++w) {
+      wpre[w] = int32_t(run);
+      run += __popc(bits[w]);
+    }
+    __syncthreads();
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      if (!flag[i]) continue;
+      const int64_t h = id_of(pts[i]);
+      if (h < lo || h >= hi) continue;
+      const int64_t o = h - lo;
+      const int64_t pos = seg_base + wpre[o >> 5] + __popc(bits[o >> 5] & ((1u << (o & 31)) - 1u));
+      if (pos < cap) {
+        starts[pos] = int32_t(h);
+        start_pos[pos] = int32_t(i);
+        start_k[pos] = k;
+      }
+    }
+    seg_base += tot;
+    __syncthreads();
   }
+}
+
+// Debug view of the links in caller ids, at the caller's cluster positions.
+__global__ void k_links_to_caller(int64_t n, const float4* __restrict__ pts,
+                                  const int32_t* __restrict__ up, const int32_t* __restrict__ down,
+                                  const int32_t* __restrict__ cdown, int32_t* __restrict__ link_up,
+                                  int32_t* __restrict__ link_down, int32_t* __restrict__ clean_up,
+                                  int32_t* __restrict__ clean_down) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 p = pts[i];
+  const int32_t h = id_of(p);
+  auto id = [&](int32_t j) { return j >= 0 ? id_of(pts[j]) : -1; };
+  if (link_up) link_up[h] = id(up[i]);
+  if (link_down) link_down[h] = id(down[i]);
+  if (clean_up) clean_up[h] = id(cup_of(p));
+  if (clean_down) clean_down[h] = id(cdown[i]);
 }
 
 }  // namespace tpcx

@@ -1,0 +1,683 @@
+// Track refit through a space-charge-distortion correction map, and its
+// hand-written adjoint.
+//
+// The paper names the space-charge-distortion correction maps as a main source
+// of track-quality problems (Abstract, Section 2) and describes the track fit
+// as a Kalman filter over the attached clusters (Section 2).  Here a map is a
+// tensor-product uniform cubic B-spline (36 phi x 17 r x 20 z nodes, three
+// components: delta r, delta r*phi, delta z); a cluster measured at (x, y, z)
+// in its sector frame (radius r, global azimuth phi) moves by delta r along
+// (x, y)/r, by delta r*phi along (-y, x)/r and by delta z along z.  The refit
+// runs outwards from the innermost cluster: y, z from that cluster, sin(phi),
+// dz/ds, q/pT from the tracking result, covariance diag(sy^2, sz^2, 1e-2, 1e-2,
+// 1); it propagates to every further cluster's own corrected x and updates,
+// without rejection.  chi2 of a track = sum of the updates' chi2.
+//
+// The backward pass gives d(sum_t dL/dchi2_t * chi2_t)/d(map coefficients).
+// The forward stores the filter state every kCkpt clusters; the backward
+// recomputes one segment at a time from its checkpoint into a per-lane scratch
+// area and runs the reverse sweep of every step (update, then propagation).
+// Coefficient gradients are summed in 64-bit fixed point (2^-32), so the sum
+// does not depend on the order of the additions: first in an LDS window of
+// phi nodes around the block's tracks, then into global memory.
+#pragma once
+
+#include "tpcx_common.h"
+#include "tracklet.h"
+
+namespace tpcx {
+
+constexpr int kMapNPhi = 36, kMapNR = 17, kMapNZ = 20, kMapComp = 3;
+constexpr int kMapNCoef = kMapComp * kMapNPhi * kMapNR * kMapNZ;
+constexpr float kMapDPhi = 6.28318530717958647692f / kMapNPhi;
+constexpr float kMapR0 = 85.0f, kMapDR = 10.0f;
+constexpr float kMapZ0 = -250.0f, kMapDZ = 500.0f / 19.0f;
+constexpr int kCkpt = 16;            // clusters per checkpoint segment
+constexpr int kCkptFloats = 16;      // 15 state numbers + padding
+constexpr int kRefitBlock = 256;
+constexpr int kWinPhi = 8;           // phi nodes held in the LDS accumulation window
+constexpr double kFixScale = 4294967296.0;  // 2^32
+
+__device__ __forceinline__ float bspline3(float t) {
+  const float a = fabsf(t);
+  if (a < 1.0f) return (4.0f - 6.0f * a * a + 3.0f * a * a * a) * (1.0f / 6.0f);
+  if (a < 2.0f) {
+    const float b = 2.0f - a;
+    return b * b * b * (1.0f / 6.0f);
+  }
+  return 0.0f;
+}
+
+__device__ __forceinline__ int map_index(int comp, int i, int j, int k) {
+  return ((comp * kMapNPhi + i) * kMapNR + j) * kMapNZ + k;
+}
+
+// 1-D weights of the four nodes around a coordinate; node index of the first.
+struct Weights4 {
+  int first;
+  float w[4];
+};
+
+__device__ __forceinline__ Weights4 weights_phi(float phi) {
+  float ph = fmodf(phi, 6.28318530717958647692f);
+  if (ph < 0.0f) ph += 6.28318530717958647692f;
+  const float u = ph / kMapDPhi;
+  const int i0 = int(floorf(u));
+  Weights4 W;
+  W.first = i0 - 1;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) W.w[a] = bspline3(u - float(i0 - 1 + a));
+  return W;
+}
+
+__device__ __forceinline__ Weights4 weights_lin(float x, float x0, float dx, int n) {
+  const float u = (x - x0) / dx;
+  const int i0 = int(floorf(u));
+  Weights4 W;
+  W.first = i0 - 1;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 - 1 + a;
+    W.w[a] = (i >= 0 && i < n) ? bspline3(u - float(i)) : 0.0f;
+  }
+  return W;
+}
+
+// Corrected position of a measured cluster.
+struct HitGeom {
+  float xm, ym, zm, inv_r, phi;
+};
+
+__device__ __forceinline__ void map_correct(const float* __restrict__ theta, const HitGeom& h,
+                                            float r, float* xc, float* yc, float* zc) {
+  float d[3] = {0.0f, 0.0f, 0.0f};
+  if (theta) {
+    const Weights4 wp = weights_phi(h.phi);
+    const Weights4 wr = weights_lin(r, kMapR0, kMapDR, kMapNR);
+    const Weights4 wz = weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ);
+    for (int a = 0; a < 4; ++a) {
+      const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
+      for (int b = 0; b < 4; ++b) {
+        const float wab = wp.w[a] * wr.w[b];
+        if (wab == 0.0f) continue;
+        const int j = wr.first + b;
+        for (int c = 0; c < 4; ++c) {
+          const float w = wab * wz.w[c];
+          if (w == 0.0f) continue;
+          const int k = wz.first + c;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) d[q] += theta[map_index(q, i, j, k)] * w;
+        }
+      }
+    }
+  }
+  *xc = h.xm + (d[0] * h.xm - d[1] * h.ym) * h.inv_r;
+  *yc = h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r;
+  *zc = h.zm + d[2];
+}
+
+struct RefitIn {
+  int64_t n_tracks;            // capacity of the track arrays
+  const int64_t* n_tracks_dev; // if set: the track count is min(n_tracks, *n_tracks_dev)
+  const int64_t* status_dev;   // if set and non-zero: nothing is refitted
+  const int32_t* n_hit;        // if set: clusters per track; else hit_begin[t + 1] - hit_begin[t]
+  int32_t min_hits;            // tracks with fewer clusters are not refitted (ok = 0)
+  const int64_t* hit_begin;
+  const int32_t* hit_id;
+  const uint8_t* hit_row;
+  const int32_t* unit;
+  const float* seed;  // [n][5]
+  const float* y;
+  const float* z;
+  const float* unit_alpha;
+  const float* row_x;
+};
+
+struct RefitWs {
+  float* xyz;       // [n_hits][4] corrected x, y, z (+pad) from the forward pass
+  float* ckpt;      // checkpoints, kCkptFloats each
+  float* scratch;   // [lanes][kCkpt][kCkptFloats] states of the segment in the backward
+  int64_t* acc;     // [kMapNCoef] fixed-point gradient accumulators
+  int64_t n_lanes;
+};
+
+__device__ __forceinline__ int64_t ckpt_base(const RefitIn& in, int64_t t) {
+  return in.hit_begin[t] / kCkpt + t;
+}
+
+__device__ __forceinline__ int64_t refit_count(const RefitIn& in) {
+  if (in.status_dev && *in.status_dev != 0) return 0;
+  if (!in.n_tracks_dev) return in.n_tracks;
+  const int64_t n = *in.n_tracks_dev;
+  return n < in.n_tracks ? n : in.n_tracks;
+}
+
+__device__ __forceinline__ int track_size(const RefitIn& in, int64_t t) {
+  return in.n_hit ? in.n_hit[t] : int(in.hit_begin[t + 1] - in.hit_begin[t]);
+}
+
+__device__ __forceinline__ void seed_state(KState& q, float xc, float yc, float zc, const float* sd,
+                                           const DevParams& p) {
+  q.x = xc;
+  q.y = yc;
+  q.z = zc;
+  q.s = sd[2];
+  q.t = sd[3];
+  q.w = sd[4];
+  q.cyy = p.sy2;
+  q.csy = 0.0f;
+  q.css = 1e-2f;
+  q.cwy = 0.0f;
+  q.cws = 0.0f;
+  q.cww = 1.0f;
+  q.czz = p.sz2;
+  q.ctz = 0.0f;
+  q.ctt = 1e-2f;
+}
+
+__device__ __forceinline__ void store_state(float* dst, const KState& q) {
+  float4* d = reinterpret_cast<float4*>(dst);
+  d[0] = make_float4(q.x, q.y, q.z, q.s);
+  d[1] = make_float4(q.t, q.w, q.cyy, q.csy);
+  d[2] = make_float4(q.css, q.cwy, q.cws, q.cww);
+  d[3] = make_float4(q.czz, q.ctz, q.ctt, 0.0f);
+}
+
+__device__ __forceinline__ KState load_state(const float* src) {
+  const float4* s = reinterpret_cast<const float4*>(src);
+  const float4 a = s[0], b = s[1], c = s[2], d = s[3];
+  KState q;
+  q.x = a.x; q.y = a.y; q.z = a.z; q.s = a.w;
+  q.t = b.x; q.w = b.y; q.cyy = b.z; q.csy = b.w;
+  q.css = c.x; q.cwy = c.y; q.cws = c.z; q.cww = c.w;
+  q.czz = d.x; q.ctz = d.y; q.ctt = d.z;
+  return q;
+}
+
+// One refit step: propagate to the cluster's x, update with its (y, z).
+__device__ __forceinline__ bool refit_step(KState& q, float xc, float yc, float zc,
+                                           const DevParams& p, float* chi2) {
+  float cp = 0.0f, rp = 0.0f;
+  bool cached = false;
+  if (!kf_propagate(q, xc, p, cp, rp, cached)) return false;
+  const float iSy = 1.0f / (q.cyy + p.sy2);
+  const float iSz = 1.0f / (q.czz + p.sz2);
+  *chi2 = *chi2 + kf_update(q, yc, zc, iSy, iSz);
+  return true;
+}
+
+// Forward refit: one lane per track, grid-stride over the tracks.  Corrected
+// clusters and checkpoints go to the workspace for the backward pass.
+__device__ void refit_track_fwd(const RefitIn& in, int64_t t, const float* __restrict__ theta,
+                                const DevParams& p, const RefitWs& ws, float* __restrict__ chi2_out,
+                                int32_t* __restrict__ ok_out) {
+  const int n = track_size(in, t);
+  if (n < in.min_hits) {
+    chi2_out[t] = 0.0f;
+    ok_out[t] = 0;
+    return;
+  }
+  const int64_t hb = in.hit_begin[t], he = hb + n;
+  const float alpha = in.unit_alpha[in.unit[t]];
+  for (int64_t q = hb; q < he; ++q) {
+    HitGeom h;
+    h.xm = in.row_x[in.hit_row[q]];
+    h.ym = in.y[in.hit_id[q]];
+    h.zm = in.z[in.hit_id[q]];
+    const float r = sqrtf(h.xm * h.xm + h.ym * h.ym);
+    h.inv_r = 1.0f / r;
+    h.phi = alpha + atan2f(h.ym, h.xm);
+    float xc, yc, zc;
+    map_correct(theta, h, r, &xc, &yc, &zc);
+    reinterpret_cast<float4*>(ws.xyz)[q] = make_float4(xc, yc, zc, 0.0f);
+  }
+  bool ok = n >= 2;
+  float chi2 = 0.0f;
+  if (ok) {
+    const float4 h0 = reinterpret_cast<const float4*>(ws.xyz)[hb];
+    KState q;
+    seed_state(q, h0.x, h0.y, h0.z, in.seed + 5 * t, p);
+    const int64_t cb = ckpt_base(in, t);
+    store_state(ws.ckpt + cb * kCkptFloats, q);
+    for (int i = 1; i < n && ok; ++i) {
+      const float4 h = reinterpret_cast<const float4*>(ws.xyz)[hb + i];
+      ok = refit_step(q, h.x, h.y, h.z, p, &chi2);
+      if (ok && i % kCkpt == 0) store_state(ws.ckpt + (cb + i / kCkpt) * kCkptFloats, q);
+    }
+  }
+  chi2_out[t] = ok ? chi2 : 0.0f;
+  ok_out[t] = ok ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kRefitBlock) k_refit_fwd(RefitIn in, const float* __restrict__ theta,
+                                                           DevParams p, RefitWs ws,
+                                                           float* __restrict__ chi2_out,
+                                                           int32_t* __restrict__ ok_out) {
+  const int64_t n = refit_count(in);
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x)
+    refit_track_fwd(in, t, theta, p, ws, chi2_out, ok_out);
+}
+
+// Adjoint of the filter state (same layout as KState).
+struct KBar {
+  float x, y, z, s, t, w;
+  float cyy, csy, css, cwy, cws, cww;
+  float czz, ctz, ctt;
+};
+
+// Reverse of one refit step.  `q` is the state before the step; `g` holds the
+// adjoint of the state after it and becomes the adjoint of the state before
+// it; gchi2 is the adjoint of the step's chi2; returns the adjoints of the
+// cluster's corrected (x, y, z).  The forward arithmetic is recomputed here.
+__device__ void refit_step_reverse(const KState& q, float x1, float my, float mz, const DevParams& p,
+                                   float gchi2, KBar& g, float* gx1, float* gmy, float* gmz) {
+  // ---------------- forward: propagation
+  const float dx = x1 - q.x;
+  const float k = p.kappa * q.w;
+  const float kd = k * dx;
+  const float s1 = q.s - kd;
+  const float c0 = sqrtf(1.0f - q.s * q.s);
+  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float cc = c0 + c1;
+  const float ss = q.s + s1;
+  const float icc = 1.0f / cc;
+  const float tg = ss * icc;
+  const float dy = dx * tg;
+  const float dl = sqrtf(dx * dx + dy * dy);
+  const float ak = fabsf(k);
+  const float u = (ak * dl) * 0.5f;
+  const float a1c = 0.16666667f, a2c = 0.075f;
+  const float u2 = u * u;
+  const float A = 1.0f + u2 * (a1c + u2 * a2c);
+  const float sgn = dx < 0.0f ? -1.0f : 1.0f;
+  const float dS = sgn * (dl * A);
+  const float r0 = q.s / c0;
+  const float r1 = s1 / c1;
+  const float icc2 = icc * icc;
+  const float na = 2.0f * cc + ss * (r0 + r1);
+  const float qa = na * icc2;
+  const float a = dx * qa;
+  const float e = -(p.kappa * dx);
+  const float nb = cc + ss * r1;
+  const float qb = nb * icc2;
+  const float de = dx * e;
+  const float b = de * qb;
+  const float Py = (q.cyy + a * q.csy) + b * q.cwy;
+  const float Ps = (q.csy + a * q.css) + b * q.cws;
+  const float Pw = (q.cwy + a * q.cws) + b * q.cww;
+  const float Qy = q.csy + e * q.cwy;
+  const float Qs = q.css + e * q.cws;
+  const float Qw = q.cws + e * q.cww;
+  const float Rz = q.czz + dS * q.ctz;
+  const float Rt = q.ctz + dS * q.ctt;
+  // state after the propagation (input of the update)
+  const float py = q.y + dy, pz = q.z + q.t * dS, ps = s1, pt = q.t, pw = q.w;
+  const float pyy = (Py + a * Ps) + b * Pw, psy = (Qy + a * Qs) + b * Qw, pwy = Pw;
+  const float pss = Qs + e * Qw, pws = Qw, pww = q.cww;
+  const float pzz = Rz + dS * Rt, ptz = Rt, ptt = q.ctt;
+  // ---------------- forward: update
+  const float ry = my - py, rz = mz - pz;
+  const float iSy = 1.0f / (pyy + p.sy2), iSz = 1.0f / (pzz + p.sz2);
+  const float k0 = pyy * iSy, k1 = psy * iSy, k2 = pwy * iSy;
+  const float kz0 = pzz * iSz, kz1 = ptz * iSz;
+
+  // ---------------- reverse: update
+  float gy = g.y, gs = g.s, gw = g.w, gz = g.z, gt = g.t, gx = g.x;
+  float gyy = 0.0f, gsy = 0.0f, gwy = 0.0f, gss = g.css, gws = 0.0f, gww = g.cww;
+  float gzz = 0.0f, gtz = 0.0f, gtt = g.ctt;
+  float gk0 = 0.0f, gk1 = 0.0f, gk2 = 0.0f, gkz0 = 0.0f, gkz1 = 0.0f, gry = 0.0f, grz = 0.0f;
+  float giSy = 0.0f, giSz = 0.0f;
+  // ctt' = ctt - kz1*ctz ; ctz' = ctz - kz1*czz ; czz' = czz - kz0*czz
+  gkz1 += -g.ctt * ptz;
+  gtz += -g.ctt * kz1;
+  gtz += g.ctz;
+  gkz1 += -g.ctz * pzz;
+  gzz += -g.ctz * kz1;
+  gzz += g.czz * (1.0f - kz0);
+  gkz0 += -g.czz * pzz;
+  // t' = t + kz1*rz ; z' = z + kz0*rz
+  gkz1 += g.t * rz;
+  grz += g.t * kz1;
+  gkz0 += g.z * rz;
+  grz += g.z * kz0;
+  // kz1 = ctz*iSz ; kz0 = czz*iSz
+  gtz += gkz1 * iSz;
+  giSz += gkz1 * ptz;
+  gzz += gkz0 * iSz;
+  giSz += gkz0 * pzz;
+  // cww' = cww - k2*cwy ; cws' = cws - k2*csy ; css' = css - k1*csy
+  gk2 += -g.cww * pwy;
+  gwy += -g.cww * k2;
+  gws += g.cws;
+  gk2 += -g.cws * psy;
+  gsy += -g.cws * k2;
+  gk1 += -g.css * psy;
+  gsy += -g.css * k1;
+  // cwy' = cwy - k2*cyy ; csy' = csy - k1*cyy ; cyy' = cyy - k0*cyy
+  gwy += g.cwy;
+  gk2 += -g.cwy * pyy;
+  gyy += -g.cwy * k2;
+  gsy += g.csy;
+  gk1 += -g.csy * pyy;
+  gyy += -g.csy * k1;
+  gyy += g.cyy * (1.0f - k0);
+  gk0 += -g.cyy * pyy;
+  // w' = w + k2*ry ; s' = s + k1*ry ; y' = y + k0*ry
+  gk2 += g.w * ry;
+  gry += g.w * k2;
+  gk1 += g.s * ry;
+  gry += g.s * k1;
+  gk0 += g.y * ry;
+  gry += g.y * k0;
+  // k2 = cwy*iSy ; k1 = csy*iSy ; k0 = cyy*iSy
+  gwy += gk2 * iSy;
+  giSy += gk2 * pwy;
+  gsy += gk1 * iSy;
+  giSy += gk1 * psy;
+  gyy += gk0 * iSy;
+  giSy += gk0 * pyy;
+  // chi2 = ry^2*iSy + rz^2*iSz
+  gry += gchi2 * 2.0f * ry * iSy;
+  giSy += gchi2 * ry * ry;
+  grz += gchi2 * 2.0f * rz * iSz;
+  giSz += gchi2 * rz * rz;
+  // iS = 1/S ; S = c + sigma^2
+  gzz += -giSz * iSz * iSz;
+  gyy += -giSy * iSy * iSy;
+  // rz = mz - z ; ry = my - y
+  *gmz = grz;
+  gz += -grz;
+  *gmy = gry;
+  gy += -gry;
+  (void)pww;
+  (void)ptt;
+  (void)pss;
+  (void)pws;
+  (void)ps;
+  (void)pt;
+  (void)pw;
+  (void)py;
+
+  // ---------------- reverse: propagation
+  float gdS = 0.0f, gdy = 0.0f, gdx = 0.0f, ga = 0.0f, gb = 0.0f, ge = 0.0f, gs1 = 0.0f;
+  float gPy = 0.0f, gPs = 0.0f, gPw = 0.0f, gQy = 0.0f, gQs = 0.0f, gQw = 0.0f, gRz = 0.0f, gRt = 0.0f;
+  // outputs after propagation: (py, pz, ps, pt, pw, x1) and covariance
+  float gx1v = gx;  // x' = x1
+  float oy = 0.0f, oz = 0.0f, os = 0.0f, ot = gt, ow = gw;
+  float oyy = 0.0f, osy = 0.0f, owy = 0.0f, oss = gss, ows = gws, oww = gww;
+  float ozz = 0.0f, otz = 0.0f, ott = gtt;
+  gs1 += gs;  // s' = s1
+  // z' = z + t*dS ; y' = y + dy
+  oz += gz;
+  ot += gz * dS;
+  gdS += gz * q.t;
+  oy += gy;
+  gdy += gy;
+  // ctt' = ctt ; ctz' = Rt ; czz' = Rz + dS*Rt
+  ott += 0.0f;
+  gRt += gtz;
+  gRz += gzz;
+  gdS += gzz * Rt;
+  gRt += gzz * dS;
+  // Rt = ctz + dS*ctt ; Rz = czz + dS*ctz
+  otz += gRt;
+  gdS += gRt * q.ctt;
+  ott += gRt * dS;
+  ozz += gRz;
+  gdS += gRz * q.ctz;
+  otz += gRz * dS;
+  // cww' = cww ; cws' = Qw ; css' = Qs + e*Qw ; cwy' = Pw
+  gQw += ows;
+  ows = 0.0f;
+  gQs += oss;
+  ge += oss * Qw;
+  gQw += oss * e;
+  oss = 0.0f;
+  gPw += gwy;
+  // csy' = Qy + a*Qs + b*Qw ; cyy' = Py + a*Ps + b*Pw
+  gQy += gsy;
+  ga += gsy * Qs;
+  gQs += gsy * a;
+  gb += gsy * Qw;
+  gQw += gsy * b;
+  gPy += gyy;
+  ga += gyy * Ps;
+  gPs += gyy * a;
+  gb += gyy * Pw;
+  gPw += gyy * b;
+  // Qw = cws + e*cww ; Qs = css + e*cws ; Qy = csy + e*cwy
+  ows += gQw;
+  ge += gQw * q.cww;
+  oww += gQw * e;
+  oss += gQs;
+  ge += gQs * q.cws;
+  ows += gQs * e;
+  osy += gQy;
+  ge += gQy * q.cwy;
+  owy += gQy * e;
+  // Pw = cwy + a*cws + b*cww ; Ps = csy + a*css + b*cws ; Py = cyy + a*csy + b*cwy
+  owy += gPw;
+  ga += gPw * q.cws;
+  ows += gPw * a;
+  gb += gPw * q.cww;
+  oww += gPw * b;
+  osy += gPs;
+  ga += gPs * q.css;
+  oss += gPs * a;
+  gb += gPs * q.cws;
+  ows += gPs * b;
+  oyy += gPy;
+  ga += gPy * q.csy;
+  osy += gPy * a;
+  gb += gPy * q.cwy;
+  owy += gPy * b;
+  // b = de*qb ; de = dx*e ; qb = nb*icc2 ; nb = cc + ss*r1
+  float gde = gb * qb, gqb = gb * de;
+  gdx += gde * e;
+  ge += gde * dx;
+  float gnb = gqb * icc2, gicc2 = gqb * nb;
+  float gcc = gnb, gsum = gnb * r1, gr1 = gnb * ss, gr0 = 0.0f;
+  // e = -kappa*dx
+  gdx += -ge * p.kappa;
+  // a = dx*qa ; qa = na*icc2 ; na = 2cc + ss*(r0 + r1)
+  gdx += ga * qa;
+  const float gqa = ga * dx;
+  const float gna = gqa * icc2;
+  gicc2 += gqa * na;
+  gcc += 2.0f * gna;
+  gsum += gna * (r0 + r1);
+  gr0 += gna * ss;
+  gr1 += gna * ss;
+  // icc2 = icc*icc
+  float gicc = 2.0f * icc * gicc2;
+  // r1 = s1/c1 ; r0 = s/c0
+  gs1 += gr1 / c1;
+  float gc1 = -gr1 * r1 / c1;
+  os += gr0 / c0;
+  float gc0 = -gr0 * r0 / c0;
+  // dS = sgn * dl * A ; A = 1 + u2*(a1 + u2*a2) ; u2 = u*u ; u = 0.5*ak*dl
+  float gdl = gdS * sgn * A;
+  const float gA = gdS * sgn * dl;
+  const float gu2 = gA * (a1c + 2.0f * a2c * u2);
+  const float gu = 2.0f * u * gu2;
+  const float gak = 0.5f * gu * dl;
+  gdl += 0.5f * gu * ak;
+  float gk = gak * (k < 0.0f ? -1.0f : (k > 0.0f ? 1.0f : 0.0f));
+  // dl = sqrt(dx^2 + dy^2)
+  if (dl > 0.0f) {
+    gdx += gdl * dx / dl;
+    gdy += gdl * dy / dl;
+  }
+  // dy = dx*tg ; tg = ss*icc ; icc = 1/cc
+  gdx += gdy * tg;
+  const float gtg = gdy * dx;
+  gsum += gtg * icc;
+  gicc += gtg * ss;
+  gcc += -gicc * icc * icc;
+  // ss = s + s1 ; cc = c0 + c1
+  os += gsum;
+  gs1 += gsum;
+  gc0 += gcc;
+  gc1 += gcc;
+  // c1 = sqrt(1 - s1^2) ; c0 = sqrt(1 - s^2)
+  gs1 += gc1 * (-s1 / c1);
+  os += gc0 * (-q.s / c0);
+  // s1 = s - kd ; kd = k*dx ; k = kappa*w
+  os += gs1;
+  const float gkd = -gs1;
+  gk += gkd * dx;
+  gdx += gkd * k;
+  ow += gk * p.kappa;
+  // dx = x1 - x
+  gx1v += gdx;
+  const float ox = -gdx;
+
+  *gx1 = gx1v;
+  g.x = ox;
+  g.y = oy;
+  g.z = oz;
+  g.s = os;
+  g.t = ot;
+  g.w = ow;
+  g.cyy = oyy;
+  g.csy = osy;
+  g.css = oss;
+  g.cwy = owy;
+  g.cws = ows;
+  g.cww = oww;
+  g.czz = ozz;
+  g.ctz = otz;
+  g.ctt = ott;
+}
+
+// Adds the coefficient gradient of one cluster: the adjoints of its corrected
+// (x, y, z) pulled back through the correction and the basis.
+__device__ __forceinline__ void add_hit_gradient(const HitGeom& h, float r, float gxc, float gyc,
+                                                 float gzc, int wref, long long* win,
+                                                 int64_t* __restrict__ acc) {
+  const float gdr = (gxc * h.xm + gyc * h.ym) * h.inv_r;
+  const float gdp = (-gxc * h.ym + gyc * h.xm) * h.inv_r;
+  const float gdz = gzc;
+  const Weights4 wp = weights_phi(h.phi);
+  const Weights4 wr = weights_lin(r, kMapR0, kMapDR, kMapNR);
+  const Weights4 wz = weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ);
+  for (int a = 0; a < 4; ++a) {
+    const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
+    int rel = i - wref;
+    if (rel > kMapNPhi / 2) rel -= kMapNPhi;
+    if (rel <= -kMapNPhi / 2) rel += kMapNPhi;
+    rel += kWinPhi / 2;
+    const bool in_win = rel >= 0 && rel < kWinPhi;
+    for (int b = 0; b < 4; ++b) {
+      const float wab = wp.w[a] * wr.w[b];
+      if (wab == 0.0f) continue;
+      const int j = wr.first + b;
+      for (int c = 0; c < 4; ++c) {
+        const float w = wab * wz.w[c];
+        if (w == 0.0f) continue;
+        const int k = wz.first + c;
+        const float g3[3] = {gdr * w, gdp * w, gdz * w};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const long long v = llrint(double(g3[q]) * kFixScale);
+          if (v == 0) continue;
+          if (in_win)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&win[((q * kWinPhi + rel) * kMapNR + j) * kMapNZ + k]),
+                      static_cast<unsigned long long>(v));
+          else
+            atomicAdd(reinterpret_cast<unsigned long long*>(&acc[map_index(q, i, j, k)]),
+                      static_cast<unsigned long long>(v));
+        }
+      }
+    }
+  }
+}
+
+// Backward: one lane per track.  The block accumulates its coefficient
+// gradients in an LDS window of kWinPhi phi nodes centred on its first track's
+// sector, then adds the window to the global accumulators.
+__global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams p, RefitWs ws,
+                                                           const float* __restrict__ dL_dchi2,
+                                                           const int32_t* __restrict__ ok_in) {
+  extern __shared__ long long win[];  // [3][kWinPhi][17][20]
+  const int nwin = kMapComp * kWinPhi * kMapNR * kMapNZ;
+  for (int i = threadIdx.x; i < nwin; i += blockDim.x) win[i] = 0;
+  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x;
+  // reference phi node: the sector centre of the block's first track
+  const float a_ref = in.unit_alpha[in.unit[min(t0, in.n_tracks - 1)]];
+  float ph = fmodf(a_ref, 6.28318530717958647692f);
+  if (ph < 0.0f) ph += 6.28318530717958647692f;
+  const int wref = int(floorf(ph / kMapDPhi));
+  __syncthreads();
+
+  const int64_t t = t0 + threadIdx.x;
+  if (t < in.n_tracks && ok_in[t] && dL_dchi2[t] != 0.0f) {
+    const int64_t hb = in.hit_begin[t];
+    const int n = track_size(in, t);
+    const float gchi2 = dL_dchi2[t];
+    const float alpha = in.unit_alpha[in.unit[t]];
+    const int64_t cb = ckpt_base(in, t);
+    float* scr = ws.scratch + t % ws.n_lanes * (kCkpt * kCkptFloats);
+    const float4* xyz = reinterpret_cast<const float4*>(ws.xyz);
+    KBar g{};
+    const int nseg = (n - 2) / kCkpt + 1;  // segments covering steps 1..n-1
+    for (int m = nseg - 1; m >= 0; --m) {
+      const int i_lo = m * kCkpt;
+      const int i_hi = min((m + 1) * kCkpt, n - 1);
+      // recompute the segment's states S_{i_lo} .. S_{i_hi - 1}
+      KState q = load_state(ws.ckpt + (cb + m) * kCkptFloats);
+      for (int i = i_lo; i < i_hi; ++i) {
+        store_state(scr + (i - i_lo) * kCkptFloats, q);
+        if (i + 1 < i_hi) {
+          const float4 h = xyz[hb + i + 1];
+          float dummy = 0.0f;
+          refit_step(q, h.x, h.y, h.z, p, &dummy);
+        }
+      }
+      // reverse sweep over the segment's steps i = i_hi .. i_lo + 1
+      for (int i = i_hi; i > i_lo; --i) {
+        const KState prev = load_state(scr + (i - 1 - i_lo) * kCkptFloats);
+        const float4 h = xyz[hb + i];
+        float gx1, gmy, gmz;
+        refit_step_reverse(prev, h.x, h.y, h.z, p, gchi2, g, &gx1, &gmy, &gmz);
+        HitGeom hg;
+        hg.xm = in.row_x[in.hit_row[hb + i]];
+        hg.ym = in.y[in.hit_id[hb + i]];
+        hg.zm = in.z[in.hit_id[hb + i]];
+        const float r = sqrtf(hg.xm * hg.xm + hg.ym * hg.ym);
+        hg.inv_r = 1.0f / r;
+        hg.phi = alpha + atan2f(hg.ym, hg.xm);
+        add_hit_gradient(hg, r, gx1, gmy, gmz, wref, win, ws.acc);
+      }
+    }
+    // the first cluster seeds x, y, z of the state
+    HitGeom hg;
+    hg.xm = in.row_x[in.hit_row[hb]];
+    hg.ym = in.y[in.hit_id[hb]];
+    hg.zm = in.z[in.hit_id[hb]];
+    const float r = sqrtf(hg.xm * hg.xm + hg.ym * hg.ym);
+    hg.inv_r = 1.0f / r;
+    hg.phi = alpha + atan2f(hg.ym, hg.xm);
+    add_hit_gradient(hg, r, g.x, g.y, g.z, wref, win, ws.acc);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nwin; i += blockDim.x) {
+    const long long v = win[i];
+    if (v == 0) continue;
+    const int k = i % kMapNZ;
+    const int j = (i / kMapNZ) % kMapNR;
+    const int rel = (i / (kMapNZ * kMapNR)) % kWinPhi;
+    const int q = i / (kMapNZ * kMapNR * kWinPhi);
+    const int ii = ((wref + rel - kWinPhi / 2) % kMapNPhi + kMapNPhi) % kMapNPhi;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&ws.acc[map_index(q, ii, j, k)]),
+              static_cast<unsigned long long>(v));
+  }
+}
+
+__global__ void k_grad_finalize(const int64_t* __restrict__ acc, float* __restrict__ grad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kMapNCoef) grad[i] = float(double(acc[i]) * (1.0 / kFixScale));
+}
+
+}  // namespace tpcx

@@ -12,6 +12,7 @@
 
 #include "grid.h"
 #include "links.h"
+#include "refit.h"
 #include "tpcx_common.h"
 #include "tracklet.h"
 
@@ -37,6 +38,9 @@ struct tpcx_ctx {
   // stage timing: (TPCX_N_STAGES + 1) events per recorded call
   std::vector<hipEvent_t> events;
   int32_t timing_max = 0, timing_used = 0;
+  // batched form: the graph of the last argument set
+  hipGraphExec_t graph = nullptr;
+  std::vector<unsigned char> graph_key;
 };
 
 namespace {
@@ -60,17 +64,16 @@ struct Carver {
 struct Layout {
   UnitZ* row_z;
   int32_t* bins;
-  float* sy;
-  float* sz;
-  int32_t* sid;
+  float4* pts;
   int32_t* up;
   int32_t* down;
-  int32_t* cup;
   int32_t* cdown;
   uint8_t* flag;
-  int32_t* blk_cnt;
-  int32_t* blk_off;
+  int32_t* row_cnt;
+  int32_t* row_off;
   int32_t* starts;
+  int32_t* start_pos;
+  int32_t* start_k;
   int32_t* queue;
   int64_t* part;
   TrackletTmp tmp;
@@ -84,33 +87,27 @@ int blocks_for(int64_t n, int b) { return int((n + b - 1) / b); }
 int64_t bins_per_unit(const tpcx_ctx* c, int nz) { return int64_t(nz) * c->sum_ny + c->n_rows; }
 
 Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t cap_start, int nz,
-             int block) {
+             int /*block*/) {
   Carver cv{static_cast<char*>(ws)};
   Layout L{};
-  const int64_t nb = blocks_for(n, block);
   L.row_z = cv.take<UnitZ>(int64_t(n_units) * c->n_rows);
   L.bins = cv.take<int32_t>(int64_t(n_units) * bins_per_unit(c, nz));
-  L.sy = cv.take<float>(n);
-  L.sz = cv.take<float>(n);
-  L.sid = cv.take<int32_t>(n);
+  L.pts = cv.take<float4>(n);
   L.up = cv.take<int32_t>(n);
   L.down = cv.take<int32_t>(n);
-  L.cup = cv.take<int32_t>(n);
   L.cdown = cv.take<int32_t>(n);
   L.flag = cv.take<uint8_t>(n);
-  L.blk_cnt = cv.take<int32_t>(nb);
-  L.blk_off = cv.take<int32_t>(nb);
+  L.row_cnt = cv.take<int32_t>(int64_t(n_units) * c->n_rows);
+  L.row_off = cv.take<int32_t>(int64_t(n_units) * c->n_rows);
   L.starts = cv.take<int32_t>(cap_start);
+  L.start_pos = cv.take<int32_t>(cap_start);
+  L.start_k = cv.take<int32_t>(cap_start);
   L.queue = cv.take<int32_t>(1);
   L.part = cv.take<int64_t>(2 * kKeepBlocks);
   L.tmp.cap = std::max<int64_t>(cap_start, 1);
-  L.tmp.n = cv.take<int32_t>(cap_start);
-  L.tmp.n_up = cv.take<int32_t>(cap_start);
-  L.tmp.flags = cv.take<int32_t>(cap_start);
-  L.tmp.unit = cv.take<int32_t>(cap_start);
-  L.tmp.f = cv.take<float>(16 * L.tmp.cap);
-  L.tmp.hit = cv.take<int32_t>(L.tmp.cap * c->n_rows);
-  L.tmp.hrow = cv.take<uint8_t>(L.tmp.cap * c->n_rows);
+  L.tmp.stride = (c->n_rows + 15) / 16 * 16;
+  L.tmp.rec = cv.take<uint32_t>(L.tmp.cap * kRecWords);
+  L.tmp.hit = cv.take<int32_t>(L.tmp.cap * L.tmp.stride);
   L.bytes = cv.off;
   return L;
 }
@@ -136,8 +133,7 @@ tpcx_tuning effective_tuning(const tpcx_ctx* c, int32_t n_units, int64_t n) {
 
 bool valid_tuning(const tpcx_tuning& t) {
   return t.bin_y > 0.0f && std::isfinite(t.bin_y) && t.n_zbins >= 1 && t.n_zbins <= 65536 &&
-         t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 && t.construct_block >= 64 &&
-         t.construct_block <= 1024 && t.construct_block % 64 == 0 && t.construct_grid >= 1;
+         t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 && t.construct_grid >= 1;
 }
 
 tpcx_status build_rows(tpcx_ctx* c) {
@@ -174,8 +170,7 @@ void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t) {
   int nz = int(per_row / 30.0);
   t->n_zbins = std::max(4, std::min(nz, 4096));
   t->block = 256;
-  t->construct_block = 256;
-  t->construct_grid = 2048;
+  t->construct_grid = 1280;  // 5 blocks of 4 wavefronts per CU, persistent
 }
 
 tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx_tuning* tuning,
@@ -185,11 +180,12 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
     if (!std::isfinite(g->row_x_host[r]) || (r > 0 && !(g->row_x_host[r] > g->row_x_host[r - 1])))
       return TPCX_E_ARG;
   }
+  if (g->n_rows > 32 * kMaskWords) return TPCX_E_ARG;
   if (!(g->tan_half_opening > 0.0f) || !std::isfinite(g->bz_tesla)) return TPCX_E_ARG;
   if (!(p->win_y >= 0.0f) || !(p->win_z >= 0.0f) || !(p->d2_max >= 0.0f) || !(p->chi2_max > 0.0f) ||
       !(p->sinphi_max > 0.0f && p->sinphi_max < 1.0f) || !(p->u_max > 0.0f && p->u_max < 1.0f) ||
       !(p->sigma_y > 0.0f) || !(p->sigma_z > 0.0f) || !(p->cww0 > 0.0f) || p->min_hits < 2 ||
-      p->max_misses < 1)
+      p->max_misses < 1 || p->descent_rows < 1 || p->descent_rows > 255)
     return TPCX_E_ARG;
   if (tuning && !valid_tuning(*tuning)) return TPCX_E_ARG;
   *out = nullptr;
@@ -220,6 +216,7 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
   c->dp.cww0 = p->cww0;
   c->dp.min_hits = p->min_hits;
   c->dp.max_misses = p->max_misses;
+  c->dp.descent_rows = p->descent_rows;
   c->frac.assign(g->n_rows, 0.0f);
   for (int r = 1; r + 1 < g->n_rows; ++r) {
     const float a = c->row_x[r] - c->row_x[r - 1];
@@ -249,6 +246,7 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
 
 void tpcx_destroy(tpcx_ctx* c) {
   if (!c) return;
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->d_row_x) (void)hipFree(c->d_row_x);
   if (c->d_frac) (void)hipFree(c->d_frac);
@@ -263,9 +261,12 @@ size_t tpcx_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_cluste
   return carve(c, nullptr, n_units, n_clusters, cap_start, t.n_zbins, t.block).bytes;
 }
 
-tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
-                       int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
-                       hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+tpcx_status check_track_args(const tpcx_ctx* c, const tpcx_clusters* in, const void* ws,
+                             int64_t cap_start, const tpcx_tracks* out) {
   if (!c || !in || !out || !out->counts || in->n_units < 1 || in->n_clusters < 0 ||
       in->n_clusters >= (int64_t(1) << 31) || cap_start < 0 || cap_start >= (int64_t(1) << 31) ||
       out->cap_tracks < 0 || out->cap_hits < 0)
@@ -279,32 +280,25 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
+  return TPCX_OK;
+}
 
+// The whole tracking sequence on `stream`.  `ev` (nullable) receives one event
+// per stage boundary.  No host synchronisation and no memset, so the sequence
+// can be captured into a graph.
+void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, const tpcx_tuning& t,
+                   int64_t cap_start, const tpcx_tracks* out, hipStream_t stream, hipEvent_t* ev) {
   const int32_t U = in->n_units;
-  const int64_t N = in->n_clusters;
   const int R = c->n_rows;
-  const tpcx_tuning t = effective_tuning(c, U, N);
-  const Layout L = carve(c, ws, U, N, cap_start, t.n_zbins, t.block);
-  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   const int B = t.block;
-  const int64_t nb = blocks_for(N, B);
-
   Grid g;
   g.rows = c->d_rows;
   g.row_z = L.row_z;
   g.bin_start = L.bins;
-  g.sy = L.sy;
-  g.sz = L.sz;
-  g.sid = L.sid;
+  g.pts = L.pts;
   g.n_rows = R;
   g.nz = t.n_zbins;
   g.btot = bins_per_unit(c, t.n_zbins);
-
-  hipEvent_t* ev = nullptr;
-  if (c->timing_used < c->timing_max) {
-    ev = &c->events[size_t(c->timing_used) * (TPCX_N_STAGES + 1)];
-    ++c->timing_used;
-  }
   auto mark = [&](int i) {
     if (ev) (void)hipEventRecord(ev[i], stream);
   };
@@ -314,33 +308,26 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   const int UR = U * R;
   const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
   hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,
-                     in->z, g, L.row_z, L.bins, L.sy, L.sz, L.sid);
+                     in->z, g, L.row_z, L.bins, L.pts);
   mark(1);
-  if (N > 0)
-    hipLaunchKernelGGL(k_neighbours, dim3(UR), dim3(kNfBlock), 0, stream, in->row_begin, g,
-                       c->d_frac, c->dp, L.up, L.down);
+  hipLaunchKernelGGL(k_neighbours, dim3(UR), dim3(kNfBlock), 0, stream, in->row_begin, g,
+                     c->d_frac, c->dp, L.up, L.down);
   mark(2);
-  if (N > 0) {
-    hipLaunchKernelGGL(k_clean_flags, dim3(nb), dim3(B), 0, stream, N, L.up, L.down, L.cup,
-                       L.cdown, L.flag, L.blk_cnt);
-  }
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, L.blk_cnt, N > 0 ? nb : 0,
-                     L.blk_off, out->counts, cap_start, out->counts + 3,
+  hipLaunchKernelGGL(k_clean_starts, dim3(UR), dim3(B), 0, stream, in->row_begin, L.up, L.down,
+                     L.pts, L.cdown, L.flag, L.row_cnt);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, L.row_cnt, int64_t(UR),
+                     L.row_off, out->counts, cap_start, out->counts + 3,
                      int64_t(TPCX_ST_START_OVERFLOW));
-  if (N > 0)
-    hipLaunchKernelGGL(k_write_starts, dim3(nb), dim3(B), 0, stream, N, L.flag, L.blk_off,
-                       cap_start, L.starts);
+  hipLaunchKernelGGL(k_write_starts, dim3(UR), dim3(B), 0, stream, in->row_begin, L.pts, L.flag,
+                     L.row_off, cap_start, L.starts, L.start_pos, L.start_k);
 
   TrackInputs ti;
-  ti.row_begin = in->row_begin;
-  ti.n_units = U;
-  ti.y = in->y;
-  ti.z = in->z;
-  ti.clean_up = L.cup;
-  ti.starts = L.starts;
+  ti.pts = L.pts;
+  ti.start_pos = L.start_pos;
+  ti.start_k = L.start_k;
   ti.row_x = c->d_row_x;
   mark(3);
-  hipLaunchKernelGGL(k_construct, dim3(t.construct_grid), dim3(t.construct_block), 0, stream,
+  hipLaunchKernelGGL(k_construct, dim3(t.construct_grid), dim3(kConstructBlock), 0, stream,
                      out->counts, cap_start, L.queue, ti, g, c->dp, L.tmp);
 
   TrackOut o;
@@ -359,19 +346,40 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   o.ndf = out->ndf;
   mark(4);
   hipLaunchKernelGGL(k_keep_count, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
-                     L.tmp.n, c->dp.min_hits, L.part);
+                     L.tmp.rec, c->dp.min_hits, L.part);
   hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(64), 0, stream, L.part, kKeepBlocks, out->counts,
                      out->cap_tracks, out->cap_hits);
-  hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(kKeepBlock), 0, stream, out->counts, cap_start,
-                     L.starts, L.tmp, R, c->dp.min_hits, L.part, o);
+  hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(kKeepBlock), 0, stream, out->counts,
+                     cap_start, L.starts, L.tmp, c->dp.min_hits, L.part, o);
   mark(5);
+}
 
+hipEvent_t* next_timing_slot(tpcx_ctx* c) {
+  if (c->timing_used >= c->timing_max) return nullptr;
+  hipEvent_t* ev = &c->events[size_t(c->timing_used) * (TPCX_N_STAGES + 1)];
+  ++c->timing_used;
+  return ev;
+}
+
+}  // namespace
+
+extern "C" {
+
+tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                       int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
+                       hipStream_t stream) {
+  const tpcx_status st = check_track_args(c, in, ws, cap_start, out);
+  if (st != TPCX_OK) return st;
+  const int64_t N = in->n_clusters;
+  const tpcx_tuning t = effective_tuning(c, in->n_units, N);
+  const Layout L = carve(c, ws, in->n_units, N, cap_start, t.n_zbins, t.block);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
+  enqueue_track(c, in, L, t, cap_start, out, stream, next_timing_slot(c));
   if (dbg) {
-    const size_t nbytes = size_t(N) * sizeof(int32_t);
-    if (dbg->link_up && N) (void)hipMemcpyAsync(dbg->link_up, L.up, nbytes, hipMemcpyDeviceToDevice, stream);
-    if (dbg->link_down && N) (void)hipMemcpyAsync(dbg->link_down, L.down, nbytes, hipMemcpyDeviceToDevice, stream);
-    if (dbg->clean_up && N) (void)hipMemcpyAsync(dbg->clean_up, L.cup, nbytes, hipMemcpyDeviceToDevice, stream);
-    if (dbg->clean_down && N) (void)hipMemcpyAsync(dbg->clean_down, L.cdown, nbytes, hipMemcpyDeviceToDevice, stream);
+    if (N > 0 && (dbg->link_up || dbg->link_down || dbg->clean_up || dbg->clean_down))
+      hipLaunchKernelGGL(k_links_to_caller, dim3(blocks_for(N, 256)), dim3(256), 0, stream, N,
+                         L.pts, L.up, L.down, L.cdown, dbg->link_up, dbg->link_down, dbg->clean_up,
+                         dbg->clean_down);
     if (dbg->starts && cap_start)
       (void)hipMemcpyAsync(dbg->starts, L.starts, size_t(cap_start) * sizeof(int32_t),
                            hipMemcpyDeviceToDevice, stream);
@@ -385,6 +393,187 @@ tpcx_status tpcx_poll(tpcx_ctx* c, const tpcx_tracks* out, hipStream_t stream) {
   int64_t st = 0;
   if (hipMemcpy(&st, out->counts + 3, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return TPCX_E_HIP;
   return st ? TPCX_E_CAPACITY : TPCX_OK;
+}
+
+namespace {
+
+struct RefitLayout {
+  RefitWs ws;
+  int32_t* ok;
+  size_t bytes;
+};
+
+RefitLayout carve_refit(void* base, int64_t n_tracks, int64_t n_hits) {
+  Carver cv{static_cast<char*>(base)};
+  RefitLayout L{};
+  L.ws.xyz = cv.take<float>(4 * std::max<int64_t>(n_hits, 1));
+  L.ws.ckpt = cv.take<float>(int64_t(kCkptFloats) * (n_hits / kCkpt + n_tracks + 1));
+  L.ws.n_lanes = std::max<int64_t>(n_tracks, 1);
+  L.ws.scratch = cv.take<float>(L.ws.n_lanes * kCkpt * kCkptFloats);
+  L.ws.acc = cv.take<int64_t>(kMapNCoef);
+  L.ok = cv.take<int32_t>(n_tracks);
+  L.bytes = cv.off;
+  return L;
+}
+
+bool refit_args_ok(const tpcx_ctx* c, const tpcx_refit_in* in) {
+  if (!c || !in || in->n_tracks < 0) return false;
+  if (in->n_tracks > 0 && (!in->hit_begin || !in->hit_id || !in->hit_row || !in->unit || !in->seed ||
+                           !in->y || !in->z || !in->unit_alpha))
+    return false;
+  return true;
+}
+
+RefitIn refit_view(const tpcx_ctx* c, const tpcx_refit_in* in) {
+  RefitIn r;
+  r.n_tracks = in->n_tracks;
+  r.n_tracks_dev = nullptr;
+  r.status_dev = nullptr;
+  r.n_hit = nullptr;
+  r.min_hits = 2;
+  r.hit_begin = in->hit_begin;
+  r.hit_id = in->hit_id;
+  r.hit_row = in->hit_row;
+  r.unit = in->unit;
+  r.seed = in->seed;
+  r.y = in->y;
+  r.z = in->z;
+  r.unit_alpha = in->unit_alpha;
+  r.row_x = c->d_row_x;
+  return r;
+}
+
+}  // namespace
+
+size_t tpcx_refit_workspace_bytes(const tpcx_ctx* c, int64_t n_tracks, int64_t n_hits) {
+  if (!c || n_tracks < 0 || n_hits < 0) return 0;
+  return carve_refit(nullptr, n_tracks, n_hits).bytes;
+}
+
+tpcx_status tpcx_refit(tpcx_ctx* c, const tpcx_refit_in* in, const float* theta, float* chi2,
+                       int32_t* ok, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!refit_args_ok(c, in) || (in->n_tracks > 0 && (!chi2 || !ok))) return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  // the hit count is the last offset; it lives on the device
+  int64_t n_hits = 0;
+  if (in->n_tracks > 0 &&
+      hipMemcpyAsync(&n_hits, in->hit_begin + in->n_tracks, sizeof n_hits, hipMemcpyDeviceToHost,
+                     stream) != hipSuccess)
+    return TPCX_E_HIP;
+  if (in->n_tracks > 0 && hipStreamSynchronize(stream) != hipSuccess) return TPCX_E_HIP;
+  const RefitLayout L = carve_refit(ws, in->n_tracks, n_hits);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
+  if (in->n_tracks == 0) return TPCX_OK;
+  hipLaunchKernelGGL(k_refit_fwd, dim3(std::min(blocks_for(in->n_tracks, kRefitBlock), 4 * c->n_cu)),
+                     dim3(kRefitBlock), 0, stream, refit_view(c, in), theta, c->dp, L.ws, chi2, L.ok);
+  (void)hipMemcpyAsync(ok, L.ok, sizeof(int32_t) * size_t(in->n_tracks), hipMemcpyDeviceToDevice,
+                       stream);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
+tpcx_status tpcx_refit_backward(tpcx_ctx* c, const tpcx_refit_in* in, const float* dL_dchi2,
+                                float* grad_theta, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!refit_args_ok(c, in) || !grad_theta || (in->n_tracks > 0 && !dL_dchi2)) return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  int64_t n_hits = 0;
+  if (in->n_tracks > 0 &&
+      (hipMemcpyAsync(&n_hits, in->hit_begin + in->n_tracks, sizeof n_hits, hipMemcpyDeviceToHost,
+                      stream) != hipSuccess ||
+       hipStreamSynchronize(stream) != hipSuccess))
+    return TPCX_E_HIP;
+  const RefitLayout L = carve_refit(ws, in->n_tracks, n_hits);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
+  hipLaunchKernelGGL(k_fill_i64, dim3(64), dim3(256), 0, stream, L.ws.acc, int64_t(kMapNCoef),
+                     int64_t(0));
+  if (in->n_tracks > 0) {
+    const size_t win_bytes = sizeof(long long) * kMapComp * kWinPhi * kMapNR * kMapNZ;
+    hipLaunchKernelGGL(k_refit_bwd, dim3(blocks_for(in->n_tracks, kRefitBlock)), dim3(kRefitBlock),
+                       win_bytes, stream, refit_view(c, in), c->dp, L.ws, dL_dchi2, L.ok);
+  }
+  hipLaunchKernelGGL(k_grad_finalize, dim3((kMapNCoef + 255) / 256), dim3(256), 0, stream, L.ws.acc,
+                     grad_theta);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
+size_t tpcx_batched_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_clusters,
+                                    int64_t cap_start, int64_t cap_tracks, int64_t cap_hits) {
+  if (!c || n_units < 1 || n_clusters < 0 || cap_start < 0 || cap_tracks < 0 || cap_hits < 0)
+    return 0;
+  const tpcx_tuning t = effective_tuning(c, n_units, n_clusters);
+  const size_t a = carve(c, nullptr, n_units, n_clusters, cap_start, t.n_zbins, t.block).bytes;
+  return a + carve_refit(nullptr, cap_tracks, cap_hits).bytes;
+}
+
+tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                               int64_t cap_start, const tpcx_tracks* out,
+                               const tpcx_batch_refit* refit, hipStream_t stream) {
+  tpcx_status st = check_track_args(c, in, ws, cap_start, out);
+  if (st != TPCX_OK) return st;
+  if (refit && (refit->min_hits < 2 || !refit->unit_alpha || !refit->chi2 || !refit->ok))
+    return TPCX_E_ARG;
+  if (!stream) return TPCX_E_ARG;  // the legacy default stream cannot be captured
+  const int64_t N = in->n_clusters;
+  const tpcx_tuning t = effective_tuning(c, in->n_units, N);
+  const Layout L = carve(c, ws, in->n_units, N, cap_start, t.n_zbins, t.block);
+  const RefitLayout RL =
+      carve_refit(ws ? static_cast<char*>(ws) + L.bytes : nullptr, out->cap_tracks, out->cap_hits);
+  if (!ws || ws_bytes < L.bytes + RL.bytes) return TPCX_E_ARG;
+
+  // the graph depends on every argument; rebuild it when one changes
+  std::vector<unsigned char> key;
+  auto put = [&](const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    key.insert(key.end(), b, b + n);
+  };
+  put(in, sizeof *in);
+  put(&ws, sizeof ws);
+  put(&ws_bytes, sizeof ws_bytes);
+  put(&cap_start, sizeof cap_start);
+  put(out, sizeof *out);
+  const int has_refit = refit ? 1 : 0;
+  put(&has_refit, sizeof has_refit);
+  if (refit) put(refit, sizeof *refit);
+  put(&t, sizeof t);
+  put(&stream, sizeof stream);
+
+  if (!c->graph || key != c->graph_key) {
+    if (c->graph) {
+      (void)hipGraphExecDestroy(c->graph);
+      c->graph = nullptr;
+    }
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
+    enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
+    if (refit) {
+      RefitIn r;
+      r.n_tracks = out->cap_tracks;
+      r.n_tracks_dev = out->counts + 1;
+      r.status_dev = out->counts + 3;
+      r.n_hit = out->n_hits;
+      r.min_hits = refit->min_hits;
+      r.hit_begin = out->hit_begin;
+      r.hit_id = out->hit_id;
+      r.hit_row = out->hit_row;
+      r.unit = out->unit;
+      r.seed = out->param;
+      r.y = in->y;
+      r.z = in->z;
+      r.unit_alpha = refit->unit_alpha;
+      r.row_x = c->d_row_x;
+      hipLaunchKernelGGL(k_refit_fwd, dim3(4 * c->n_cu), dim3(kRefitBlock), 0, stream, r,
+                         refit->theta, c->dp, RL.ws, refit->chi2, refit->ok);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(stream, &g);
+    if (e1 != hipSuccess || !g) return TPCX_E_HIP;
+    const hipError_t e2 = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+      c->graph = nullptr;
+      return TPCX_E_HIP;
+    }
+    c->graph_key = key;
+  }
+  return hipGraphLaunch(c->graph, stream) == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
 tpcx_status tpcx_timing_enable(tpcx_ctx* c, int32_t max_calls) {

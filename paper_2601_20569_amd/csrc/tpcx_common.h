@@ -13,7 +13,7 @@ struct DevParams {
   float kappa;   // d sin(phi) / dx per unit of q/pT
   float sy2, sz2;
   float wy, wz, d2max, chi2max, smax, umax, cww0;
-  int32_t min_hits, max_misses;
+  int32_t min_hits, max_misses, descent_rows;
 };
 
 // Search-grid description of one pad row (identical for every unit).
@@ -35,9 +35,7 @@ struct Grid {
   const RowInfo* rows;
   const UnitZ* row_z;        // [n_units * n_rows]
   const int32_t* bin_start;  // [n_units * btot]; absolute sorted positions
-  const float* sy;
-  const float* sz;
-  const int32_t* sid;  // sorted position -> caller index
+  const float4* pts;         // sorted clusters: y, z, caller id (bits), cleaned up-link (bits)
   int32_t n_rows, nz;
   int64_t btot;  // bins (+1 sentinel per row) of one unit
 

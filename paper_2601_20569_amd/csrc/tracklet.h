@@ -31,29 +31,39 @@ __device__ __forceinline__ float arc_chord_ratio(float u) {
 
 // Exact circle step to the plane x1 with the linearised covariance transport.
 // Returns false (state unchanged) when |sin(phi)| would reach smax or the
-// chord is too long.
-__device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParams& p) {
+// chord is too long.  (c_prev, r_prev) = (sqrt(1 - s^2), s / that) of the
+// current s when `cached` (the previous step ended at this s): the values are
+// the ones the step would compute itself, bit for bit.
+__device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParams& p, float& c_prev,
+                                             float& r_prev, bool& cached) {
   const float dx = x1 - q.x;
   const float k = p.kappa * q.w;
   const float s1 = q.s - k * dx;
   if (!(fabsf(s1) < p.smax)) return false;
-  const float c0 = sqrtf(1.0f - q.s * q.s);
+  float c0, r0;
+  if (cached) {
+    c0 = c_prev;
+    r0 = r_prev;
+  } else {
+    c0 = sqrtf(1.0f - q.s * q.s);
+    r0 = q.s / c0;
+  }
   const float c1 = sqrtf(1.0f - s1 * s1);
   const float cc = c0 + c1;
   const float ss = q.s + s1;
-  const float tg = ss / cc;
+  const float icc = 1.0f / cc;
+  const float tg = ss * icc;
   const float dy = dx * tg;
   const float dl = sqrtf(dx * dx + dy * dy);
   const float u = (fabsf(k) * dl) * 0.5f;
   if (!(u <= p.umax)) return false;
   float dS = dl * arc_chord_ratio(u);
   if (dx < 0.0f) dS = -dS;
-  const float r0 = q.s / c0;
   const float r1 = s1 / c1;
-  const float cc2 = cc * cc;
-  const float a = dx * ((2.0f * cc + ss * (r0 + r1)) / cc2);
+  const float icc2 = icc * icc;
+  const float a = dx * ((2.0f * cc + ss * (r0 + r1)) * icc2);
   const float e = -(p.kappa * dx);
-  const float b = (dx * e) * ((cc + ss * r1) / cc2);
+  const float b = (dx * e) * ((cc + ss * r1) * icc2);
   const float Py = (q.cyy + a * q.csy) + b * q.cwy;
   const float Ps = (q.csy + a * q.css) + b * q.cws;
   const float Pw = (q.cwy + a * q.cws) + b * q.cww;
@@ -73,24 +83,19 @@ __device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParam
   q.z = q.z + q.t * dS;
   q.s = s1;
   q.x = x1;
+  c_prev = c1;
+  r_prev = r1;
+  cached = true;
   return true;
 }
 
-__device__ __forceinline__ float kf_chi2(const KState& q, float my, float mz, const DevParams& p) {
+// Kalman update with the cluster (my, mz), given the inverse residual
+// variances iSy = 1/(cyy + sy^2), iSz = 1/(czz + sz^2); returns the chi2.
+__device__ __forceinline__ float kf_update(KState& q, float my, float mz, float iSy, float iSz) {
   const float ry = my - q.y;
   const float rz = mz - q.z;
-  const float Sy = q.cyy + p.sy2;
-  const float Sz = q.czz + p.sz2;
-  return (ry * ry) / Sy + (rz * rz) / Sz;
-}
-
-__device__ __forceinline__ float kf_update(KState& q, float my, float mz, const DevParams& p) {
-  const float ry = my - q.y;
-  const float rz = mz - q.z;
-  const float Sy = q.cyy + p.sy2;
-  const float Sz = q.czz + p.sz2;
-  const float chi2 = (ry * ry) / Sy + (rz * rz) / Sz;
-  const float k0 = q.cyy / Sy, k1 = q.csy / Sy, k2 = q.cwy / Sy;
+  const float chi2 = (ry * ry) * iSy + (rz * rz) * iSz;
+  const float k0 = q.cyy * iSy, k1 = q.csy * iSy, k2 = q.cwy * iSy;
   q.y = q.y + k0 * ry;
   q.s = q.s + k1 * ry;
   q.w = q.w + k2 * ry;
@@ -101,7 +106,7 @@ __device__ __forceinline__ float kf_update(KState& q, float my, float mz, const 
   q.css = q.css - k1 * csy;
   q.cws = q.cws - k2 * csy;
   q.cww = q.cww - k2 * cwy;
-  const float kz0 = q.czz / Sz, kz1 = q.ctz / Sz;
+  const float kz0 = q.czz * iSz, kz1 = q.ctz * iSz;
   q.z = q.z + kz0 * rz;
   q.t = q.t + kz1 * rz;
   const float czz = q.czz, ctz = q.ctz;
@@ -111,15 +116,16 @@ __device__ __forceinline__ float kf_update(KState& q, float my, float mz, const 
   return chi2;
 }
 
-// Best cluster of row r by (chi2, caller id) among chi2 <= chi2max, or -1.
-// The grid box is |dy| <= 4 sqrt(Sy) (and z alike), widened to be exact.
-__device__ __forceinline__ int32_t kf_search(const Grid& g, int u, int r, const KState& q,
-                                             const DevParams& p, float* out_my, float* out_mz) {
-  const int k = u * g.n_rows + r;
-  const float Sy = q.cyy + p.sy2;
-  const float Sz = q.czz + p.sz2;
-  const float hy = sqrtf(p.chi2max * Sy) * 1.0001f + box_pad(q.y);
-  const float hz = sqrtf(p.chi2max * Sz) * 1.0001f + box_pad(q.z);
+// Best cluster of row r (grid row k) by (chi2, caller id) among chi2 <=
+// chi2max, or -1.  The grid box |dy| <= 4 sqrt(Sy), |dz| <= 4 sqrt(Sz) is
+// widened so that it holds every cluster the float chi2 cut can accept.
+__device__ __forceinline__ int32_t kf_search(const Grid& g, int k, int r, const KState& q,
+                                             const DevParams& p, float iSy, float iSz,
+                                             float* out_my, float* out_mz) {
+  // the hardware square root (within 1 ulp) is enough: the box only has to
+  // be large enough, and the 1e-3 relative margin covers its error
+  const float hy = __builtin_amdgcn_sqrtf(p.chi2max * (q.cyy + p.sy2)) * 1.001f + box_pad(q.y);
+  const float hz = __builtin_amdgcn_sqrtf(p.chi2max * (q.czz + p.sz2)) * 1.001f + box_pad(q.z);
   const int zb0 = g.zbin(k, q.z - hz), zb1 = g.zbin(k, q.z + hz);
   const int yb0 = g.ybin(r, q.y - hy), yb1 = g.ybin(r, q.y + hy);
   const int64_t base = g.row_base(k);
@@ -129,10 +135,13 @@ __device__ __forceinline__ int32_t kf_search(const Grid& g, int u, int r, const 
   for (int zb = zb0; zb <= zb1; ++zb) {
     const int32_t j0 = g.bin_start[base + zb * ny + yb0], j1 = g.bin_start[base + zb * ny + yb1 + 1];
     for (int32_t j = j0; j < j1; ++j) {
-      const float my = g.sy[j], mz = g.sz[j];
-      const float ch = kf_chi2(q, my, mz, p);
+      const float4 m = g.pts[j];
+      const float my = m.x, mz = m.y;
+      const float ry = my - q.y;
+      const float rz = mz - q.z;
+      const float ch = (ry * ry) * iSy + (rz * rz) * iSz;
       if (!(ch <= p.chi2max)) continue;
-      const int32_t id = g.sid[j];
+      const int32_t id = __float_as_int(m.z);
       if (best < 0 || ch < bch || (ch == bch && id < best)) {
         best = id;
         bch = ch;
@@ -146,161 +155,263 @@ __device__ __forceinline__ int32_t kf_search(const Grid& g, int u, int r, const 
   return best;
 }
 
-// Per-start-hit results before compaction (structure of arrays, cap entries).
+// Per-start-hit results before compaction.  One 128-byte record per slot:
+//   words 0-15  x_ref, y, z, s, t, w, cyy, csy, css, cwy, cws, cww, czz, ctz, ctt, chi2 (float)
+//   words 16-19 n, n_up, flags, unit (int)
+//   words 20-24 mask of the rows with an attached cluster (rows 0..159)
+// and `stride` hit slots with the cluster ids in attachment order: the
+// outward phase in ascending rows, then the inward phase in descending rows.
+constexpr int kRecWords = 32;
+constexpr int kRecN = 16, kRecNUp = 17, kRecFlags = 18, kRecUnit = 19, kRecMask = 20;
+constexpr int kMaskWords = 5;
+
 struct TrackletTmp {
   int64_t cap;
-  int32_t* n;        // clusters attached
-  int32_t* n_up;     // of which at or above the start row
-  int32_t* flags;    // bit 0: the walk back to the start row failed
-  int32_t* unit;
-  float* f;          // [16][cap]: x_ref, y, z, s, t, w, cyy, csy, css, cwy, cws, cww, czz, ctz, ctt, chi2
-  int32_t* hit;      // [cap][n_rows]: up-phase ids from slot 0, down-phase from the end
-  uint8_t* hrow;     // [cap][n_rows]
+  int32_t stride;  // hit slots per record, n_rows rounded up to a multiple of 16
+  uint32_t* rec;   // [cap][kRecWords]
+  int32_t* hit;    // [cap][stride]
 };
 
 constexpr int kFlagDescentFailed = 1;
 
 struct TrackInputs {
-  const int64_t* row_begin;
-  int n_units;
-  const float* y;  // caller order
-  const float* z;
-  const int32_t* clean_up;
-  const int32_t* starts;
-  const float* row_x;  // [n_rows]
+  const float4* pts;         // sorted clusters (y, z, caller id, cleaned up-link)
+  const int32_t* start_pos;  // sorted position of every start hit
+  const int32_t* start_k;    // its unit * n_rows + row
+  const float* row_x;        // [n_rows]
 };
 
-__device__ void build_tracklet(int64_t s, const TrackInputs& in, const Grid& g, const DevParams& p,
-                               const TrackletTmp& out) {
-  const int R = g.n_rows;
-  const int32_t h0 = in.starts[s];
-  const int k = upper_row(in.row_begin, in.n_units * R + 1, h0);
-  const int u = k / R, r0 = k % R;
-  int32_t* hits = out.hit + s * R;
-  uint8_t* hrow = out.hrow + s * R;
+// Phases of a tracklet: the chain of the seed (clusters attached without a
+// cut), following outwards, the walk back to the start row, following inwards.
+enum : int { kChain = 0, kUp = 1, kDescend = 2, kDown = 3, kIdle = 4 };
 
-  // 2-point seed at the second cluster of the chain
-  const int32_t c0 = h0, c1 = in.clean_up[h0];
-  KState q;
-  const float dx = in.row_x[r0 + 1] - in.row_x[r0];
-  const float dy = in.y[c1] - in.y[c0];
-  const float dz = in.z[c1] - in.z[c0];
-  const float dl = sqrtf(dx * dx + dy * dy);
-  q.x = in.row_x[r0 + 1];
-  q.y = in.y[c1];
-  q.z = in.z[c1];
-  q.s = dy / dl;
-  q.t = dz / dl;
-  q.w = 0.0f;
-  q.cyy = p.sy2;
-  q.csy = p.sy2 / dl;
-  q.css = (p.sy2 + p.sy2) / (dl * dl);
-  q.cwy = 0.0f;
-  q.cws = 0.0f;
-  q.cww = p.cww0;
-  q.czz = p.sz2;
-  q.ctz = p.sz2 / dl;
-  q.ctt = (p.sz2 + p.sz2) / (dl * dl);
-  float chi2 = 0.0f;
-  int n_up = 0, n_dn = 0;
-  hits[n_up] = c0;
-  hrow[n_up++] = uint8_t(r0);
-  hits[n_up] = c1;
-  hrow[n_up++] = uint8_t(r0 + 1);
-  int row = r0 + 1;
+constexpr int kConstructBlock = 256;
+constexpr int kRefill = 16;  // idle lanes that trigger a refill from the queue
 
-  // rest of the chain, attached without a cut
-  bool up_ok = true;
-  for (int32_t c = in.clean_up[c1]; c >= 0; c = in.clean_up[c]) {
-    const int rr = row + 1;
-    if (!kf_propagate(q, in.row_x[rr], p)) {
-      up_ok = false;
-      break;
-    }
-    chi2 = chi2 + kf_update(q, in.y[c], in.z[c], p);
-    hits[n_up] = c;
-    hrow[n_up++] = uint8_t(rr);
-    row = rr;
-  }
-  KState best = q;
-  int best_row = row;
+// Every lane runs one tracklet at a time as a sequence of row steps (one
+// propagation each); the four phases share the step so that lanes of a
+// wavefront in different phases still execute together.  Idle lanes take new
+// start hits from the device queue in batches.  Results depend only on the
+// start hit: the order in which lanes pick them up is irrelevant.
+// Attached cluster ids are staged per lane in LDS and written 16 at a time
+// (one full 64-byte line), the row mask is kept in LDS too; the record is
+// written once, as whole lines, when the tracklet ends.
+constexpr int kHitBuf = 16;
+constexpr int kConstructWaves = kConstructBlock / kWave;
 
-  // outward following
-  if (up_ok) {
-    int misses = 0;
-    for (int rr = row + 1; rr < R; ++rr) {
-      if (!kf_propagate(q, in.row_x[rr], p)) break;
-      float my, mz;
-      const int32_t c = kf_search(g, u, rr, q, p, &my, &mz);
-      if (c >= 0) {
-        chi2 = chi2 + kf_update(q, my, mz, p);
-        hits[n_up] = c;
-        hrow[n_up++] = uint8_t(rr);
-        best = q;
-        best_row = rr;
-        misses = 0;
-      } else if (++misses == p.max_misses) {
-        break;
-      }
-    }
-  }
-
-  // back to the start row, then inward following
-  q = best;
-  bool down_ok = true;
-  for (int rr = best_row - 1; rr >= r0; --rr) {
-    if (!kf_propagate(q, in.row_x[rr], p)) {
-      down_ok = false;
-      break;
-    }
-  }
-  KState res = best;
-  int flags = 0;
-  if (!down_ok) {
-    flags |= kFlagDescentFailed;
-  } else {
-    res = q;
-    int misses = 0;
-    for (int rr = r0 - 1; rr >= 0; --rr) {
-      if (!kf_propagate(q, in.row_x[rr], p)) break;
-      float my, mz;
-      const int32_t c = kf_search(g, u, rr, q, p, &my, &mz);
-      if (c >= 0) {
-        chi2 = chi2 + kf_update(q, my, mz, p);
-        hits[R - 1 - n_dn] = c;
-        hrow[R - 1 - n_dn] = uint8_t(rr);
-        ++n_dn;
-        res = q;
-        misses = 0;
-      } else if (++misses == p.max_misses) {
-        break;
-      }
-    }
-  }
-
-  const int64_t C = out.cap;
-  out.n[s] = n_up + n_dn;
-  out.n_up[s] = n_up;
-  out.flags[s] = flags;
-  out.unit[s] = u;
-  const float v[16] = {res.x,   res.y,   res.z,   res.s,   res.t,   res.w,   res.cyy, res.csy,
-                       res.css, res.cwy, res.cws, res.cww, res.czz, res.ctz, res.ctt, chi2};
-#pragma unroll
-  for (int j = 0; j < 16; ++j) out.f[j * C + s] = v[j];
-}
-
-// Work-queue driven constructor: each wavefront takes 64 start hits at a time.
-__global__ void k_construct(const int64_t* __restrict__ counts, int64_t cap_start,
-                            int32_t* __restrict__ queue, TrackInputs in, Grid g, DevParams p,
-                            TrackletTmp out) {
+__global__ void __launch_bounds__(kConstructBlock) k_construct(
+    const int64_t* __restrict__ counts, int64_t cap_start, int32_t* __restrict__ queue,
+    TrackInputs in, Grid g, DevParams p, TrackletTmp out) {
+  __shared__ int32_t hbuf[kConstructWaves][kHitBuf][kWave];
+  __shared__ uint32_t rmask[kConstructWaves][kMaskWords][kWave];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
+  const int R = g.n_rows;
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  int nbuf = 0, nflushed = 0;
+  int64_t slot = 0;
+  auto flush = [&]() {
+    int32_t* dst = out.hit + slot * out.stride + nflushed;
+    if (nbuf == kHitBuf) {
+#pragma unroll
+      for (int j = 0; j < kHitBuf; j += 4)
+        *reinterpret_cast<int4*>(dst + j) =
+            make_int4(hbuf[wv][j][lane], hbuf[wv][j + 1][lane], hbuf[wv][j + 2][lane], hbuf[wv][j + 3][lane]);
+    } else {
+      for (int j = 0; j < nbuf; ++j) dst[j] = hbuf[wv][j][lane];
+    }
+    nflushed += nbuf;
+    nbuf = 0;
+  };
+  KState q{}, best{};
+  float c_prev = 0.0f, r_prev = 0.0f, chi2 = 0.0f;
+  bool cached = false;
+  int kbase = 0, r0 = 0, row = 0, best_row = 0, phase = kIdle, misses = 0, n_up = 0, n_dn = 0,
+      flags = 0;
+  int32_t next_c = -1;
+  int64_t extra_begin = 0, extra_end = 0;
+  // wavefront-private pool [pool, pool_end) of start slots, refilled from the
+  // device queue kWave slots at a time
+  int64_t pool = 0, pool_end = 0;
+  bool exhausted = false;
+
   while (true) {
-    int32_t base = 0;
-    if (lane_id() == 0) base = atomicAdd(queue, kWave);
-    base = __shfl(base, 0, kWave);
-    if (base >= n_start) break;
-    const int64_t s = int64_t(base) + lane_id();
-    if (s < n_start) build_tracklet(s, in, g, p, out);
+    // ---- hand start slots to idle lanes
+    const uint64_t idle = __ballot(phase == kIdle);
+    const int nidle = __popcll(idle);
+    if (nidle == kWave && exhausted && pool == pool_end) break;
+    if (nidle > 0 && (nidle >= kRefill || nidle == kWave) && !(exhausted && pool == pool_end)) {
+      if (pool_end - pool < nidle && !exhausted) {
+        // keep the rest of the pool (consumed first), then a fresh chunk
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(queue, kWave);
+        base = __shfl(base, 0, kWave);
+        if (int64_t(base) + kWave >= n_start) exhausted = true;
+        if (pool == pool_end) {
+          pool = min(int64_t(base), n_start);
+          pool_end = min(int64_t(base) + kWave, n_start);
+        } else {
+          extra_begin = min(int64_t(base), n_start);
+          extra_end = min(int64_t(base) + kWave, n_start);
+        }
+      }
+      const int rank = __popcll(idle & lanes_below());
+      const int from_pool = int(min(int64_t(nidle), pool_end - pool));
+      int64_t sidx = -1;
+      if (phase == kIdle) {
+        if (rank < from_pool)
+          sidx = pool + rank;
+        else if (rank - from_pool < extra_end - extra_begin)
+          sidx = extra_begin + (rank - from_pool);
+      }
+      const int from_extra = int(min(int64_t(nidle - from_pool), extra_end - extra_begin));
+      pool += from_pool;
+      if (pool == pool_end && extra_end > extra_begin) {
+        pool = extra_begin + from_extra;
+        pool_end = extra_end;
+        extra_begin = extra_end = 0;
+      }
+      if (phase == kIdle) {
+        if (sidx >= 0) {
+          // 2-point seed at the second cluster of the chain
+          slot = sidx;
+          const float4 P0 = in.pts[in.start_pos[sidx]];
+          const int kk = in.start_k[sidx];
+          r0 = kk % R;
+          kbase = kk - r0;
+          const float4 P1 = in.pts[__float_as_int(P0.w)];
+          const int32_t c0 = __float_as_int(P0.z), c1 = __float_as_int(P1.z);
+          const float dx = in.row_x[r0 + 1] - in.row_x[r0];
+          const float dy = P1.x - P0.x;
+          const float dz = P1.y - P0.y;
+          const float idl = 1.0f / sqrtf(dx * dx + dy * dy);
+          const float idl2 = idl * idl;
+          q.x = in.row_x[r0 + 1];
+          q.y = P1.x;
+          q.z = P1.y;
+          q.s = dy * idl;
+          q.t = dz * idl;
+          q.w = 0.0f;
+          q.cyy = p.sy2;
+          q.csy = p.sy2 * idl;
+          q.css = (p.sy2 + p.sy2) * idl2;
+          q.cwy = 0.0f;
+          q.cws = 0.0f;
+          q.cww = p.cww0;
+          q.czz = p.sz2;
+          q.ctz = p.sz2 * idl;
+          q.ctt = (p.sz2 + p.sz2) * idl2;
+          cached = false;
+          chi2 = 0.0f;
+#pragma unroll
+          for (int w = 0; w < kMaskWords; ++w) rmask[wv][w][lane] = 0u;
+          hbuf[wv][0][lane] = c0;
+          hbuf[wv][1][lane] = c1;
+          nbuf = 2;
+          nflushed = 0;
+          rmask[wv][r0 >> 5][lane] |= 1u << (r0 & 31);
+          rmask[wv][(r0 + 1) >> 5][lane] |= 1u << ((r0 + 1) & 31);
+          n_up = 2;
+          n_dn = 0;
+          flags = 0;
+          misses = 0;
+          row = r0 + 1;
+          best = q;
+          best_row = row;
+          next_c = __float_as_int(P1.w);
+          phase = next_c >= 0 ? kChain : kUp;
+        }
+      }
+    }
+    if (phase == kIdle) continue;
+
+    // ---- one row step
+    const bool outward = phase <= kUp;
+    const int target = outward ? row + 1
+                               : (phase == kDescend ? max(r0, row - p.descent_rows) : row - 1);
+    bool ok = target >= 0 && target < R;
+    if (ok) ok = kf_propagate(q, in.row_x[target], p, c_prev, r_prev, cached);
+    bool finish = false, to_descend = false;
+    if (phase == kDescend) {
+      if (!ok) {
+        flags |= kFlagDescentFailed;
+        finish = true;
+      } else {
+        row = target;
+        if (row == r0) {
+          best = q;
+          best_row = row;
+          misses = 0;
+          phase = kDown;
+        }
+      }
+    } else if (!ok) {
+      if (phase == kDown)
+        finish = true;
+      else
+        to_descend = true;
+    } else {
+      const float iSy = 1.0f / (q.cyy + p.sy2);
+      const float iSz = 1.0f / (q.czz + p.sz2);
+      float my, mz;
+      int32_t c, chain_next = -1;
+      if (phase == kChain) {
+        const float4 P = in.pts[next_c];
+        my = P.x;
+        mz = P.y;
+        c = __float_as_int(P.z);
+        chain_next = __float_as_int(P.w);
+      } else {
+        c = kf_search(g, kbase + target, target, q, p, iSy, iSz, &my, &mz);
+      }
+      row = target;
+      if (c >= 0) {
+        chi2 = chi2 + kf_update(q, my, mz, iSy, iSz);
+        cached = false;
+        if (phase == kDown)
+          ++n_dn;
+        else
+          ++n_up;
+        hbuf[wv][nbuf][lane] = c;
+        rmask[wv][row >> 5][lane] |= 1u << (row & 31);
+        if (++nbuf == kHitBuf) flush();
+        best = q;
+        best_row = row;
+        misses = 0;
+        if (phase == kChain) {
+          next_c = chain_next;
+          if (next_c < 0) phase = kUp;
+        }
+      } else if (++misses == p.max_misses) {
+        if (phase == kDown)
+          finish = true;
+        else
+          to_descend = true;
+      }
+    }
+    if (to_descend) {
+      q = best;
+      row = best_row;
+      cached = false;
+      phase = kDescend;
+    }
+    if (finish) {
+      flush();
+      uint4* rec = reinterpret_cast<uint4*>(out.rec + slot * kRecWords);
+      rec[0] = make_uint4(__float_as_uint(best.x), __float_as_uint(best.y), __float_as_uint(best.z),
+                          __float_as_uint(best.s));
+      rec[1] = make_uint4(__float_as_uint(best.t), __float_as_uint(best.w), __float_as_uint(best.cyy),
+                          __float_as_uint(best.csy));
+      rec[2] = make_uint4(__float_as_uint(best.css), __float_as_uint(best.cwy),
+                          __float_as_uint(best.cws), __float_as_uint(best.cww));
+      rec[3] = make_uint4(__float_as_uint(best.czz), __float_as_uint(best.ctz),
+                          __float_as_uint(best.ctt), __float_as_uint(chi2));
+      rec[4] = make_uint4(uint32_t(n_up + n_dn), uint32_t(n_up), uint32_t(flags), uint32_t(kbase / R));
+      rec[5] = make_uint4(rmask[wv][0][lane], rmask[wv][1][lane], rmask[wv][2][lane], rmask[wv][3][lane]);
+      rec[6] = make_uint4(rmask[wv][4][lane], 0u, 0u, 0u);
+      rec[7] = make_uint4(0u, 0u, 0u, 0u);
+      phase = kIdle;
+    }
   }
 }
 
@@ -314,7 +425,7 @@ __device__ __forceinline__ void chunk_of(int64_t n, int64_t* b, int64_t* e) {
 }
 
 __global__ void k_keep_count(const int64_t* __restrict__ counts, int64_t cap_start,
-                             const int32_t* __restrict__ tn, int min_hits,
+                             const uint32_t* __restrict__ rec, int min_hits,
                              int64_t* __restrict__ part) {
   __shared__ int64_t lds[1024 / kWave];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
@@ -322,7 +433,7 @@ __global__ void k_keep_count(const int64_t* __restrict__ counts, int64_t cap_sta
   chunk_of(n_start, &b, &e);
   int64_t ct = 0, ch = 0;
   for (int64_t s = b + threadIdx.x; s < e; s += blockDim.x) {
-    const int32_t n = tn[s];
+    const int32_t n = int32_t(rec[s * kRecWords + kRecN]);
     if (n >= min_hits) {
       ++ct;
       ch += n;
@@ -379,69 +490,103 @@ constexpr int kKeepBlock = 256;
 
 __global__ void __launch_bounds__(kKeepBlock) k_keep_write(
     const int64_t* __restrict__ counts, int64_t cap_start, const int32_t* __restrict__ starts,
-    TrackletTmp tmp, int n_rows, int min_hits, const int64_t* __restrict__ part, TrackOut o) {
+    TrackletTmp tmp, int min_hits, const int64_t* __restrict__ part, TrackOut o) {
   __shared__ int64_t lds[kKeepBlock / kWave];
   __shared__ int64_t s_hb[kKeepBlock];
   __shared__ int32_t s_slot[kKeepBlock];
   __shared__ int32_t s_n[kKeepBlock];
   __shared__ int32_t s_nu[kKeepBlock];
+  __shared__ uint32_t s_mask[kMaskWords][kKeepBlock];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
   int64_t b, e;
   chunk_of(n_start, &b, &e);
   int64_t t_run = part[2 * blockIdx.x], h_run = part[2 * blockIdx.x + 1];
-  const int64_t C = tmp.cap;
   const int wid = threadIdx.x / kWave, nw = kKeepBlock / kWave;
   for (int64_t s0 = b; s0 < e; s0 += kKeepBlock) {
     const int64_t s = s0 + threadIdx.x;
     int32_t n = 0;
     bool keep = false;
     if (s < e) {
-      n = tmp.n[s];
+      n = int32_t(tmp.rec[s * kRecWords + kRecN]);
       keep = n >= min_hits;
     }
     int64_t tt, th;
     const int64_t pt = block_exclusive_scan(keep ? 1 : 0, lds, &tt);
     const int64_t ph = block_exclusive_scan(keep ? n : 0, lds, &th);
-    bool fits = false;
     if (keep) {
       const int64_t ti = t_run + pt, hb = h_run + ph;
-      fits = ti < o.cap_tracks && hb + n <= o.cap_hits;
+      const bool fits = ti < o.cap_tracks && hb + n <= o.cap_hits;
+      const uint4* r4 = reinterpret_cast<const uint4*>(tmp.rec + s * kRecWords);
+      const uint4 a0 = r4[0], a1 = r4[1], a2 = r4[2], a3 = r4[3], a4 = r4[4], a5 = r4[5], a6 = r4[6];
       if (fits) {
-        o.unit[ti] = tmp.unit[s];
+        o.unit[ti] = int32_t(a4.w);
         o.start[ti] = starts[s];
         o.n_hits[ti] = n;
         o.hit_begin[ti] = hb;
         o.ndf[ti] = 2 * n - 5;
-        o.x_ref[ti] = tmp.f[0 * C + s];
-        for (int j = 0; j < 5; ++j) o.param[ti * 5 + j] = tmp.f[(1 + j) * C + s];
-        const float cyy = tmp.f[6 * C + s], csy = tmp.f[7 * C + s], css = tmp.f[8 * C + s];
-        const float cwy = tmp.f[9 * C + s], cws = tmp.f[10 * C + s], cww = tmp.f[11 * C + s];
-        const float czz = tmp.f[12 * C + s], ctz = tmp.f[13 * C + s], ctt = tmp.f[14 * C + s];
+        o.x_ref[ti] = __uint_as_float(a0.x);
+        float* pp = o.param + ti * 5;
+        pp[0] = __uint_as_float(a0.y);
+        pp[1] = __uint_as_float(a0.z);
+        pp[2] = __uint_as_float(a0.w);
+        pp[3] = __uint_as_float(a1.x);
+        pp[4] = __uint_as_float(a1.y);
+        const float cyy = __uint_as_float(a1.z), csy = __uint_as_float(a1.w);
+        const float css = __uint_as_float(a2.x), cwy = __uint_as_float(a2.y);
+        const float cws = __uint_as_float(a2.z), cww = __uint_as_float(a2.w);
+        const float czz = __uint_as_float(a3.x), ctz = __uint_as_float(a3.y);
+        const float ctt = __uint_as_float(a3.z);
         const float cv[15] = {cyy, 0.0f, czz, csy, 0.0f, css, 0.0f, ctz,
                               0.0f, ctt, cwy, 0.0f, cws, 0.0f, cww};
         for (int j = 0; j < 15; ++j) o.cov[ti * 15 + j] = cv[j];
-        o.chi2[ti] = tmp.f[15 * C + s];
+        o.chi2[ti] = __uint_as_float(a3.w);
       }
       s_slot[pt] = fits ? int32_t(s - s0) : -1;
       s_hb[pt] = hb;
       s_n[pt] = n;
-      s_nu[pt] = tmp.n_up[s];
+      s_nu[pt] = int32_t(a4.y);
+      s_mask[0][pt] = a5.x;
+      s_mask[1][pt] = a5.y;
+      s_mask[2][pt] = a5.z;
+      s_mask[3][pt] = a5.w;
+      s_mask[4][pt] = a6.x;
     }
     __syncthreads();
-    // hit lists: down-phase clusters sit at the end of the slot in ascending
-    // row order, up-phase clusters at its start
+    // Hit lists sorted by row: the inward phase reversed, then the outward
+    // phase; the row of the j-th hit is the j-th set bit of the row mask.
     for (int q = wid; q < int(tt); q += nw) {
       const int32_t sl = s_slot[q];
       if (sl < 0) continue;
       const int64_t ss = s0 + sl;
       const int nn = s_n[q], nu = s_nu[q], nd = nn - nu;
       const int64_t hb = s_hb[q];
-      const int32_t* hs = tmp.hit + ss * n_rows;
-      const uint8_t* rs = tmp.hrow + ss * n_rows;
+      const int32_t* hs = tmp.hit + ss * tmp.stride;
       for (int j = lane_id(); j < nn; j += kWave) {
-        const int src = j < nd ? n_rows - nd + j : j - nd;
+        const int src = j < nd ? nu + (nd - 1 - j) : j - nd;
         o.hit_id[hb + j] = hs[src];
-        o.hit_row[hb + j] = rs[src];
+      }
+      uint32_t m[kMaskWords];
+      int below[kMaskWords];
+      int acc = 0;
+#pragma unroll
+      for (int w = 0; w < kMaskWords; ++w) {
+        m[w] = s_mask[w][q];
+        below[w] = acc;
+        acc += __popc(m[w]);
+      }
+#pragma unroll
+      for (int w = 0; w < kMaskWords; w += 2) {
+        // lanes 0-31 take word w, lanes 32-63 word w+1
+        const int ww = w + (lane_id() >> 5);
+        if (ww < kMaskWords) {
+          const int bit = lane_id() & 31;
+          const uint32_t mw = ww == 0 ? m[0] : ww == 1 ? m[1] : ww == 2 ? m[2] : ww == 3 ? m[3] : m[4];
+          const int bw = ww == 0 ? below[0] : ww == 1 ? below[1] : ww == 2 ? below[2] : ww == 3 ? below[3] : below[4];
+          if ((mw >> bit) & 1u) {
+            const int rank = bw + __popc(mw & ((1u << bit) - 1u));
+            o.hit_row[hb + rank] = uint8_t(ww * 32 + bit);
+          }
+        }
       }
     }
     __syncthreads();

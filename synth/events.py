@@ -107,14 +107,14 @@ def helix_crossings(tr: Tracks, distortion: RadialDistortion | None = None,
     A helix is followed for at most one full turn in the transverse plane
     (outgoing and returning leg), until it reaches the outer radius, and while
     |z| <= z_max.  Returns a dict of arrays over crossings (numpy, or torch
-    tensors on ``device``): track, sector, row, y (local), z, psi (turning
-    angle from the vertex).
+    tensors on ``device``): track, sector, row, y (local, as measured), z, psi
+    (turning angle from the vertex), y_true (local y of the undistorted point).
     """
     dt = torch.float64
     xr = torch.tensor(G.row_x_f64(), dtype=dt, device=device)          # [152]
     tanh = G.tan_half_opening()
     kap = G.C_LIGHT_GEV * G.BZ_TESLA
-    out = {k: [] for k in ("track", "sector", "row", "y", "z", "psi")}
+    out = {k: [] for k in ("track", "sector", "row", "y", "z", "psi", "y_true")}
     n = len(tr)
     for c0 in range(0, n, chunk):
         sl = slice(c0, min(n, c0 + chunk))
@@ -157,7 +157,7 @@ def helix_crossings(tr: Tracks, distortion: RadialDistortion | None = None,
                 continue
             ti, si, ri = idx
             if distortion is not None:
-                Yd, zd, psid, okd = _distorted_crossing(
+                Yd, zd, psid, okd, Yt = _distorted_crossing(
                     xr[ri], cxl[ti, si], cyl[ti, si], R[ti], q[ti], theta0[ti], alpha[si],
                     vz[ti], tl[ti], br, distortion)
                 okd = (okd & (Yd.abs() <= xr[ri] * tanh) & (psid > 0.0)
@@ -165,21 +165,24 @@ def helix_crossings(tr: Tracks, distortion: RadialDistortion | None = None,
                        & ((zd >= 0.0) == side_a[ti]))
                 sel = okd.nonzero(as_tuple=True)[0]
                 ti, si, ri = ti[sel], si[sel], ri[sel]
-                Yv, zv, pv = Yd[sel], zd[sel], psid[sel]
+                Yv, zv, pv, Yt = Yd[sel], zd[sel], psid[sel], Yt[sel]
             else:
                 Yv, zv, pv = Y[idx], z[idx], psi[idx]
+                Yt = Yv
             out["track"].append(ti + c0)
             out["sector"].append(sec[ti, si])
             out["row"].append(ri)
             out["y"].append(Yv)
             out["z"].append(zv)
             out["psi"].append(pv)
+            out["y_true"].append(Yt)
     res = {}
     for k, v in out.items():
         if v:
             res[k] = torch.cat(v)
         else:
-            res[k] = torch.zeros(0, dtype=dt if k in ("y", "z", "psi") else torch.int64, device=device)
+            res[k] = torch.zeros(0, dtype=dt if k in ("y", "z", "psi", "y_true") else torch.int64,
+                                 device=device)
     if as_numpy:
         res = {k: v.cpu().numpy() for k, v in res.items()}
     return res
@@ -190,7 +193,8 @@ def _distorted_crossing(x_row, cxl, cyl, R, q, theta0, alpha, vz, tl, br, dist, 
 
     Fixed-point iteration on the plane X the true helix crosses:
     X <- x_row / (1 - delta(r)/r), r the radius of the crossing with plane X.
-    Returns the measured local y (the image), z, turning angle and validity.
+    Returns the measured local y (the image), z, turning angle, validity and
+    the true local y.
     """
     X = x_row.clone()
     ok = torch.ones_like(X, dtype=torch.bool)
@@ -210,7 +214,7 @@ def _distorted_crossing(x_row, cxl, cyl, R, q, theta0, alpha, vz, tl, br, dist, 
     th = torch.atan2(Y - cyl, d) + alpha
     psi = torch.remainder(q * (theta0 - th), 2.0 * math.pi)
     z = vz + tl * R * psi
-    return Y * scale, z, psi, ok
+    return Y * scale, z, psi, ok, Y
 
 
 # ----------------------------------------------------------------------------
@@ -229,7 +233,7 @@ class ClusterSet:
     y: np.ndarray                    # float32 [N]
     z: np.ndarray                    # float32 [N]
     truth_track: np.ndarray          # int64 [N], -1 for noise
-    truth_y: np.ndarray              # float64 [N] position before smearing
+    truth_y: np.ndarray              # float64 [N] true local y (before distortion and smearing)
     truth_z: np.ndarray
     truth_psi: np.ndarray            # float64 [N] turning angle from the vertex (nan for noise)
     tracks: Tracks
@@ -272,7 +276,8 @@ def build_clusters(tracks: Tracks, sectors, rng_seed, smear_sigma=0.1, noise_fra
     trk = cr["track"][keep]
     unit = unit[keep]
     row = cr["row"][keep].to(torch.int64)
-    ty = cr["y"][keep]
+    my0 = cr["y"][keep]
+    ty = cr["y_true"][keep]
     tz = cr["z"][keep]
     tpsi = cr["psi"][keep]
     if drift_offsets:
@@ -283,10 +288,10 @@ def build_clusters(tracks: Tracks, sectors, rng_seed, smear_sigma=0.1, noise_fra
         tz = tz - sgn * G.DRIFT_CM_PER_US * t_us[trk]
     n_sig = int(trk.numel())
     if smear_sigma > 0:
-        my = ty + smear_sigma * torch.randn(n_sig, generator=gen, device=dev, dtype=dt)
+        my = my0 + smear_sigma * torch.randn(n_sig, generator=gen, device=dev, dtype=dt)
         mz = tz + smear_sigma * torch.randn(n_sig, generator=gen, device=dev, dtype=dt)
     else:
-        my, mz = ty.clone(), tz.clone()
+        my, mz = my0.clone(), tz.clone()
 
     n_noise = int(round(noise_frac * n_sig))
     if n_noise:

@@ -44,7 +44,7 @@ def test_host_argument_checks(lib):
     g = px.Geometry(3, ctypes.cast(xs, ctypes.POINTER(ctypes.c_float)), 0.17, 0.5)
     bad = px.MethodParams(sinphi_max=1.5).c_struct()
     assert lib.tpcx_create(ctypes.byref(g), ctypes.byref(bad), None, ctypes.byref(h)) == px.TPCX_E_ARG
-    t = px.Tuning(2.0, 0, 256, 256, 16)  # zero z bins
+    t = px.Tuning(2.0, 0, 256, 16)  # zero z bins
     assert lib.tpcx_create(ctypes.byref(g), ctypes.byref(p), ctypes.byref(t), ctypes.byref(h)) == px.TPCX_E_ARG
     assert lib.tpcx_workspace_bytes(None, 1, 10, 1) == 0
     assert lib.tpcx_track(None, None, None, 0, 0, None, None, None) == px.TPCX_E_ARG

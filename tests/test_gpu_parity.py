@@ -51,7 +51,7 @@ def test_results_do_not_depend_on_search_grid(nz, bin_y):
     print(f"case: grid nz={nz} bin_y={bin_y}", flush=True)
     t = px.default_tuning(1, 20000)
     t.n_zbins, t.bin_y = nz, bin_y
-    t.construct_grid, t.construct_block = 3, 64
+    t.construct_grid = 3
     _full_parity(synth.single_sector(seed=5), tuning=t)
 
 

@@ -1,0 +1,127 @@
+"""Refit through the distortion map and its hand-written adjoint, on the GPU,
+against the FP64 oracle (refit chi2; forward-mode gradient).
+
+The refit input is the oracle's own tracklet list (clusters, rows, seeds), so
+no value computed by the HIP path feeds the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import geometry as G
+
+from gpu_helpers import make_tracker
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n_primaries=2500, stride=1, seed=5):
+    cs = synth.central_event(seed=seed, n_primaries=n_primaries, distortion=synth.RadialDistortion())
+    k = oracle.kept_tracklets(oracle.track(cs))
+    tk = oracle.select_tracks(k, 20)
+    if stride > 1:
+        tk = oracle.select_tracks(tk, 20, index=np.arange(0, len(tk["n"]), stride))
+    return cs, tk
+
+
+def _job(cs, tk, tracker=None):
+    import torch
+
+    import paper_2601_20569_amd as px
+    dev = torch.device("cuda")
+    tr = tracker or make_tracker()
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    alpha = G.sector_alpha(cs.unit_sector).astype(np.float32)
+    job = px.RefitJob(tr, T(tk["hit_begin"], torch.int64), T(tk["hits"], torch.int32),
+                      T(tk["rows"], torch.uint8), T(tk["unit"], torch.int32),
+                      T(np.asarray(tk["param"], np.float32), torch.float32), T(cs.y, torch.float32),
+                      T(cs.z, torch.float32), T(alpha, torch.float32))
+    return job, tr
+
+
+def _theta(kind, n):
+    if kind == "zero":
+        return np.zeros(n)
+    if kind == "random":
+        return np.random.default_rng(3).normal(0.0, 0.05, n)
+    from test_refit_oracle import inverse_radial_correction_map
+    return inverse_radial_correction_map(synth.RadialDistortion())
+
+
+@pytest.mark.parametrize("kind", ["zero", "random", "inverse"])
+def test_refit_chi2_matches_fp64(kind):
+    import torch
+    print(f"case: refit forward, theta={kind}", flush=True)
+    cs, tk = _case()
+    job, _ = _job(cs, tk)
+    theta = _theta(kind, oracle.map_ncoef())
+    want, ok_ref = oracle.refit(cs, tk, theta)
+    chi2 = job.forward(torch.as_tensor(theta, dtype=torch.float32, device="cuda")).cpu().numpy()
+    ok = job.ok[:job.n_tracks].cpu().numpy().astype(bool)
+    assert len(chi2) > 1000
+    # a guard may trip on one side only right at its threshold
+    assert (ok == ok_ref).mean() > 0.999
+    both = ok & ok_ref
+    rel = np.abs(chi2[both] - want[both]) / np.maximum(want[both], 1.0)
+    assert rel.max() < 1e-3, rel.max()
+
+
+def test_refit_without_map_equals_zero_map():
+    import torch
+    cs, tk = _case(n_primaries=800)
+    job, _ = _job(cs, tk)
+    a = job.forward(None).cpu().numpy().copy()
+    b = job.forward(torch.zeros(oracle.map_ncoef(), dtype=torch.float32, device="cuda")).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("kind", ["zero", "random", "inverse"])
+def test_adjoint_matches_fp64_gradient(kind):
+    import torch
+    print(f"case: refit adjoint, theta={kind}", flush=True)
+    cs, tk = _case(stride=4)
+    job, _ = _job(cs, tk)
+    theta = _theta(kind, oracle.map_ncoef())
+    job.forward(torch.as_tensor(theta, dtype=torch.float32, device="cuda"))
+    ok = job.ok[:job.n_tracks].cpu().numpy().astype(bool)
+    _, ok_ref = oracle.refit(cs, tk, theta)
+    w = np.random.default_rng(5).uniform(0.5, 1.5, job.n_tracks) * (ok & ok_ref)
+    g = job.backward(torch.as_tensor(w, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    want = oracle.refit_grad(cs, tk, theta, dL_dchi2=w)
+    err = np.linalg.norm(g - want) / np.linalg.norm(want)
+    assert err < 1e-3, err
+    # coefficients without any contributing cluster are exactly zero
+    assert (g[want == 0.0] == 0.0).all()
+    big = np.abs(want) > 1e-2 * np.abs(want).max()
+    assert (np.abs(g[big] - want[big]) <= 1e-2 * np.abs(want[big])).all()
+
+
+def test_adjoint_is_deterministic_and_linear_in_weights():
+    import torch
+    cs, tk = _case(n_primaries=1500)
+    job, _ = _job(cs, tk)
+    th = torch.as_tensor(_theta("random", oracle.map_ncoef()), dtype=torch.float32, device="cuda")
+    job.forward(th)
+    w = torch.ones(job.n_tracks, dtype=torch.float32, device="cuda") * job.ok[:job.n_tracks].float()
+    a = job.backward(w).cpu().numpy()
+    b = job.backward(w).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    c = job.backward(2.0 * w).cpu().numpy()
+    np.testing.assert_allclose(c, 2.0 * a, rtol=1e-6, atol=1e-6 * np.abs(a).max())
+
+
+def test_autograd_function_uses_the_adjoint():
+    import torch
+
+    import paper_2601_20569_amd as px
+    cs, tk = _case(n_primaries=1500)
+    job, _ = _job(cs, tk)
+    theta = torch.as_tensor(_theta("random", oracle.map_ncoef()), dtype=torch.float32,
+                            device="cuda").requires_grad_(True)
+    chi2 = px.refit_chi2(theta, job)
+    ok = job.ok[:job.n_tracks].float()
+    loss = (chi2 * ok).sum()
+    (g,) = torch.autograd.grad(loss, theta)
+    want = job.backward(ok)
+    np.testing.assert_array_equal(g.cpu().numpy(), want.cpu().numpy())
