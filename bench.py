@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of per-sector TPC track finding on one MI355X.
 
-One step is one pass of the whole tracking path (search-grid build, neighbour
-finder, cleaning and start hits, tracklet constructor, output compaction) over
-one synthetic input already resident in HBM.  Prints one JSON line with the
-clusters/s, the roofline position of the dominant stage (timed with HIP events
-recorded by the library on its stream) and the CPU oracle timed on a bounded
+Default workload ("batched"): 16 synthetic time-frame slices (32-160 Pb-Pb
+collisions each, overlapped in drift time, radial space-charge distortion),
+all 576 sector units tracked plus the refit of every tracklet with at least 20
+clusters through a distortion-correction map, as one HIP graph.  One step is
+one replay of that graph with the inputs resident in HBM.
+
+The JSON line also carries: the plain form (one tpcx_track call per slice),
+the adjoint refit (forward + hand-written backward) on a central event, the
+roofline position of the dominant kernel (HIP events recorded by the library
+on its stream around every stage), and the CPU oracle timed on a bounded
 sample of the same input.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload timeframe|central|single]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload batched|timeframe|central|single]
 """
 from __future__ import annotations
 
@@ -36,43 +42,135 @@ B_CON_PER_ATTACHED = 5         # write id and row of every attached cluster
 B_OUT_PER_START = 4            # read n
 B_OUT_PER_TRACK = 88 + 104     # read the record, write the output record
 B_OUT_PER_HIT = 10             # read and write id + row
+B_REFIT_PER_HIT = 5 + 8 + 16   # read id + row, measured y, z; write the corrected cluster
+B_REFIT_PER_TRACK = 20 + 8 + 64  # seed, counts, result; one checkpoint per 16 clusters ~ 64 B
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_input(workload, device):
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def gen_batch(device):
+    """16 slices, generated one at a time, packed unit-major on the device."""
+    import numpy as np
+    import torch
+
     import synth
-    if workload == "timeframe":
-        return synth.timeframe_slice(seed=3000, device=device), dict(
-            workload="timeframe-slice", collisions=128, seed=3000)
-    if workload == "central":
-        return synth.central_event(seed=2, device=device), dict(workload="central-event", seed=2)
-    return synth.single_sector(seed=1, device=device), dict(workload="single-sector", seed=1)
+    ncoll = synth.slice_batch_collisions(seed=4000, n_slices=16)
+    ys, zs, rbs, sectors, sizes, first = [], [], [], [], [], None
+    off = 0
+    for i, nc in enumerate(ncoll):
+        cs = synth.timeframe_slice(seed=4000 + i, n_collisions=nc, device=device, truth=(i == 0))
+        if i == 0:
+            first = cs
+        ys.append(torch.as_tensor(cs.y, device=device))
+        zs.append(torch.as_tensor(cs.z, device=device))
+        rbs.append(cs.row_begin[:-1] + off)
+        sectors.append(cs.unit_sector)
+        sizes.append((off, cs.n_clusters, cs.row_begin.copy()))
+        off += cs.n_clusters
+        log(f"slice {i}: {nc} collisions, {cs.n_clusters} clusters")
+    rb = np.concatenate(rbs + [np.array([off], np.int64)])
+    y = torch.cat(ys)
+    z = torch.cat(zs)
+    del ys, zs
+    return dict(rb=torch.as_tensor(rb, device=device), y=y, z=z, n=off,
+                n_units=len(rb) - 1 - 0, sectors=np.concatenate(sectors), slices=sizes,
+                first=first, ncoll=ncoll)
+
+
+def make_tracker(n_units, n):
+    import paper_2601_20569_amd as px
+    from synth import geometry as G
+    tuning = px.default_tuning(n_units, n)
+    return px.SectorTracker(G.row_x(), G.tan_half_opening(), G.BZ_TESLA, tuning=tuning)
+
+
+def size_run(tr, rb, y, z, n_units):
+    """Required capacities from one tracking call (retries on overflow)."""
+    n = int(y.numel())
+    res = tr.track(rb, y, z, n_units, cap_start=max(1024, n // 16), cap_tracks=max(1024, n // 16),
+                   cap_hits=max(4096, 3 * n))
+    out = (res["n_start"], len(res["n_hits"]), len(res["hit_id"]))
+    del res
+    return out
 
 
 def cpu_baseline(cs, n_units_sample, threads):
     """The oracle (float decisions) on the first units of the same input."""
     import oracle
-    lo, hi = 0, min(cs.n_units, n_units_sample)
     from synth import geometry as G
+    lo, hi = 0, min(cs.n_units, n_units_sample)
     n = int(cs.row_begin[hi * G.N_ROWS] - cs.row_begin[lo * G.N_ROWS])
     t0 = time.perf_counter()
     res = oracle.track(cs, units=(lo, hi), n_threads=threads)
     dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="clusters/s", cores=threads, kind="oracle",
-                sample=f"sectors {lo}-{hi - 1} of the same input: {n} clusters, {dt:.1f} s"), res, n
+                sample=f"sectors {lo}-{hi - 1} of the first slice: {n} clusters, {dt:.1f} s"), res
+
+
+def timed(fn, steps, stream=None):
+    import torch
+    s = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sync()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def adjoint_form(steps):
+    """Refit forward + hand-written backward on the distorted central event."""
+    import numpy as np
+    import torch
+
+    import paper_2601_20569_amd as px
+    import synth
+    from synth import geometry as G
+    dev = torch.device("cuda", 0)
+    cs = synth.central_event(seed=5, distortion=synth.RadialDistortion(), device="cuda")
+    tr = make_tracker(cs.n_units, cs.n_clusters)
+    y = torch.as_tensor(cs.y, device=dev)
+    z = torch.as_tensor(cs.z, device=dev)
+    res = tr.track(torch.as_tensor(cs.row_begin, device=dev), y, z, cs.n_units)
+    keep = (res["n_hits"] >= 20).nonzero().squeeze(1)
+    n_hits = res["n_hits"][keep].to(torch.int64)
+    hb = torch.zeros(len(keep) + 1, dtype=torch.int64, device=dev)
+    hb[1:] = torch.cumsum(n_hits, 0)
+    src = torch.repeat_interleave(res["hit_begin"][keep], n_hits) + (
+        torch.arange(int(hb[-1]), device=dev) - torch.repeat_interleave(hb[:-1], n_hits))
+    job = px.RefitJob(tr, hb, res["hit_id"][src].contiguous(), res["hit_row"][src].contiguous(),
+                      res["unit"][keep].contiguous(), res["param"][keep].contiguous(), y, z,
+                      torch.as_tensor(G.sector_alpha(cs.unit_sector).astype(np.float32), device=dev))
+    theta = torch.as_tensor(np.random.default_rng(1).normal(0.0, 0.05, px.MAP_NCOEF).astype(np.float32),
+                            device=dev)
+    job.forward(theta)
+    w = job.ok[:job.n_tracks].float()
+    job.backward(w)
+    fwd = timed(lambda: job.forward(theta), steps)
+    bwd = timed(lambda: job.backward(w), steps)
+    return dict(workload="central-event+distortion", tracks=job.n_tracks, hits=job.n_hits,
+                forward_ms=round(fwd, 4), backward_ms=round(bwd, 4),
+                backward_over_forward=round(bwd / fwd, 3))
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="timeframe", choices=["timeframe", "central", "single"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "timeframe", "central", "single"])
     ap.add_argument("--cpu-units", type=int, default=0, help="sectors in the oracle sample (0: one per thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-forms", action="store_true", help="skip the plain and adjoint comparisons")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -83,52 +181,98 @@ def main():
     import numpy as np
     import torch
 
-    import paper_2601_20569_amd as px
+    import synth
     from synth import geometry as G
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    log(f"generating {args.workload} input on {dev}")
     t0 = time.perf_counter()
-    cs, cfg = make_input(args.workload, "cuda")
-    N = cs.n_clusters
-    log(f"input: {N} clusters in {cs.n_units} sectors ({time.perf_counter() - t0:.1f} s)")
-    rb = torch.as_tensor(cs.row_begin, device=dev)
-    y = torch.as_tensor(cs.y, device=dev)
-    z = torch.as_tensor(cs.z, device=dev)
+    if args.workload == "batched":
+        log("generating 16 time-frame slices on the GPU")
+        B = gen_batch("cuda")
+        rb, y, z, N, U = B["rb"], B["y"], B["z"], B["n"], len(B["sectors"])
+        first = B["first"]
+        cfg = dict(workload="timeframe-slice-batch", slices=16, collisions=int(sum(B["ncoll"])),
+                   seeds="4000-4015", form="batched graph: tracking + refit of tracklets >= 20 clusters")
+    else:
+        gen = {"timeframe": lambda: synth.timeframe_slice(seed=3000, device="cuda"),
+               "central": lambda: synth.central_event(seed=2, device="cuda"),
+               "single": lambda: synth.single_sector(seed=1, device="cuda")}[args.workload]
+        first = gen()
+        rb = torch.as_tensor(first.row_begin, device=dev)
+        y = torch.as_tensor(first.y, device=dev)
+        z = torch.as_tensor(first.z, device=dev)
+        N, U = first.n_clusters, first.n_units
+        cfg = dict(workload=first.meta["workload"], seed=first.meta["seed"],
+                   form="batched graph: tracking + refit of tracklets >= 20 clusters")
+        B = dict(sectors=first.unit_sector, slices=[(0, N, first.row_begin.copy())])
+    log(f"input: {N} clusters in {U} sector units ({time.perf_counter() - t0:.1f} s)")
 
-    tuning = px.default_tuning(cs.n_units, N)
-    tr = px.SectorTracker(G.row_x(), G.tan_half_opening(), G.BZ_TESLA, tuning=tuning)
-    # size the outputs from one call, then reuse the buffers for every step
-    first = tr.track(rb, y, z, cs.n_units)
-    n_start, n_tracks, n_hits = first["n_start"], len(first["n_hits"]), len(first["hit_id"])
-    del first
-    bufs = tr.allocate(cs.n_units, N, cap_start=max(n_start, 1), cap_tracks=max(n_tracks, 1),
-                       cap_hits=max(n_hits, 1))
-    log(f"tracklets: {n_start} start hits, {n_tracks} kept, {n_hits} attached clusters; "
-        f"workspace {bufs['ws_bytes'] / 2**30:.2f} GiB")
-    for _ in range(args.warmup):
-        tr.track_into(rb, y, z, cs.n_units, bufs)
-    torch.cuda.synchronize()
-    log(f"warm-up done ({args.warmup} steps)")
+    tr = make_tracker(U, N)
+    n_start, n_tracks, n_hits = size_run(tr, rb, y, z, U)
+    log(f"tracklets: {n_start} start hits, {n_tracks} kept, {n_hits} attached clusters")
+    bufs = tr.allocate_batched(U, N, cap_start=n_start + 1, cap_tracks=n_tracks + 1, cap_hits=n_hits + 1)
+    alpha = torch.as_tensor(G.sector_alpha(B["sectors"]).astype(np.float32), device=dev)
+    theta = torch.as_tensor(np.random.default_rng(1).normal(0.0, 0.05, 36720).astype(np.float32),
+                            device=dev)
+    stream = torch.cuda.Stream()
+    log(f"workspace {bufs['ws_bytes'] / 2**30:.1f} GiB; capturing the graph")
 
-    tr.timing_enable(args.steps)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        tr.track_into(rb, y, z, cs.n_units, bufs)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    def step():
+        tr.track_batched_into(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta)
+
+    with torch.cuda.stream(stream):
+        for _ in range(max(1, args.warmup)):
+            step()
+        sync()
+        counts = bufs["out"]["counts"].cpu().tolist()
+        assert counts[3] == 0 and counts[0] == n_start and counts[1] == n_tracks, counts
+        n_refit = int(bufs["refit_ok"][:n_tracks].sum())
+        log(f"warm-up done; {n_refit} tracklets refitted")
+        ms = timed(step, args.steps, stream)
+        log(f"timed {args.steps} graph replays: {ms:.3f} ms/step")
+        # per-stage kernel times: the same sequence launched directly with events
+        tr.timing_enable(args.steps)
+        for _ in range(args.steps):
+            step()
+        sync()
     stage_ms, ncalls = tr.timing_read()
     stage_ms = {k: v / max(ncalls, 1) for k, v in stage_ms.items()}
-    counts = bufs["out"]["counts"].cpu().tolist()
-    assert counts[3] == 0 and counts[0] == n_start, counts
-    log(f"timed {args.steps} steps: {ms:.3f} ms/step; stages (ms) " +
-        ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    log("stages (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+    del bufs
+    torch.cuda.empty_cache()
+
+    forms = {}
+    if not args.no_extra_forms:
+        # plain form: one tpcx_track call per slice
+        slices = B["slices"]
+        if len(slices) > 1:
+            caps = []
+            views = []
+            for off, n, rb_s in slices:
+                rbt = torch.as_tensor(rb_s, device=dev)
+                views.append((rbt, y[off:off + n], z[off:off + n]))
+            mx = max(n for _, n, _ in slices)
+            pbufs = tr.allocate(36, mx, cap_start=n_start + 1, cap_tracks=n_tracks + 1,
+                                cap_hits=n_hits + 1)
+
+            def plain_all():
+                for rbt, ys, zs in views:
+                    tr.track_into(rbt, ys, zs, 36, pbufs)
+
+            plain_all()
+            plain_ms = timed(plain_all, args.steps)
+            forms["plain_per_slice_ms"] = round(plain_ms, 3)
+            forms["batched_ms"] = round(ms, 3)
+            forms["batched_speedup_vs_plain"] = round(plain_ms / ms, 3)
+            log(f"plain, one call per slice: {plain_ms:.3f} ms per batch (tracking only)")
+            del pbufs, views
+            torch.cuda.empty_cache()
+        adj = adjoint_form(args.steps)
+        forms["adjoint"] = adj
+        log(f"adjoint refit: forward {adj['forward_ms']} ms, backward {adj['backward_ms']} ms "
+            f"({adj['tracks']} tracks)")
 
     # ----- CPU baseline (oracle) on a bounded sample of the same input
     cpu = None
@@ -137,7 +281,7 @@ def main():
         threads = min(16, os.cpu_count() or 1)
         nu = args.cpu_units or threads
         log(f"oracle on {nu} sectors with {threads} threads")
-        cpu, ores, n_sample = cpu_baseline(cs, nu, threads)
+        cpu, ores = cpu_baseline(first, nu, threads)
         c = ores["counters"]
         s = max(len(ores["starts"]), 1)
         per_start_con = (B_CON_PER_START * s + B_CON_PER_CHAIN_HIT * c["chain"] +
@@ -153,9 +297,10 @@ def main():
         "starts": B_STARTS_PER_CLUSTER * N + B_STARTS_PER_START * n_start,
         "construct": (per_start_con * n_start) if per_start_con else None,
         "compact": B_OUT_PER_START * n_start + B_OUT_PER_TRACK * n_tracks + B_OUT_PER_HIT * n_hits,
+        "refit": None,
     }
     dom = max(stage_ms, key=stage_ms.get)
-    b = stage_bytes[dom]
+    b = stage_bytes.get(dom)
     roof = None
     if b is not None:
         gbs = b / (stage_ms[dom] * 1e-3) / 1e9
@@ -167,10 +312,10 @@ def main():
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                 data="synthetic",
-                config=dict(cfg, form="plain", clusters=N, units=cs.n_units, start_hits=n_start,
-                            tracklets=n_tracks, attached=n_hits),
+                config=dict(cfg, clusters=N, units=U, start_hits=n_start, tracklets=n_tracks,
+                            attached=n_hits),
                 roofline=roof, cpu_baseline=cpu,
-                stages_ms={k: round(v, 4) for k, v in stage_ms.items()})
+                stages_ms={k: round(v, 4) for k, v in stage_ms.items()}, forms=forms)
     print(json.dumps(line), flush=True)
 
 

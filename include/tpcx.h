@@ -243,11 +243,14 @@ tpcx_status tpcx_track_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws,
 #define TPCX_STAGE_STARTS 2     /* cleaning, start flags, ordered compaction */
 #define TPCX_STAGE_CONSTRUCT 3  /* tracklet constructor */
 #define TPCX_STAGE_COMPACT 4    /* ordered compaction of the kept tracklets */
-#define TPCX_N_STAGES 5
+#define TPCX_STAGE_REFIT 5      /* refit (batched form only; zero otherwise) */
+#define TPCX_N_STAGES 6
 
 /* Record HIP events on the call's stream around every stage of the next
- * max_calls tpcx_track calls (max_calls = 0 switches timing off).  Creates the
- * events; call it outside timed or captured regions. */
+ * max_calls tpcx_track / tpcx_track_batched calls (max_calls = 0 switches
+ * timing off).  While timing slots are left, tpcx_track_batched launches its
+ * sequence directly (same kernels and launch shapes) instead of replaying the
+ * graph.  Creates the events; call it outside timed or captured regions. */
 tpcx_status tpcx_timing_enable(tpcx_ctx* ctx, int32_t max_calls);
 
 /* Waits for the recorded events and writes, per stage, the summed elapsed

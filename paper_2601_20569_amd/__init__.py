@@ -79,7 +79,7 @@ class Debug(ctypes.Structure):
                 ("starts", ctypes.c_void_p)]
 
 
-STAGES = ("grid", "neighbours", "starts", "construct", "compact")
+STAGES = ("grid", "neighbours", "starts", "construct", "compact", "refit")
 
 _lib = None
 

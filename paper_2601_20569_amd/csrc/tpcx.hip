@@ -112,6 +112,52 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   return L;
 }
 
+struct RefitLayout {
+  RefitWs ws;
+  int32_t* ok;
+  size_t bytes;
+};
+
+RefitLayout carve_refit(void* base, int64_t n_tracks, int64_t n_hits) {
+  Carver cv{static_cast<char*>(base)};
+  RefitLayout L{};
+  L.ws.xyz = cv.take<float>(4 * std::max<int64_t>(n_hits, 1));
+  L.ws.ckpt = cv.take<float>(int64_t(kCkptFloats) * (n_hits / kCkpt + n_tracks + 1));
+  L.ws.n_lanes = std::max<int64_t>(n_tracks, 1);
+  L.ws.scratch = cv.take<float>(L.ws.n_lanes * kCkpt * kCkptFloats);
+  L.ws.acc = cv.take<int64_t>(kMapNCoef);
+  L.ok = cv.take<int32_t>(n_tracks);
+  L.bytes = cv.off;
+  return L;
+}
+
+bool refit_args_ok(const tpcx_ctx* c, const tpcx_refit_in* in) {
+  if (!c || !in || in->n_tracks < 0) return false;
+  if (in->n_tracks > 0 && (!in->hit_begin || !in->hit_id || !in->hit_row || !in->unit || !in->seed ||
+                           !in->y || !in->z || !in->unit_alpha))
+    return false;
+  return true;
+}
+
+RefitIn refit_view(const tpcx_ctx* c, const tpcx_refit_in* in) {
+  RefitIn r;
+  r.n_tracks = in->n_tracks;
+  r.n_tracks_dev = nullptr;
+  r.status_dev = nullptr;
+  r.n_hit = nullptr;
+  r.min_hits = 2;
+  r.hit_begin = in->hit_begin;
+  r.hit_id = in->hit_id;
+  r.hit_row = in->hit_row;
+  r.unit = in->unit;
+  r.seed = in->seed;
+  r.y = in->y;
+  r.z = in->z;
+  r.unit_alpha = in->unit_alpha;
+  r.row_x = c->d_row_x;
+  return r;
+}
+
 // The bin counters of one row live in LDS during the grid build.
 constexpr int kMaxRowBins = 16384;
 
@@ -354,6 +400,27 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   mark(5);
 }
 
+void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_tracks* out,
+                         const tpcx_batch_refit* refit, const RefitLayout& RL, hipStream_t stream) {
+  RefitIn r;
+  r.n_tracks = out->cap_tracks;
+  r.n_tracks_dev = out->counts + 1;
+  r.status_dev = out->counts + 3;
+  r.n_hit = out->n_hits;
+  r.min_hits = refit->min_hits;
+  r.hit_begin = out->hit_begin;
+  r.hit_id = out->hit_id;
+  r.hit_row = out->hit_row;
+  r.unit = out->unit;
+  r.seed = out->param;
+  r.y = in->y;
+  r.z = in->z;
+  r.unit_alpha = refit->unit_alpha;
+  r.row_x = c->d_row_x;
+  hipLaunchKernelGGL(k_refit_fwd, dim3(4 * c->n_cu), dim3(kRefitBlock), 0, stream, r, refit->theta,
+                     c->dp, RL.ws, refit->chi2, refit->ok);
+}
+
 hipEvent_t* next_timing_slot(tpcx_ctx* c) {
   if (c->timing_used >= c->timing_max) return nullptr;
   hipEvent_t* ev = &c->events[size_t(c->timing_used) * (TPCX_N_STAGES + 1)];
@@ -374,7 +441,9 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   const tpcx_tuning t = effective_tuning(c, in->n_units, N);
   const Layout L = carve(c, ws, in->n_units, N, cap_start, t.n_zbins, t.block);
   if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
-  enqueue_track(c, in, L, t, cap_start, out, stream, next_timing_slot(c));
+  hipEvent_t* ev = next_timing_slot(c);
+  enqueue_track(c, in, L, t, cap_start, out, stream, ev);
+  if (ev) (void)hipEventRecord(ev[TPCX_N_STAGES], stream);  // no refit stage here
   if (dbg) {
     if (N > 0 && (dbg->link_up || dbg->link_down || dbg->clean_up || dbg->clean_down))
       hipLaunchKernelGGL(k_links_to_caller, dim3(blocks_for(N, 256)), dim3(256), 0, stream, N,
@@ -395,55 +464,6 @@ tpcx_status tpcx_poll(tpcx_ctx* c, const tpcx_tracks* out, hipStream_t stream) {
   return st ? TPCX_E_CAPACITY : TPCX_OK;
 }
 
-namespace {
-
-struct RefitLayout {
-  RefitWs ws;
-  int32_t* ok;
-  size_t bytes;
-};
-
-RefitLayout carve_refit(void* base, int64_t n_tracks, int64_t n_hits) {
-  Carver cv{static_cast<char*>(base)};
-  RefitLayout L{};
-  L.ws.xyz = cv.take<float>(4 * std::max<int64_t>(n_hits, 1));
-  L.ws.ckpt = cv.take<float>(int64_t(kCkptFloats) * (n_hits / kCkpt + n_tracks + 1));
-  L.ws.n_lanes = std::max<int64_t>(n_tracks, 1);
-  L.ws.scratch = cv.take<float>(L.ws.n_lanes * kCkpt * kCkptFloats);
-  L.ws.acc = cv.take<int64_t>(kMapNCoef);
-  L.ok = cv.take<int32_t>(n_tracks);
-  L.bytes = cv.off;
-  return L;
-}
-
-bool refit_args_ok(const tpcx_ctx* c, const tpcx_refit_in* in) {
-  if (!c || !in || in->n_tracks < 0) return false;
-  if (in->n_tracks > 0 && (!in->hit_begin || !in->hit_id || !in->hit_row || !in->unit || !in->seed ||
-                           !in->y || !in->z || !in->unit_alpha))
-    return false;
-  return true;
-}
-
-RefitIn refit_view(const tpcx_ctx* c, const tpcx_refit_in* in) {
-  RefitIn r;
-  r.n_tracks = in->n_tracks;
-  r.n_tracks_dev = nullptr;
-  r.status_dev = nullptr;
-  r.n_hit = nullptr;
-  r.min_hits = 2;
-  r.hit_begin = in->hit_begin;
-  r.hit_id = in->hit_id;
-  r.hit_row = in->hit_row;
-  r.unit = in->unit;
-  r.seed = in->seed;
-  r.y = in->y;
-  r.z = in->z;
-  r.unit_alpha = in->unit_alpha;
-  r.row_x = c->d_row_x;
-  return r;
-}
-
-}  // namespace
 
 size_t tpcx_refit_workspace_bytes(const tpcx_ctx* c, int64_t n_tracks, int64_t n_hits) {
   if (!c || n_tracks < 0 || n_hits < 0) return 0;
@@ -536,6 +556,13 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   put(&t, sizeof t);
   put(&stream, sizeof stream);
 
+  if (hipEvent_t* ev = next_timing_slot(c)) {
+    // timed run: the same sequence launched directly, with stage events
+    enqueue_track(c, in, L, t, cap_start, out, stream, ev);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, stream);
+    (void)hipEventRecord(ev[TPCX_N_STAGES], stream);
+    return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+  }
   if (!c->graph || key != c->graph_key) {
     if (c->graph) {
       (void)hipGraphExecDestroy(c->graph);
@@ -543,25 +570,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
     enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
-    if (refit) {
-      RefitIn r;
-      r.n_tracks = out->cap_tracks;
-      r.n_tracks_dev = out->counts + 1;
-      r.status_dev = out->counts + 3;
-      r.n_hit = out->n_hits;
-      r.min_hits = refit->min_hits;
-      r.hit_begin = out->hit_begin;
-      r.hit_id = out->hit_id;
-      r.hit_row = out->hit_row;
-      r.unit = out->unit;
-      r.seed = out->param;
-      r.y = in->y;
-      r.z = in->z;
-      r.unit_alpha = refit->unit_alpha;
-      r.row_x = c->d_row_x;
-      hipLaunchKernelGGL(k_refit_fwd, dim3(4 * c->n_cu), dim3(kRefitBlock), 0, stream, r,
-                         refit->theta, c->dp, RL.ws, refit->chi2, refit->ok);
-    }
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, stream);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipStreamEndCapture(stream, &g);
     if (e1 != hipSuccess || !g) return TPCX_E_HIP;

@@ -254,7 +254,7 @@ class ClusterSet:
 
 
 def build_clusters(tracks: Tracks, sectors, rng_seed, smear_sigma=0.1, noise_frac=0.0,
-                   distortion=None, drift_offsets=False, device="cpu", meta=None):
+                   distortion=None, drift_offsets=False, device="cpu", meta=None, truth=True):
     """Turn particles into a ClusterSet over the given sectors (one unit each).
 
     Random numbers for smearing, noise and the in-row order come from a torch
@@ -322,6 +322,10 @@ def build_clusters(tracks: Tracks, sectors, rng_seed, smear_sigma=0.1, noise_fra
     row_begin = np.zeros(len(sectors) * G.N_ROWS + 1, dtype=np.int64)
     np.cumsum(counts.cpu().numpy(), out=row_begin[1:])
     h = lambda t: t[order].cpu().numpy()
+    if not truth:
+        # measured clusters only (large inputs: no per-cluster truth on the host)
+        return ClusterSet(len(sectors), sectors, row_begin, h(my.to(torch.float32)),
+                          h(mz.to(torch.float32)), None, None, None, None, tracks, dict(meta or {}))
     return ClusterSet(len(sectors), sectors, row_begin, h(my.to(torch.float32)),
                       h(mz.to(torch.float32)), h(trk), h(ty), h(tz), h(tpsi), tracks,
                       dict(meta or {}))
@@ -366,7 +370,7 @@ def _event_tracks(rng, n_prim, secondary_frac, t_us):
 
 def timeframe_slice(seed=3000, n_collisions=128, mean_primaries=2500.0, secondary_frac=0.2,
                     noise_frac=0.10, smear_sigma=0.1, rate_per_us=0.05,
-                    distortion=RadialDistortion(), device="cpu"):
+                    distortion=RadialDistortion(), device="cpu", truth=True):
     """Overlapping minimum-bias collisions in continuous drift time.
 
     Collision times form a Poisson process (5 per 100 us); multiplicities are
@@ -380,7 +384,14 @@ def timeframe_slice(seed=3000, n_collisions=128, mean_primaries=2500.0, secondar
     tr = Tracks.concat(parts)
     return build_clusters(tr, np.arange(G.N_SECTORS), int(rc.integers(2**63)), smear_sigma,
                           noise_frac, distortion=distortion, drift_offsets=True, device=device,
-                          meta=dict(workload="timeframe-slice", seed=seed, n_collisions=n_collisions))
+                          meta=dict(workload="timeframe-slice", seed=seed, n_collisions=n_collisions),
+                          truth=truth)
+
+
+def slice_batch_collisions(seed=4000, n_slices=16, lo=32, hi=160):
+    """Collision counts of a batch of time-frame slices: uniform in [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    return [int(v) for v in rng.integers(lo, hi + 1, n_slices)]
 
 
 def exact_tracks(seed, n_tracks=10, pt_range=(0.5, 5.0), eta_range=(0.05, 0.85), sector=0):

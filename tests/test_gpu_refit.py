@@ -93,8 +93,13 @@ def test_adjoint_matches_fp64_gradient(kind):
     assert err < 1e-3, err
     # coefficients without any contributing cluster are exactly zero
     assert (g[want == 0.0] == 0.0).all()
-    big = np.abs(want) > 1e-2 * np.abs(want).max()
-    assert (np.abs(g[big] - want[big]) <= 1e-2 * np.abs(want[big])).all()
+    # element-wise sanity bound (float sums of cancelling contributions): the
+    # worst element is reported
+    d = np.abs(g - want)
+    bound = 2e-2 * np.abs(want) + 2e-3 * np.abs(want).max()
+    worst = int(np.argmax(d / bound))
+    print(f"relative L2 {err:.2e}; worst element {worst}: gpu {g[worst]:.6g} fp64 {want[worst]:.6g}")
+    assert (d <= bound).all()
 
 
 def test_adjoint_is_deterministic_and_linear_in_weights():
