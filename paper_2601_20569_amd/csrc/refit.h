@@ -83,13 +83,27 @@ __device__ __forceinline__ Weights4 weights_lin(float x, float x0, float dx, int
   return W;
 }
 
-// Corrected position of a measured cluster.
+// Corrected position of a measured cluster (x_m, y_m, z_m) in a sector whose
+// centre lies at azimuth alpha.
 struct HitGeom {
   float xm, ym, zm, inv_r, phi;
 };
 
-__device__ __forceinline__ void map_correct(const float* __restrict__ theta, const HitGeom& h,
-                                            float r, float* xc, float* yc, float* zc) {
+__device__ __forceinline__ HitGeom hit_geom(float xm, float ym, float zm, float alpha, float* r) {
+  HitGeom h;
+  h.xm = xm;
+  h.ym = ym;
+  h.zm = zm;
+  *r = sqrtf(xm * xm + ym * ym);
+  h.inv_r = 1.0f / *r;
+  h.phi = alpha + atan2f(ym, xm);
+  return h;
+}
+
+__device__ __forceinline__ float4 correct_cluster(const float* __restrict__ theta, float xm, float ym,
+                                                  float zm, float alpha) {
+  float r;
+  const HitGeom h = hit_geom(xm, ym, zm, alpha, &r);
   float d[3] = {0.0f, 0.0f, 0.0f};
   if (theta) {
     const Weights4 wp = weights_phi(h.phi);
@@ -111,9 +125,8 @@ __device__ __forceinline__ void map_correct(const float* __restrict__ theta, con
       }
     }
   }
-  *xc = h.xm + (d[0] * h.xm - d[1] * h.ym) * h.inv_r;
-  *yc = h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r;
-  *zc = h.zm + d[2];
+  return make_float4(h.xm + (d[0] * h.xm - d[1] * h.ym) * h.inv_r,
+                     h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r, h.zm + d[2], 0.0f);
 }
 
 struct RefitIn {
@@ -139,6 +152,7 @@ struct RefitWs {
   float* scratch;   // [lanes][kCkpt][kCkptFloats] states of the segment in the backward
   int64_t* acc;     // [kMapNCoef] fixed-point gradient accumulators
   int64_t n_lanes;
+  unsigned long long* queue;  // track queue of the filter kernel (zeroed before each launch)
 };
 
 __device__ __forceinline__ int64_t ckpt_base(const RefitIn& in, int64_t t) {
@@ -206,57 +220,124 @@ __device__ __forceinline__ bool refit_step(KState& q, float xc, float yc, float 
   return true;
 }
 
-// Forward refit: one lane per track, grid-stride over the tracks.  Corrected
-// clusters and checkpoints go to the workspace for the backward pass.
-__device__ void refit_track_fwd(const RefitIn& in, int64_t t, const float* __restrict__ theta,
-                                const DevParams& p, const RefitWs& ws, float* __restrict__ chi2_out,
-                                int32_t* __restrict__ ok_out) {
-  const int n = track_size(in, t);
-  if (n < in.min_hits) {
-    chi2_out[t] = 0.0f;
-    ok_out[t] = 0;
-    return;
-  }
-  const int64_t hb = in.hit_begin[t], he = hb + n;
-  const float alpha = in.unit_alpha[in.unit[t]];
-  for (int64_t q = hb; q < he; ++q) {
-    HitGeom h;
-    h.xm = in.row_x[in.hit_row[q]];
-    h.ym = in.y[in.hit_id[q]];
-    h.zm = in.z[in.hit_id[q]];
-    const float r = sqrtf(h.xm * h.xm + h.ym * h.ym);
-    h.inv_r = 1.0f / r;
-    h.phi = alpha + atan2f(h.ym, h.xm);
-    float xc, yc, zc;
-    map_correct(theta, h, r, &xc, &yc, &zc);
-    reinterpret_cast<float4*>(ws.xyz)[q] = make_float4(xc, yc, zc, 0.0f);
-  }
-  bool ok = n >= 2;
-  float chi2 = 0.0f;
-  if (ok) {
-    const float4 h0 = reinterpret_cast<const float4*>(ws.xyz)[hb];
-    KState q;
-    seed_state(q, h0.x, h0.y, h0.z, in.seed + 5 * t, p);
-    const int64_t cb = ckpt_base(in, t);
-    store_state(ws.ckpt + cb * kCkptFloats, q);
-    for (int i = 1; i < n && ok; ++i) {
-      const float4 h = reinterpret_cast<const float4*>(ws.xyz)[hb + i];
-      ok = refit_step(q, h.x, h.y, h.z, p, &chi2);
-      if (ok && i % kCkpt == 0) store_state(ws.ckpt + (cb + i / kCkpt) * kCkptFloats, q);
+// Corrected clusters, one per attached hit, for the standalone refit: a block
+// takes the hits of kRefitBlock consecutive tracks (they are contiguous) and
+// finds each hit's track by binary search over the block's offsets in LDS.
+__global__ void __launch_bounds__(kRefitBlock) k_correct_hits(RefitIn in, const float* __restrict__ theta,
+                                                              float4* __restrict__ xyz) {
+  __shared__ int64_t hb[kRefitBlock + 1];
+  __shared__ float al[kRefitBlock];
+  const int64_t n_tr = in.n_tracks;
+  const int64_t t0 = int64_t(blockIdx.x) * kRefitBlock;
+  const int cnt = int(min(int64_t(kRefitBlock), n_tr - t0));
+  const int tid = threadIdx.x;
+  if (tid <= cnt) hb[tid] = in.hit_begin[t0 + tid];
+  if (tid == 0 && cnt == kRefitBlock) hb[kRefitBlock] = in.hit_begin[t0 + kRefitBlock];
+  if (tid < cnt) al[tid] = in.unit_alpha[in.unit[t0 + tid]];
+  __syncthreads();
+  for (int64_t q = hb[0] + tid; q < hb[cnt]; q += kRefitBlock) {
+    int lo = 0, hi = cnt - 1;  // last s with hb[s] <= q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hb[mid] <= q) lo = mid; else hi = mid - 1;
     }
+    xyz[q] = correct_cluster(theta, in.row_x[in.hit_row[q]], in.y[in.hit_id[q]], in.z[in.hit_id[q]], al[lo]);
   }
-  chi2_out[t] = ok ? chi2 : 0.0f;
-  ok_out[t] = ok ? 1 : 0;
 }
 
-__global__ void __launch_bounds__(kRefitBlock) k_refit_fwd(RefitIn in, const float* __restrict__ theta,
-                                                           DevParams p, RefitWs ws,
-                                                           float* __restrict__ chi2_out,
-                                                           int32_t* __restrict__ ok_out) {
-  const int64_t n = refit_count(in);
-  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
-       t += int64_t(gridDim.x) * blockDim.x)
-    refit_track_fwd(in, t, theta, p, ws, chi2_out, ok_out);
+// Corrected clusters, one per input cluster (caller order), for the batched
+// refit: one block per (unit, row).
+__global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
+    int n_rows, const int64_t* __restrict__ row_begin, const float* __restrict__ y,
+    const float* __restrict__ z, const float* __restrict__ unit_alpha,
+    const float* __restrict__ row_x, const float* __restrict__ theta, float4* __restrict__ corr) {
+  const int64_t ur = blockIdx.x;
+  const float alpha = unit_alpha[ur / n_rows];
+  const float x = row_x[ur % n_rows];
+  const int64_t e = row_begin[ur + 1];
+  for (int64_t c = row_begin[ur] + threadIdx.x; c < e; c += kRefitBlock)
+    corr[c] = correct_cluster(theta, x, y[c], z[c], alpha);
+}
+
+// Forward filter over the corrected clusters: xyz[hit_id[q]] when by_cluster,
+// else xyz[q].  Persistent; every lane runs one track at a time and takes the
+// next one as soon as its track ends, from a wavefront-private chunk of
+// kRefitChunk consecutive tracks refilled from the device queue, so lanes do
+// not wait for the longest track of their wavefront.  Which lane runs a track
+// does not change its result.  Checkpoints (every kCkpt clusters) are written
+// when ckpt is set.
+constexpr int kRefitChunk = 64;
+
+__global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
+    RefitIn in, DevParams p, const float4* __restrict__ xyz, int by_cluster, float* __restrict__ ckpt,
+    unsigned long long* __restrict__ queue, float* __restrict__ chi2_out,
+    int32_t* __restrict__ ok_out) {
+  const int64_t n_tr = refit_count(in);
+  const int lane = lane_id();
+  int64_t chunk = 0, chunk_end = 0;  // wavefront-uniform
+  bool exhausted = false;            // wavefront-uniform
+  int64_t t = -1, hb = 0, cb = 0;
+  int i = 0, n = 0;
+  bool done = false;
+  float chi2 = 0.0f;
+  KState q{};
+  while (true) {
+    // hand tracks to idle lanes; tracks too short to refit are finished here
+    while (true) {
+      const uint64_t want = __ballot(t < 0 && !done);
+      if (!want) break;
+      if (chunk == chunk_end) {
+        if (!exhausted) {
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(queue, static_cast<unsigned long long>(kRefitChunk));
+          base = __shfl(base, 0, kWave);
+          if (int64_t(base) >= n_tr) {
+            exhausted = true;
+          } else {
+            chunk = int64_t(base);
+            chunk_end = min(chunk + kRefitChunk, n_tr);
+          }
+        }
+        if (exhausted) {
+          if (t < 0) done = true;
+          break;
+        }
+      }
+      const int rank = __popcll(want & lanes_below());
+      const int64_t avail = chunk_end - chunk;
+      if (t < 0 && !done && rank < avail) {
+        t = chunk + rank;
+        n = track_size(in, t);
+        if (n < in.min_hits || n < 2) {
+          chi2_out[t] = 0.0f;
+          ok_out[t] = 0;
+          t = -1;
+        } else {
+          hb = in.hit_begin[t];
+          const float4 h0 = xyz[by_cluster ? int64_t(in.hit_id[hb]) : hb];
+          seed_state(q, h0.x, h0.y, h0.z, in.seed + 5 * t, p);
+          cb = ckpt_base(in, t);
+          if (ckpt) store_state(ckpt + cb * kCkptFloats, q);
+          i = 1;
+          chi2 = 0.0f;
+        }
+      }
+      chunk += min(int64_t(__popcll(want)), avail);
+    }
+    if (!__ballot(t >= 0)) break;
+    if (t >= 0) {
+      const int64_t qh = hb + i;
+      const float4 h = xyz[by_cluster ? int64_t(in.hit_id[qh]) : qh];
+      const bool ok = refit_step(q, h.x, h.y, h.z, p, &chi2);
+      if (ok && ckpt && i % kCkpt == 0) store_state(ckpt + (cb + i / kCkpt) * kCkptFloats, q);
+      ++i;
+      if (!ok || i == n) {
+        chi2_out[t] = ok ? chi2 : 0.0f;
+        ok_out[t] = ok ? 1 : 0;
+        t = -1;
+      }
+    }
+  }
 }
 
 // Adjoint of the filter state (same layout as KState).
@@ -641,24 +722,16 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams
         const float4 h = xyz[hb + i];
         float gx1, gmy, gmz;
         refit_step_reverse(prev, h.x, h.y, h.z, p, gchi2, g, &gx1, &gmy, &gmz);
-        HitGeom hg;
-        hg.xm = in.row_x[in.hit_row[hb + i]];
-        hg.ym = in.y[in.hit_id[hb + i]];
-        hg.zm = in.z[in.hit_id[hb + i]];
-        const float r = sqrtf(hg.xm * hg.xm + hg.ym * hg.ym);
-        hg.inv_r = 1.0f / r;
-        hg.phi = alpha + atan2f(hg.ym, hg.xm);
+        float r;
+        const HitGeom hg = hit_geom(in.row_x[in.hit_row[hb + i]], in.y[in.hit_id[hb + i]],
+                                    in.z[in.hit_id[hb + i]], alpha, &r);
         add_hit_gradient(hg, r, gx1, gmy, gmz, wref, win, ws.acc);
       }
     }
     // the first cluster seeds x, y, z of the state
-    HitGeom hg;
-    hg.xm = in.row_x[in.hit_row[hb]];
-    hg.ym = in.y[in.hit_id[hb]];
-    hg.zm = in.z[in.hit_id[hb]];
-    const float r = sqrtf(hg.xm * hg.xm + hg.ym * hg.ym);
-    hg.inv_r = 1.0f / r;
-    hg.phi = alpha + atan2f(hg.ym, hg.xm);
+    float r;
+    const HitGeom hg = hit_geom(in.row_x[in.hit_row[hb]], in.y[in.hit_id[hb]], in.z[in.hit_id[hb]],
+                                alpha, &r);
     add_hit_gradient(hg, r, g.x, g.y, g.z, wref, win, ws.acc);
   }
   __syncthreads();

@@ -126,9 +126,37 @@ RefitLayout carve_refit(void* base, int64_t n_tracks, int64_t n_hits) {
   L.ws.n_lanes = std::max<int64_t>(n_tracks, 1);
   L.ws.scratch = cv.take<float>(L.ws.n_lanes * kCkpt * kCkptFloats);
   L.ws.acc = cv.take<int64_t>(kMapNCoef);
+  L.ws.queue = cv.take<unsigned long long>(1);
   L.ok = cv.take<int32_t>(n_tracks);
   L.bytes = cv.off;
   return L;
+}
+
+// Workspace of the refit inside the batched call: corrected clusters, one per
+// input cluster, and the filter's queue word.
+struct BatchRefitLayout {
+  float4* corr;
+  unsigned long long* queue;
+  size_t bytes;
+};
+
+BatchRefitLayout carve_batch_refit(void* base, int64_t n_clusters) {
+  Carver cv{static_cast<char*>(base)};
+  BatchRefitLayout L{};
+  L.corr = cv.take<float4>(n_clusters);
+  L.queue = cv.take<unsigned long long>(1);
+  L.bytes = cv.off;
+  return L;
+}
+
+// Persistent grid of the refit filter: enough blocks for the tracks, at most
+// kRefitBlocksPerCu per compute unit.
+constexpr int kRefitBlocksPerCu = 7;
+
+int refit_filter_grid(const tpcx_ctx* c, int64_t n_tracks) {
+  const int64_t per_block = int64_t(kRefitBlock) / kWave * kRefitChunk;
+  return int(std::max<int64_t>(1, std::min<int64_t>((n_tracks + per_block - 1) / per_block,
+                                                     int64_t(kRefitBlocksPerCu) * c->n_cu)));
 }
 
 bool refit_args_ok(const tpcx_ctx* c, const tpcx_refit_in* in) {
@@ -401,7 +429,8 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
 }
 
 void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_tracks* out,
-                         const tpcx_batch_refit* refit, const RefitLayout& RL, hipStream_t stream) {
+                         const tpcx_batch_refit* refit, const BatchRefitLayout& RL,
+                         hipStream_t stream) {
   RefitIn r;
   r.n_tracks = out->cap_tracks;
   r.n_tracks_dev = out->counts + 1;
@@ -417,8 +446,16 @@ void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_
   r.z = in->z;
   r.unit_alpha = refit->unit_alpha;
   r.row_x = c->d_row_x;
-  hipLaunchKernelGGL(k_refit_fwd, dim3(4 * c->n_cu), dim3(kRefitBlock), 0, stream, r, refit->theta,
-                     c->dp, RL.ws, refit->chi2, refit->ok);
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, reinterpret_cast<int64_t*>(RL.queue),
+                     int64_t(1), int64_t(0));
+  const int64_t n_ur = int64_t(in->n_units) * c->n_rows;
+  if (in->n_clusters > 0)
+    hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, stream,
+                       c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
+                       refit->theta, RL.corr);
+  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, out->cap_tracks)), dim3(kRefitBlock), 0,
+                     stream, r, c->dp, RL.corr, 1, static_cast<float*>(nullptr), RL.queue, refit->chi2,
+                     refit->ok);
 }
 
 hipEvent_t* next_timing_slot(tpcx_ctx* c) {
@@ -484,8 +521,14 @@ tpcx_status tpcx_refit(tpcx_ctx* c, const tpcx_refit_in* in, const float* theta,
   const RefitLayout L = carve_refit(ws, in->n_tracks, n_hits);
   if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   if (in->n_tracks == 0) return TPCX_OK;
-  hipLaunchKernelGGL(k_refit_fwd, dim3(std::min(blocks_for(in->n_tracks, kRefitBlock), 4 * c->n_cu)),
-                     dim3(kRefitBlock), 0, stream, refit_view(c, in), theta, c->dp, L.ws, chi2, L.ok);
+  const RefitIn rv = refit_view(c, in);
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, reinterpret_cast<int64_t*>(L.ws.queue),
+                     int64_t(1), int64_t(0));
+  hipLaunchKernelGGL(k_correct_hits, dim3(blocks_for(in->n_tracks, kRefitBlock)), dim3(kRefitBlock), 0,
+                     stream, rv, theta, reinterpret_cast<float4*>(L.ws.xyz));
+  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, in->n_tracks)), dim3(kRefitBlock), 0,
+                     stream, rv, c->dp, reinterpret_cast<const float4*>(L.ws.xyz), 0, L.ws.ckpt,
+                     L.ws.queue, chi2, L.ok);
   (void)hipMemcpyAsync(ok, L.ok, sizeof(int32_t) * size_t(in->n_tracks), hipMemcpyDeviceToDevice,
                        stream);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
@@ -521,7 +564,9 @@ size_t tpcx_batched_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t 
     return 0;
   const tpcx_tuning t = effective_tuning(c, n_units, n_clusters);
   const size_t a = carve(c, nullptr, n_units, n_clusters, cap_start, t.n_zbins, t.block).bytes;
-  return a + carve_refit(nullptr, cap_tracks, cap_hits).bytes;
+  (void)cap_tracks;
+  (void)cap_hits;
+  return a + carve_batch_refit(nullptr, n_clusters).bytes;
 }
 
 tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
@@ -535,8 +580,8 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   const int64_t N = in->n_clusters;
   const tpcx_tuning t = effective_tuning(c, in->n_units, N);
   const Layout L = carve(c, ws, in->n_units, N, cap_start, t.n_zbins, t.block);
-  const RefitLayout RL =
-      carve_refit(ws ? static_cast<char*>(ws) + L.bytes : nullptr, out->cap_tracks, out->cap_hits);
+  const BatchRefitLayout RL =
+      carve_batch_refit(ws ? static_cast<char*>(ws) + L.bytes : nullptr, in->n_clusters);
   if (!ws || ws_bytes < L.bytes + RL.bytes) return TPCX_E_ARG;
 
   // the graph depends on every argument; rebuild it when one changes
