@@ -172,6 +172,9 @@ def main():
     ap.add_argument("--cpu-units", type=int, default=0, help="sectors in the oracle sample (0: one per thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-forms", action="store_true", help="skip the plain and adjoint comparisons")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one plain 1 GiB device-to-device copy kernel (reference for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -213,11 +216,18 @@ def main():
     tr = make_tracker(U, N)
     n_start, n_tracks, n_hits = size_run(tr, rb, y, z, U)
     log(f"tracklets: {n_start} start hits, {n_tracks} kept, {n_hits} attached clusters")
-    bufs = tr.allocate_batched(U, N, cap_start=n_start + 1, cap_tracks=n_tracks + 1, cap_hits=n_hits + 1)
+    bufs = tr.allocate_batched(U, N, cap_start=n_start + 1, cap_tracks=n_tracks + 1, cap_hits=n_hits + 1,
+                               autotune=not args.no_autotune)
     alpha = torch.as_tensor(G.sector_alpha(B["sectors"]).astype(np.float32), device=dev)
     theta = torch.as_tensor(np.random.default_rng(1).normal(0.0, 0.05, 36720).astype(np.float32),
                             device=dev)
     stream = torch.cuda.Stream()
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            tuning = tr.autotune_batched(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta)
+        log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
     log(f"workspace {bufs['ws_bytes'] / 2**30:.1f} GiB; capturing the graph")
 
     def step():
@@ -336,11 +346,20 @@ def main():
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                 data="synthetic",
                 config=dict(cfg, clusters=N, units=U, start_hits=n_start, tracklets=n_tracks,
-                            attached=n_hits, refitted=n_refit, refitted_clusters=n_refit_hits),
+                            attached=n_hits, refitted=n_refit, refitted_clusters=n_refit_hits,
+                            tuning=tuning or "default"),
                 roofline=roof, cpu_baseline=cpu,
                 stages_ms={k: round(v, 4) for k, v in stage_ms.items()}, path_roofline=path,
                 forms=forms)
     print(json.dumps(line), flush=True)
+    if args.copy_calibration:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        sync()
+        dst.copy_(src)
+        sync()
+        log(f"copy calibration: {4 * n} bytes read, {4 * n} bytes written")
 
 
 if __name__ == "__main__":

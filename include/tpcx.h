@@ -82,12 +82,15 @@ typedef struct {
   int32_t descent_rows; /* longest step (rows) of the walk back to the start row */
 } tpcx_params;
 
-/* Launch and search-grid tuning.  Never changes results. */
+/* Launch, work-queue and search-grid tuning.  Never changes results. */
 typedef struct {
-  float bin_y;          /* search-grid bin width along the pad row, cm */
+  float bin_y;          /* search-grid bin width along the pad row, cm (fixed per context) */
   int32_t n_zbins;      /* search-grid bins along z per unit (z range taken from data) */
   int32_t block;        /* threads per block of the per-cluster kernels (64..1024) */
-  int32_t construct_grid;  /* blocks of 256 lanes of the persistent tracklet constructor */
+  int32_t construct_grid;   /* blocks of 256 lanes of the persistent tracklet constructor */
+  int32_t construct_refill; /* idle lanes of a constructor wavefront that trigger a refill (1..64) */
+  int32_t refit_grid;       /* blocks of 256 lanes of the persistent refit filter; 0: 7 per CU */
+  int32_t refit_refill;     /* idle lanes of a refit wavefront that trigger a refill (1..64) */
 } tpcx_tuning;
 
 /* Clusters grouped by (unit, row): those of unit u, row r are the index range
@@ -236,6 +239,35 @@ size_t tpcx_batched_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_
 tpcx_status tpcx_track_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t ws_bytes,
                                int64_t cap_start, const tpcx_tracks* out,
                                const tpcx_batch_refit* refit, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Tuning and autotuning.  No tuning changes any result (every selection of
+ * the method has a total order), only the speed.
+ * ------------------------------------------------------------------------ */
+
+/* Make *t the context's tuning for later calls (NULL: back to the defaults,
+ * chosen by workload size).  t->bin_y must equal the context's.  A batched
+ * graph captured with another tuning is captured again on its next call. */
+tpcx_status tpcx_set_tuning(tpcx_ctx* ctx, const tpcx_tuning* t);
+
+/* Workspace that fits every tuning tpcx_autotune_batched tries. */
+size_t tpcx_autotune_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters,
+                                     int64_t cap_start, int64_t cap_tracks, int64_t cap_hits);
+
+/* Autotuner of the batched form.  Times the batched sequence (tracking, plus
+ * the refit when refit is set) on the caller's input for candidate tunings,
+ * one parameter at a time in a fixed order: z bins of the search grid, block
+ * size of the per-row kernels, grid and refill threshold of the persistent
+ * constructor, grid and refill threshold of the persistent refit filter.  A
+ * candidate replaces the current best when it is at least 1% faster (one
+ * warm-up run, then the mean of reps >= 1 runs; a candidate whose workspace
+ * exceeds ws_bytes is skipped).  The best tuning becomes the context's
+ * tuning and is written to *best.  Synchronises the stream.  Returns
+ * TPCX_E_CAPACITY if the output capacities are too small for the input. */
+tpcx_status tpcx_autotune_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                                  int64_t cap_start, const tpcx_tracks* out,
+                                  const tpcx_batch_refit* refit, int32_t reps, tpcx_tuning* best,
+                                  hipStream_t stream);
 
 /* Stage timing (profiling aid).  Stages of one tpcx_track call, in order. */
 #define TPCX_STAGE_GRID 0       /* search-grid build */

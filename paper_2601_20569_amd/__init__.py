@@ -41,7 +41,11 @@ class Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("bin_y", ctypes.c_float), ("n_zbins", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("construct_grid", ctypes.c_int32)]
+                ("construct_grid", ctypes.c_int32), ("construct_refill", ctypes.c_int32),
+                ("refit_grid", ctypes.c_int32), ("refit_refill", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Clusters(ctypes.Structure):
@@ -121,6 +125,15 @@ def lib():
                                          ctypes.c_int64, ctypes.POINTER(Tracks),
                                          ctypes.POINTER(BatchRefit), P]
         L.tpcx_track_batched.restype = ctypes.c_int32
+        L.tpcx_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+        L.tpcx_set_tuning.restype = ctypes.c_int32
+        L.tpcx_autotune_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                    ctypes.c_int64, ctypes.c_int64]
+        L.tpcx_autotune_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_autotune_batched.argtypes = [P, ctypes.POINTER(Clusters), P, ctypes.c_size_t, ctypes.c_int64,
+                                            ctypes.POINTER(Tracks), ctypes.POINTER(BatchRefit), ctypes.c_int32,
+                                            ctypes.POINTER(Tuning), P]
+        L.tpcx_autotune_batched.restype = ctypes.c_int32
         L.tpcx_timing_enable.argtypes = [P, ctypes.c_int32]
         L.tpcx_timing_enable.restype = ctypes.c_int32
         L.tpcx_timing_read.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int32)]
@@ -276,13 +289,15 @@ class SectorTracker:
         self._last = (tr, s)
         return tr
 
-    def allocate_batched(self, n_units, n_clusters, cap_start, cap_tracks, cap_hits, refit=True):
+    def allocate_batched(self, n_units, n_clusters, cap_start, cap_tracks, cap_hits, refit=True,
+                         autotune=False):
         """Buffers for tpcx_track_batched: workspace (tracking + refit), outputs
-        and the refit results."""
+        and the refit results.  ``autotune``: a workspace large enough for
+        every tuning the autotuner tries."""
         import torch
         bufs = self.allocate(n_units, n_clusters, cap_start, cap_tracks, cap_hits)
-        nb = int(lib().tpcx_batched_workspace_bytes(self._h, n_units, n_clusters, bufs["cap_start"],
-                                                    bufs["cap_tracks"], bufs["cap_hits"]))
+        size = lib().tpcx_autotune_workspace_bytes if autotune else lib().tpcx_batched_workspace_bytes
+        nb = int(size(self._h, n_units, n_clusters, bufs["cap_start"], bufs["cap_tracks"], bufs["cap_hits"]))
         dev = bufs["ws"].device
         bufs["ws"] = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         bufs["ws_off"] = (-bufs["ws"].data_ptr()) % 256
@@ -292,13 +307,7 @@ class SectorTracker:
             bufs["refit_ok"] = torch.zeros(max(bufs["cap_tracks"], 1), dtype=torch.int32, device=dev)
         return bufs
 
-    def track_batched_into(self, row_begin, y, z, n_units, bufs, stream, unit_alpha=None,
-                           theta=None, refit_min_hits=20):
-        """Enqueue tpcx_track_batched (graph captured on the first call with
-        these buffers, replayed afterwards).  ``stream`` must be a non-default
-        torch stream.  With ``unit_alpha`` the tracklets with at least
-        ``refit_min_hits`` clusters are refitted (results in bufs["refit_chi2"],
-        bufs["refit_ok"])."""
+    def _batched_args(self, row_begin, y, z, n_units, bufs, unit_alpha, theta, refit_min_hits):
         import torch
         n = int(y.numel())
         cl = Clusters(n_units, n, _ptr(row_begin), _ptr(y), _ptr(z))
@@ -314,15 +323,46 @@ class SectorTracker:
             rf = BatchRefit(int(refit_min_hits), _ptr(theta) if theta is not None else None,
                             _ptr(unit_alpha), _ptr(bufs["refit_chi2"]), _ptr(bufs["refit_ok"]))
             bufs["_refit_keep"] = (theta, unit_alpha)
+        ws = ctypes.c_void_p(bufs["ws"].data_ptr() + bufs["ws_off"])
+        return cl, tr, rf, ws
+
+    def track_batched_into(self, row_begin, y, z, n_units, bufs, stream, unit_alpha=None,
+                           theta=None, refit_min_hits=20):
+        """Enqueue tpcx_track_batched (graph captured on the first call with
+        these buffers, replayed afterwards).  ``stream`` must be a non-default
+        torch stream.  With ``unit_alpha`` the tracklets with at least
+        ``refit_min_hits`` clusters are refitted (results in bufs["refit_chi2"],
+        bufs["refit_ok"])."""
         if stream is None or stream.cuda_stream == 0:
             raise TpcxError("the batched form needs a non-default stream (graph capture)")
-        ws = bufs["ws"]
-        st = lib().tpcx_track_batched(self._h, ctypes.byref(cl),
-                                      ctypes.c_void_p(ws.data_ptr() + bufs["ws_off"]), bufs["ws_bytes"],
-                                      bufs["cap_start"], ctypes.byref(tr),
-                                      ctypes.byref(rf) if rf is not None else None,
+        cl, tr, rf, ws = self._batched_args(row_begin, y, z, n_units, bufs, unit_alpha, theta,
+                                            refit_min_hits)
+        st = lib().tpcx_track_batched(self._h, ctypes.byref(cl), ws, bufs["ws_bytes"], bufs["cap_start"],
+                                      ctypes.byref(tr), ctypes.byref(rf) if rf is not None else None,
                                       ctypes.c_void_p(stream.cuda_stream))
         _check(st, "tpcx_track_batched")
+
+    def autotune_batched(self, row_begin, y, z, n_units, bufs, stream, unit_alpha=None, theta=None,
+                         refit_min_hits=20, reps=1):
+        """Run tpcx_autotune_batched on this input (buffers from
+        allocate_batched(..., autotune=True)); the chosen tuning stays in the
+        context and is returned as a dict."""
+        cl, tr, rf, ws = self._batched_args(row_begin, y, z, n_units, bufs, unit_alpha, theta,
+                                            refit_min_hits)
+        best = Tuning()
+        st = lib().tpcx_autotune_batched(self._h, ctypes.byref(cl), ws, bufs["ws_bytes"], bufs["cap_start"],
+                                         ctypes.byref(tr), ctypes.byref(rf) if rf is not None else None,
+                                         int(reps), ctypes.byref(best), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "tpcx_autotune_batched")
+        return best.as_dict()
+
+    def set_tuning(self, tuning):
+        """Fix the context's tuning (a Tuning or a dict as autotune_batched
+        returns); None returns to the size-dependent defaults."""
+        t = None
+        if tuning is not None:
+            t = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
+        _check(lib().tpcx_set_tuning(self._h, ctypes.byref(t) if t is not None else None), "tpcx_set_tuning")
 
     def track(self, row_begin, y, z, n_units, debug=False, cap_start=None, cap_tracks=None,
               cap_hits=None):

@@ -60,7 +60,7 @@ __global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float*
   extern __shared__ int32_t hist[];
   __shared__ float red[1024 / kWave];
   __shared__ int64_t scan_lds[1024 / kWave];
-  const int k = blockIdx.x;
+  const int k = int(xcd_block());
   const int r = k % g.n_rows;
   const int64_t b = row_begin[k], e = row_begin[k + 1];
   const int ny = g.rows[r].ny;

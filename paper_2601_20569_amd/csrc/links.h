@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
   __shared__ float dz_l[kNfD][kNfBlock];
   __shared__ int32_t did_l[kNfD][kNfBlock];
   __shared__ int32_t dpos_l[kNfD][kNfBlock];
-  const int k = blockIdx.x;
+  const int k = int(xcd_block());
   const int r = k % g.n_rows;
   const int64_t b = row_begin[k], e = row_begin[k + 1];
   const int t = threadIdx.x;
@@ -126,7 +126,7 @@ __global__ void k_clean_starts(const int64_t* __restrict__ row_begin, const int3
                                int32_t* __restrict__ cdown, uint8_t* __restrict__ flag,
                                int32_t* __restrict__ row_cnt) {
   __shared__ int32_t wcnt[1024 / kWave];
-  const int k = blockIdx.x;
+  const int k = int(xcd_block());
   const int64_t b = row_begin[k], e = row_begin[k + 1];
   int32_t cnt = 0;
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
@@ -189,7 +189,7 @@ __global__ void k_write_starts(const int64_t* __restrict__ row_begin, const floa
   __shared__ uint32_t bits[kSegWords];
   __shared__ int32_t wpre[kSegWords];
   __shared__ int64_t scan_lds[1024 / kWave];
-  const int k = blockIdx.x;
+  const int k = int(xcd_block());
   const int64_t b = row_begin[k], e = row_begin[k + 1];
   int64_t seg_base = row_off[k];
   for (int64_t lo = b; lo < e; lo += kSegBits) {

@@ -100,33 +100,86 @@ __device__ __forceinline__ HitGeom hit_geom(float xm, float ym, float zm, float 
   return h;
 }
 
+// Map coefficients of node (i, j, k), the three components as one float4,
+// read from the coefficient array itself.
+struct ThetaGlobal {
+  const float* __restrict__ theta;
+  __device__ __forceinline__ float4 operator()(int i, int j, int k) const {
+    return make_float4(theta[map_index(0, i, j, k)], theta[map_index(1, i, j, k)],
+                       theta[map_index(2, i, j, k)], 0.0f);
+  }
+};
+
+// The same from a block-local copy in LDS of kStageNPhi x kStageNR x kMapNZ
+// nodes starting at phi node i_lo (periodic) and r node j_lo.
+constexpr int kStageNPhi = 8, kStageNR = 6;
+constexpr int kStageNodes = kStageNPhi * kStageNR * kMapNZ;
+
+struct ThetaStaged {
+  const float4* lds;
+  int i_lo, j_lo;
+  __device__ __forceinline__ float4 operator()(int i, int j, int k) const {
+    const int si = (i - i_lo + kMapNPhi) % kMapNPhi;
+    return lds[(si * kStageNR + (j - j_lo)) * kMapNZ + k];
+  }
+  // whether every node of a cluster with these first indices is in the copy
+  __device__ __forceinline__ bool covers(int phi_first, int r_first) const {
+    const int si = ((phi_first - i_lo) % kMapNPhi + kMapNPhi) % kMapNPhi;
+    const int j0 = min(max(r_first, 0), kMapNR - 1), j1 = min(max(r_first + 3, 0), kMapNR - 1);
+    return si + 3 < kStageNPhi && j0 >= j_lo && j1 < j_lo + kStageNR;
+  }
+};
+
+// Map displacement (delta r, delta r*phi, delta z) at a cluster: the sum over
+// the 4 x 4 x 4 nodes around it of the coefficients times the product of the
+// three 1-D weights, summed z first, then r, then phi.  Nodes outside the r or
+// z range have weight 0 (their index is clamped into the table).
+template <class Theta>
+__device__ __forceinline__ void map_displacement(const Theta& th, const Weights4& wp, const Weights4& wr,
+                                                 const Weights4& wz, float d[3]) {
+  d[0] = d[1] = d[2] = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
+    float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = min(max(wr.first + b, 0), kMapNR - 1);
+      float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int k = min(max(wz.first + c, 0), kMapNZ - 1);
+        const float4 v = th(i, j, k);
+        f0 += v.x * wz.w[c];
+        f1 += v.y * wz.w[c];
+        f2 += v.z * wz.w[c];
+      }
+      e0 += f0 * wr.w[b];
+      e1 += f1 * wr.w[b];
+      e2 += f2 * wr.w[b];
+    }
+    d[0] += e0 * wp.w[a];
+    d[1] += e1 * wp.w[a];
+    d[2] += e2 * wp.w[a];
+  }
+}
+
+__device__ __forceinline__ float4 apply_displacement(const HitGeom& h, const float d[3]) {
+  return make_float4(h.xm + (d[0] * h.xm - d[1] * h.ym) * h.inv_r,
+                     h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r, h.zm + d[2], 0.0f);
+}
+
+// Corrected cluster (x_c, y_c, z_c, 0); theta == nullptr means no map.  The
+// coefficients must be finite.
 __device__ __forceinline__ float4 correct_cluster(const float* __restrict__ theta, float xm, float ym,
                                                   float zm, float alpha) {
   float r;
   const HitGeom h = hit_geom(xm, ym, zm, alpha, &r);
   float d[3] = {0.0f, 0.0f, 0.0f};
-  if (theta) {
-    const Weights4 wp = weights_phi(h.phi);
-    const Weights4 wr = weights_lin(r, kMapR0, kMapDR, kMapNR);
-    const Weights4 wz = weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ);
-    for (int a = 0; a < 4; ++a) {
-      const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
-      for (int b = 0; b < 4; ++b) {
-        const float wab = wp.w[a] * wr.w[b];
-        if (wab == 0.0f) continue;
-        const int j = wr.first + b;
-        for (int c = 0; c < 4; ++c) {
-          const float w = wab * wz.w[c];
-          if (w == 0.0f) continue;
-          const int k = wz.first + c;
-#pragma unroll
-          for (int q = 0; q < 3; ++q) d[q] += theta[map_index(q, i, j, k)] * w;
-        }
-      }
-    }
-  }
-  return make_float4(h.xm + (d[0] * h.xm - d[1] * h.ym) * h.inv_r,
-                     h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r, h.zm + d[2], 0.0f);
+  if (theta)
+    map_displacement(ThetaGlobal{theta}, weights_phi(h.phi), weights_lin(r, kMapR0, kMapDR, kMapNR),
+                     weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ), d);
+  return apply_displacement(h, d);
 }
 
 struct RefitIn {
@@ -152,7 +205,7 @@ struct RefitWs {
   float* scratch;   // [lanes][kCkpt][kCkptFloats] states of the segment in the backward
   int64_t* acc;     // [kMapNCoef] fixed-point gradient accumulators
   int64_t n_lanes;
-  unsigned long long* queue;  // track queue of the filter kernel (zeroed before each launch)
+  unsigned long long* queue;  // [kXcds] track queues of the filter kernel (zeroed before each launch)
 };
 
 __device__ __forceinline__ int64_t ckpt_base(const RefitIn& in, int64_t t) {
@@ -246,88 +299,144 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_hits(RefitIn in, const 
 }
 
 // Corrected clusters, one per input cluster (caller order), for the batched
-// refit: one block per (unit, row).
+// refit: one block per (unit, row).  The block first copies into LDS the map
+// nodes around its sector (phi within +-20 degrees of the centre line,
+// the r nodes of the row's radius range); a cluster whose nodes lie outside
+// that copy reads the coefficient array.  Both give the same arithmetic as
+// correct_cluster.
 __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     int n_rows, const int64_t* __restrict__ row_begin, const float* __restrict__ y,
     const float* __restrict__ z, const float* __restrict__ unit_alpha,
     const float* __restrict__ row_x, const float* __restrict__ theta, float4* __restrict__ corr) {
-  const int64_t ur = blockIdx.x;
+  __shared__ float4 stage[kStageNodes];
+  const int64_t ur = xcd_block();
   const float alpha = unit_alpha[ur / n_rows];
   const float x = row_x[ur % n_rows];
   const int64_t e = row_begin[ur + 1];
-  for (int64_t c = row_begin[ur] + threadIdx.x; c < e; c += kRefitBlock)
-    corr[c] = correct_cluster(theta, x, y[c], z[c], alpha);
+  if (!theta) {
+    const float d[3] = {0.0f, 0.0f, 0.0f};
+    for (int64_t c = row_begin[ur] + threadIdx.x; c < e; c += kRefitBlock) {
+      float r;
+      corr[c] = apply_displacement(hit_geom(x, y[c], z[c], alpha, &r), d);
+    }
+    return;
+  }
+  ThetaStaged ts;
+  ts.lds = stage;
+  {
+    const float two_pi = 6.28318530717958647692f;
+    float ph = fmodf(alpha - 0.3490658503988659f, two_pi);  // 20 degrees below the centre line
+    if (ph < 0.0f) ph += two_pi;
+    ts.i_lo = (int(floorf(ph / kMapDPhi)) - 1 + kMapNPhi) % kMapNPhi;
+    ts.j_lo = min(max(int(floorf((x - kMapR0) / kMapDR)) - 1, 0), kMapNR - kStageNR);
+  }
+  for (int q = threadIdx.x; q < kStageNodes; q += kRefitBlock) {
+    const int k = q % kMapNZ;
+    const int j = ts.j_lo + (q / kMapNZ) % kStageNR;
+    const int i = (ts.i_lo + q / (kMapNZ * kStageNR)) % kMapNPhi;
+    stage[q] = ThetaGlobal{theta}(i, j, k);
+  }
+  __syncthreads();
+  for (int64_t c = row_begin[ur] + threadIdx.x; c < e; c += kRefitBlock) {
+    float r;
+    const HitGeom h = hit_geom(x, y[c], z[c], alpha, &r);
+    const Weights4 wp = weights_phi(h.phi);
+    const Weights4 wr = weights_lin(r, kMapR0, kMapDR, kMapNR);
+    const Weights4 wz = weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ);
+    float d[3];
+    if (ts.covers(wp.first, wr.first))
+      map_displacement(ts, wp, wr, wz, d);
+    else
+      map_displacement(ThetaGlobal{theta}, wp, wr, wz, d);
+    corr[c] = apply_displacement(h, d);
+  }
 }
 
 // Forward filter over the corrected clusters: xyz[hit_id[q]] when by_cluster,
-// else xyz[q].  Persistent; every lane runs one track at a time and takes the
-// next one as soon as its track ends, from a wavefront-private chunk of
-// kRefitChunk consecutive tracks refilled from the device queue, so lanes do
-// not wait for the longest track of their wavefront.  Which lane runs a track
-// does not change its result.  Checkpoints (every kCkpt clusters) are written
-// when ckpt is set.
+// else xyz[q].  Persistent; every lane runs one track at a time.  Idle lanes
+// take new tracks, `refill` or more at a time, from a wavefront-private
+// chunk of kRefitChunk consecutive tracks refilled from kXcds device queues, so
+// lanes do not wait for the longest track of their wavefront.  The cluster of
+// the next step is loaded one step ahead (and its index two steps ahead), so
+// the loads overlap the arithmetic of the current step.  Which lane runs a
+// track does not change its result.  Checkpoints (every kCkpt clusters) are
+// written when ckpt is set.
 constexpr int kRefitChunk = 64;
 
 __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
     RefitIn in, DevParams p, const float4* __restrict__ xyz, int by_cluster, float* __restrict__ ckpt,
-    unsigned long long* __restrict__ queue, float* __restrict__ chi2_out,
+    unsigned long long* __restrict__ queue, int refill, float* __restrict__ chi2_out,
     int32_t* __restrict__ ok_out) {
   const int64_t n_tr = refit_count(in);
   const int lane = lane_id();
   int64_t chunk = 0, chunk_end = 0;  // wavefront-uniform
   bool exhausted = false;            // wavefront-uniform
+  const int qhome = int(blockIdx.x % kXcds);
+  int qtried = 0;
   int64_t t = -1, hb = 0, cb = 0;
   int i = 0, n = 0;
-  bool done = false;
   float chi2 = 0.0f;
   KState q{};
+  float4 hn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // corrected cluster of hit i
+  int64_t idn = 0;                                  // xyz index of hit i + 1
+  auto xyz_index = [&](int64_t qh) -> int64_t { return by_cluster ? int64_t(in.hit_id[qh]) : qh; };
   while (true) {
-    // hand tracks to idle lanes; tracks too short to refit are finished here
-    while (true) {
-      const uint64_t want = __ballot(t < 0 && !done);
-      if (!want) break;
-      if (chunk == chunk_end) {
-        if (!exhausted) {
-          unsigned long long base = 0;
-          if (lane == 0) base = atomicAdd(queue, static_cast<unsigned long long>(kRefitChunk));
-          base = __shfl(base, 0, kWave);
-          if (int64_t(base) >= n_tr) {
+    const int nidle = __popcll(__ballot(t < 0));
+    if (nidle == kWave && exhausted) break;
+    if (nidle > 0 && !exhausted && (nidle >= refill || nidle == kWave)) {
+      // hand tracks to idle lanes; tracks too short to refit are finished here
+      while (true) {
+        const uint64_t want = __ballot(t < 0);
+        if (!want) break;
+        if (chunk == chunk_end) {
+          // queue j hands out the j-th eighth of the tracks; the wavefront
+          // starts with the queue of its own XCD
+          while (qtried < kXcds) {
+            const int j = (qhome + qtried) % kXcds;
+            const int64_t qb = n_tr * j / kXcds, qe = n_tr * (j + 1) / kXcds;
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(queue + j, static_cast<unsigned long long>(kRefitChunk));
+            base = __shfl(base, 0, kWave);
+            if (qb + int64_t(base) < qe) {
+              chunk = qb + int64_t(base);
+              chunk_end = min(chunk + kRefitChunk, qe);
+              break;
+            }
+            ++qtried;
+          }
+          if (qtried >= kXcds) {
             exhausted = true;
-          } else {
-            chunk = int64_t(base);
-            chunk_end = min(chunk + kRefitChunk, n_tr);
+            break;
           }
         }
-        if (exhausted) {
-          if (t < 0) done = true;
-          break;
+        const int rank = __popcll(want & lanes_below());
+        const int64_t avail = chunk_end - chunk;
+        if (t < 0 && rank < avail) {
+          t = chunk + rank;
+          n = track_size(in, t);
+          if (n < in.min_hits || n < 2) {
+            chi2_out[t] = 0.0f;
+            ok_out[t] = 0;
+            t = -1;
+          } else {
+            hb = in.hit_begin[t];
+            const float4 h0 = xyz[xyz_index(hb)];
+            seed_state(q, h0.x, h0.y, h0.z, in.seed + 5 * t, p);
+            cb = ckpt_base(in, t);
+            if (ckpt) store_state(ckpt + cb * kCkptFloats, q);
+            i = 1;
+            chi2 = 0.0f;
+            hn = xyz[xyz_index(hb + 1)];
+            idn = n > 2 ? xyz_index(hb + 2) : 0;
+          }
         }
+        chunk += min(int64_t(__popcll(want)), avail);
       }
-      const int rank = __popcll(want & lanes_below());
-      const int64_t avail = chunk_end - chunk;
-      if (t < 0 && !done && rank < avail) {
-        t = chunk + rank;
-        n = track_size(in, t);
-        if (n < in.min_hits || n < 2) {
-          chi2_out[t] = 0.0f;
-          ok_out[t] = 0;
-          t = -1;
-        } else {
-          hb = in.hit_begin[t];
-          const float4 h0 = xyz[by_cluster ? int64_t(in.hit_id[hb]) : hb];
-          seed_state(q, h0.x, h0.y, h0.z, in.seed + 5 * t, p);
-          cb = ckpt_base(in, t);
-          if (ckpt) store_state(ckpt + cb * kCkptFloats, q);
-          i = 1;
-          chi2 = 0.0f;
-        }
-      }
-      chunk += min(int64_t(__popcll(want)), avail);
     }
-    if (!__ballot(t >= 0)) break;
     if (t >= 0) {
-      const int64_t qh = hb + i;
-      const float4 h = xyz[by_cluster ? int64_t(in.hit_id[qh]) : qh];
+      const float4 h = hn;
+      if (i + 1 < n) hn = xyz[idn];
+      if (i + 2 < n) idn = xyz_index(hb + i + 2);
       const bool ok = refit_step(q, h.x, h.y, h.z, p, &chi2);
       if (ok && ckpt && i % kCkpt == 0) store_state(ckpt + (cb + i / kCkpt) * kCkptFloats, q);
       ++i;

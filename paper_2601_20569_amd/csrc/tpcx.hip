@@ -102,7 +102,7 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   L.starts = cv.take<int32_t>(cap_start);
   L.start_pos = cv.take<int32_t>(cap_start);
   L.start_k = cv.take<int32_t>(cap_start);
-  L.queue = cv.take<int32_t>(1);
+  L.queue = cv.take<int32_t>(kXcds);
   L.part = cv.take<int64_t>(2 * kKeepBlocks);
   L.tmp.cap = std::max<int64_t>(cap_start, 1);
   L.tmp.stride = (c->n_rows + 15) / 16 * 16;
@@ -126,14 +126,14 @@ RefitLayout carve_refit(void* base, int64_t n_tracks, int64_t n_hits) {
   L.ws.n_lanes = std::max<int64_t>(n_tracks, 1);
   L.ws.scratch = cv.take<float>(L.ws.n_lanes * kCkpt * kCkptFloats);
   L.ws.acc = cv.take<int64_t>(kMapNCoef);
-  L.ws.queue = cv.take<unsigned long long>(1);
+  L.ws.queue = cv.take<unsigned long long>(kXcds);
   L.ok = cv.take<int32_t>(n_tracks);
   L.bytes = cv.off;
   return L;
 }
 
 // Workspace of the refit inside the batched call: corrected clusters, one per
-// input cluster, and the filter's queue word.
+// input cluster, and the filter's queue words.
 struct BatchRefitLayout {
   float4* corr;
   unsigned long long* queue;
@@ -144,19 +144,20 @@ BatchRefitLayout carve_batch_refit(void* base, int64_t n_clusters) {
   Carver cv{static_cast<char*>(base)};
   BatchRefitLayout L{};
   L.corr = cv.take<float4>(n_clusters);
-  L.queue = cv.take<unsigned long long>(1);
+  L.queue = cv.take<unsigned long long>(kXcds);
   L.bytes = cv.off;
   return L;
 }
 
 // Persistent grid of the refit filter: enough blocks for the tracks, at most
-// kRefitBlocksPerCu per compute unit.
+// the tuning's refit_grid (0: kRefitBlocksPerCu per compute unit, the
+// filter's occupancy limit).
 constexpr int kRefitBlocksPerCu = 7;
 
-int refit_filter_grid(const tpcx_ctx* c, int64_t n_tracks) {
+int refit_filter_grid(const tpcx_ctx* c, int64_t n_tracks, int32_t refit_grid) {
   const int64_t per_block = int64_t(kRefitBlock) / kWave * kRefitChunk;
-  return int(std::max<int64_t>(1, std::min<int64_t>((n_tracks + per_block - 1) / per_block,
-                                                     int64_t(kRefitBlocksPerCu) * c->n_cu)));
+  const int64_t cap = refit_grid > 0 ? refit_grid : int64_t(kRefitBlocksPerCu) * c->n_cu;
+  return int(std::max<int64_t>(1, std::min<int64_t>((n_tracks + per_block - 1) / per_block, cap)));
 }
 
 bool refit_args_ok(const tpcx_ctx* c, const tpcx_refit_in* in) {
@@ -207,7 +208,9 @@ tpcx_tuning effective_tuning(const tpcx_ctx* c, int32_t n_units, int64_t n) {
 
 bool valid_tuning(const tpcx_tuning& t) {
   return t.bin_y > 0.0f && std::isfinite(t.bin_y) && t.n_zbins >= 1 && t.n_zbins <= 65536 &&
-         t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 && t.construct_grid >= 1;
+         t.block >= 64 && t.block <= 1024 && t.block % 64 == 0 && t.construct_grid >= 1 &&
+         t.construct_refill >= 1 && t.construct_refill <= kWave && t.refit_grid >= 0 &&
+         t.refit_refill >= 1 && t.refit_refill <= kWave;
 }
 
 tpcx_status build_rows(tpcx_ctx* c) {
@@ -245,6 +248,9 @@ void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t) {
   t->n_zbins = std::max(4, std::min(nz, 4096));
   t->block = 256;
   t->construct_grid = 1280;  // 5 blocks of 4 wavefronts per CU, persistent
+  t->construct_refill = 16;
+  t->refit_grid = 0;
+  t->refit_refill = 16;
 }
 
 tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx_tuning* tuning,
@@ -378,7 +384,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   };
   mark(0);
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, out->counts, int64_t(4), int64_t(0));
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(1), 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(kXcds), 0);
   const int UR = U * R;
   const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
   hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,
@@ -402,7 +408,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   ti.row_x = c->d_row_x;
   mark(3);
   hipLaunchKernelGGL(k_construct, dim3(t.construct_grid), dim3(kConstructBlock), 0, stream,
-                     out->counts, cap_start, L.queue, ti, g, c->dp, L.tmp);
+                     out->counts, cap_start, L.queue, t.construct_refill, ti, g, c->dp, L.tmp);
 
   TrackOut o;
   o.cap_tracks = out->cap_tracks;
@@ -430,7 +436,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
 
 void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_tracks* out,
                          const tpcx_batch_refit* refit, const BatchRefitLayout& RL,
-                         hipStream_t stream) {
+                         const tpcx_tuning& t, hipStream_t stream) {
   RefitIn r;
   r.n_tracks = out->cap_tracks;
   r.n_tracks_dev = out->counts + 1;
@@ -447,15 +453,92 @@ void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_
   r.unit_alpha = refit->unit_alpha;
   r.row_x = c->d_row_x;
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, reinterpret_cast<int64_t*>(RL.queue),
-                     int64_t(1), int64_t(0));
+                     int64_t(kXcds), int64_t(0));
   const int64_t n_ur = int64_t(in->n_units) * c->n_rows;
   if (in->n_clusters > 0)
     hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, stream,
                        c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
                        refit->theta, RL.corr);
-  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, out->cap_tracks)), dim3(kRefitBlock), 0,
-                     stream, r, c->dp, RL.corr, 1, static_cast<float*>(nullptr), RL.queue, refit->chi2,
-                     refit->ok);
+  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, out->cap_tracks, t.refit_grid)),
+                     dim3(kRefitBlock), 0, stream, r, c->dp, RL.corr, 1, static_cast<float*>(nullptr),
+                     RL.queue, t.refit_refill, refit->chi2, refit->ok);
+}
+
+// Candidate values of one tuning parameter (knob) around the tuning b: the
+// search-grid z bins, the block size of the per-row kernels, the grid and
+// refill threshold of the constructor, the grid and refill threshold of the
+// refit filter.
+constexpr int kAutotuneKnobs = 6;
+
+std::vector<tpcx_tuning> autotune_candidates(const tpcx_ctx* c, const tpcx_tuning& b, int knob) {
+  std::vector<tpcx_tuning> v;
+  auto add = [&](tpcx_tuning t) {
+    t.n_zbins = std::max(1, std::min(t.n_zbins, (kMaxRowBins - 1) / max_row_ny(c)));
+    if (!valid_tuning(t) || std::memcmp(&t, &b, sizeof t) == 0) return;
+    for (const tpcx_tuning& u : v)
+      if (std::memcmp(&t, &u, sizeof t) == 0) return;
+    v.push_back(t);
+  };
+  tpcx_tuning t = b;
+  switch (knob) {
+    case 0:
+      for (double f : {0.5, 0.7, 1.4, 2.0}) {
+        t = b;
+        t.n_zbins = std::max(1, int(std::lround(b.n_zbins * f)));
+        add(t);
+      }
+      break;
+    case 1:
+      for (int blk : {128, 256, 512}) {
+        t = b;
+        t.block = blk;
+        add(t);
+      }
+      break;
+    case 2:
+      for (int per_cu : {3, 4, 5, 6}) {
+        t = b;
+        t.construct_grid = per_cu * c->n_cu;
+        add(t);
+      }
+      break;
+    case 3:
+      for (int r : {4, 8, 16, 32}) {
+        t = b;
+        t.construct_refill = r;
+        add(t);
+      }
+      break;
+    case 4:
+      for (int per_cu : {4, 5, 6, 7}) {
+        t = b;
+        t.refit_grid = per_cu * c->n_cu;
+        add(t);
+      }
+      break;
+    case 5:
+      for (int r : {4, 8, 16, 32}) {
+        t = b;
+        t.refit_refill = r;
+        add(t);
+      }
+      break;
+    default:
+      break;
+  }
+  return v;
+}
+
+// One eager batched run with tuning t; TPCX_E_ARG when t needs more workspace.
+tpcx_status autotune_run(const tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                         int64_t cap_start, const tpcx_tracks* out, const tpcx_batch_refit* refit,
+                         const tpcx_tuning& t, hipStream_t stream) {
+  const Layout L = carve(c, ws, in->n_units, in->n_clusters, cap_start, t.n_zbins, t.block);
+  const BatchRefitLayout RL = carve_batch_refit(static_cast<char*>(ws) + L.bytes, in->n_clusters);
+  if (L.bytes + RL.bytes > ws_bytes) return TPCX_E_ARG;
+  enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
+  if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
 hipEvent_t* next_timing_slot(tpcx_ctx* c) {
@@ -523,12 +606,12 @@ tpcx_status tpcx_refit(tpcx_ctx* c, const tpcx_refit_in* in, const float* theta,
   if (in->n_tracks == 0) return TPCX_OK;
   const RefitIn rv = refit_view(c, in);
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, reinterpret_cast<int64_t*>(L.ws.queue),
-                     int64_t(1), int64_t(0));
+                     int64_t(kXcds), int64_t(0));
   hipLaunchKernelGGL(k_correct_hits, dim3(blocks_for(in->n_tracks, kRefitBlock)), dim3(kRefitBlock), 0,
                      stream, rv, theta, reinterpret_cast<float4*>(L.ws.xyz));
-  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, in->n_tracks)), dim3(kRefitBlock), 0,
-                     stream, rv, c->dp, reinterpret_cast<const float4*>(L.ws.xyz), 0, L.ws.ckpt,
-                     L.ws.queue, chi2, L.ok);
+  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, in->n_tracks, c->tuning.refit_grid)),
+                     dim3(kRefitBlock), 0, stream, rv, c->dp, reinterpret_cast<const float4*>(L.ws.xyz), 0,
+                     L.ws.ckpt, L.ws.queue, c->tuning.refit_refill, chi2, L.ok);
   (void)hipMemcpyAsync(ok, L.ok, sizeof(int32_t) * size_t(in->n_tracks), hipMemcpyDeviceToDevice,
                        stream);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
@@ -604,7 +687,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   if (hipEvent_t* ev = next_timing_slot(c)) {
     // timed run: the same sequence launched directly, with stage events
     enqueue_track(c, in, L, t, cap_start, out, stream, ev);
-    if (refit) enqueue_batch_refit(c, in, out, refit, RL, stream);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
     (void)hipEventRecord(ev[TPCX_N_STAGES], stream);
     return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
   }
@@ -615,7 +698,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
     enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
-    if (refit) enqueue_batch_refit(c, in, out, refit, RL, stream);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipStreamEndCapture(stream, &g);
     if (e1 != hipSuccess || !g) return TPCX_E_HIP;
@@ -628,6 +711,100 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
     c->graph_key = key;
   }
   return hipGraphLaunch(c->graph, stream) == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
+tpcx_status tpcx_set_tuning(tpcx_ctx* c, const tpcx_tuning* t) {
+  if (!c) return TPCX_E_ARG;
+  if (!t) {
+    const float bin_y = c->tuning.bin_y;
+    tpcx_default_tuning(36, 1, &c->tuning);
+    c->tuning.bin_y = bin_y;
+    c->tuning_fixed = false;
+    return TPCX_OK;
+  }
+  if (!valid_tuning(*t) || t->bin_y != c->tuning.bin_y) return TPCX_E_ARG;
+  c->tuning = *t;
+  c->tuning_fixed = true;
+  return TPCX_OK;
+}
+
+size_t tpcx_autotune_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_clusters,
+                                     int64_t cap_start, int64_t cap_tracks, int64_t cap_hits) {
+  if (!c || n_units < 1 || n_clusters < 0 || cap_start < 0 || cap_tracks < 0 || cap_hits < 0)
+    return 0;
+  const tpcx_tuning b = effective_tuning(c, n_units, n_clusters);
+  size_t most = 0;
+  std::vector<tpcx_tuning> zs = autotune_candidates(c, b, 0);
+  zs.push_back(b);
+  for (const tpcx_tuning& z : zs) {
+    std::vector<tpcx_tuning> bs = autotune_candidates(c, z, 1);
+    bs.push_back(z);
+    for (const tpcx_tuning& t : bs)
+      most = std::max(most, carve(c, nullptr, n_units, n_clusters, cap_start, t.n_zbins, t.block).bytes);
+  }
+  return most + carve_batch_refit(nullptr, n_clusters).bytes;
+}
+
+tpcx_status tpcx_autotune_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                                  int64_t cap_start, const tpcx_tracks* out,
+                                  const tpcx_batch_refit* refit, int32_t reps, tpcx_tuning* best,
+                                  hipStream_t stream) {
+  tpcx_status st = check_track_args(c, in, ws, cap_start, out);
+  if (st != TPCX_OK) return st;
+  if (!ws || !best || reps < 1) return TPCX_E_ARG;
+  if (refit && (refit->min_hits < 2 || !refit->unit_alpha || !refit->chi2 || !refit->ok))
+    return TPCX_E_ARG;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return TPCX_E_HIP;
+  }
+  auto measure = [&](const tpcx_tuning& t, float* ms) -> tpcx_status {
+    tpcx_status r = autotune_run(c, in, ws, ws_bytes, cap_start, out, refit, t, stream);  // warm-up
+    if (r != TPCX_OK) return r;
+    if (hipEventRecord(e0, stream) != hipSuccess) return TPCX_E_HIP;
+    for (int i = 0; i < reps && r == TPCX_OK; ++i)
+      r = autotune_run(c, in, ws, ws_bytes, cap_start, out, refit, t, stream);
+    if (r != TPCX_OK) return r;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return TPCX_E_HIP;
+    *ms /= float(reps);
+    return TPCX_OK;
+  };
+  tpcx_tuning b = effective_tuning(c, in->n_units, in->n_clusters);
+  float best_ms = 0.0f;
+  st = measure(b, &best_ms);
+  if (st == TPCX_OK) {
+    int64_t status = 0;
+    if (hipMemcpy(&status, out->counts + 3, sizeof status, hipMemcpyDeviceToHost) != hipSuccess)
+      st = TPCX_E_HIP;
+    else if (status != 0)
+      st = TPCX_E_CAPACITY;
+  }
+  for (int knob = 0; knob < kAutotuneKnobs && st == TPCX_OK; ++knob) {
+    if (knob >= 4 && !refit) break;
+    for (const tpcx_tuning& t : autotune_candidates(c, b, knob)) {
+      float ms = 0.0f;
+      const tpcx_status r = measure(t, &ms);
+      if (r == TPCX_E_ARG) continue;  // does not fit the workspace
+      if (r != TPCX_OK) {
+        st = r;
+        break;
+      }
+      if (ms < 0.99f * best_ms) {
+        best_ms = ms;
+        b = t;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != TPCX_OK) return st;
+  c->tuning = b;
+  c->tuning_fixed = true;
+  *best = b;
+  return TPCX_OK;
 }
 
 tpcx_status tpcx_timing_enable(tpcx_ctx* c, int32_t max_calls) {

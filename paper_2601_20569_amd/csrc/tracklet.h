@@ -186,7 +186,6 @@ struct TrackInputs {
 enum : int { kChain = 0, kUp = 1, kDescend = 2, kDown = 3, kIdle = 4 };
 
 constexpr int kConstructBlock = 256;
-constexpr int kRefill = 16;  // idle lanes that trigger a refill from the queue
 
 // Every lane runs one tracklet at a time as a sequence of row steps (one
 // propagation each); the four phases share the step so that lanes of a
@@ -200,7 +199,7 @@ constexpr int kHitBuf = 16;
 constexpr int kConstructWaves = kConstructBlock / kWave;
 
 __global__ void __launch_bounds__(kConstructBlock) k_construct(
-    const int64_t* __restrict__ counts, int64_t cap_start, int32_t* __restrict__ queue,
+    const int64_t* __restrict__ counts, int64_t cap_start, int32_t* __restrict__ queue, int refill,
     TrackInputs in, Grid g, DevParams p, TrackletTmp out) {
   __shared__ int32_t hbuf[kConstructWaves][kHitBuf][kWave];
   __shared__ uint32_t rmask[kConstructWaves][kMaskWords][kWave];
@@ -230,29 +229,50 @@ __global__ void __launch_bounds__(kConstructBlock) k_construct(
       flags = 0;
   int32_t next_c = -1;
   int64_t extra_begin = 0, extra_end = 0;
-  // wavefront-private pool [pool, pool_end) of start slots, refilled from the
-  // device queue kWave slots at a time
+  // wavefront-private pool [pool, pool_end) of start slots, refilled kWave
+  // slots at a time from one of kXcds device queues: queue j hands out the
+  // j-th eighth of the start list.  A wavefront draws from the queue of its
+  // own XCD first (so each XCD works through its own units and keeps them in
+  // its L2), then from the others in turn.
   int64_t pool = 0, pool_end = 0;
   bool exhausted = false;
+  const int qhome = int(blockIdx.x % kXcds);
+  int qtried = 0;
+  auto grab = [&](int64_t& lo, int64_t& hi) {
+    lo = hi = 0;
+    while (qtried < kXcds) {
+      const int j = (qhome + qtried) % kXcds;
+      const int64_t qb = n_start * j / kXcds, qe = n_start * (j + 1) / kXcds;
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(queue + j, kWave);
+      base = __shfl(base, 0, kWave);
+      if (qb + base < qe) {
+        lo = qb + base;
+        hi = min(lo + kWave, qe);
+        if (hi == qe) ++qtried;
+        break;
+      }
+      ++qtried;
+    }
+    exhausted = qtried >= kXcds;
+  };
 
   while (true) {
     // ---- hand start slots to idle lanes
     const uint64_t idle = __ballot(phase == kIdle);
     const int nidle = __popcll(idle);
     if (nidle == kWave && exhausted && pool == pool_end) break;
-    if (nidle > 0 && (nidle >= kRefill || nidle == kWave) && !(exhausted && pool == pool_end)) {
+    if (nidle > 0 && (nidle >= refill || nidle == kWave) && !(exhausted && pool == pool_end)) {
       if (pool_end - pool < nidle && !exhausted) {
         // keep the rest of the pool (consumed first), then a fresh chunk
-        int32_t base = 0;
-        if (lane == 0) base = atomicAdd(queue, kWave);
-        base = __shfl(base, 0, kWave);
-        if (int64_t(base) + kWave >= n_start) exhausted = true;
+        int64_t lo, hi;
+        grab(lo, hi);
         if (pool == pool_end) {
-          pool = min(int64_t(base), n_start);
-          pool_end = min(int64_t(base) + kWave, n_start);
+          pool = lo;
+          pool_end = hi;
         } else {
-          extra_begin = min(int64_t(base), n_start);
-          extra_end = min(int64_t(base) + kWave, n_start);
+          extra_begin = lo;
+          extra_end = hi;
         }
       }
       const int rank = __popcll(idle & lanes_below());
