@@ -16,23 +16,59 @@ namespace tpcx {
 // from the chord d-u at row r is e = h - (d + (u - d) * f_r), D = ey^2 + ez^2.
 // The pair with the smallest (D, id_u, id_d) (caller ids) among D <= d2max
 // gives the links (sorted positions), -1 if none.
-// f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.  The down candidates
-// of a cluster are collected once in LDS (up to kNfD; more fall back to
-// re-reading them for every up candidate).
+// f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.
+//
+// The candidates of each row inside the window are first collected in LDS
+// (y, z and sorted position; up to kNfD per row), then all pairs are visited
+// in one flat loop, so a wavefront runs max(n_u * n_d) pair steps rather than
+// (scanned up candidates) x max(n_d).  Caller ids are read only to break an
+// exact tie of D.  A cluster with more than kNfD candidates in a row takes
+// the direct double scan instead.
 constexpr int kNfD = 8;
-constexpr int kNfBlock = 256;
+constexpr int kNfBlock = 128;
 
 __device__ __forceinline__ int32_t id_of(const float4& p) { return __float_as_int(p.z); }
 __device__ __forceinline__ int32_t cup_of(const float4& p) { return __float_as_int(p.w); }
+
+// Window candidates of row k (grid row) around (yh, zh) into LDS (up to kNfD);
+// returns their number (which may exceed kNfD).
+__device__ __forceinline__ int nf_collect(const Grid& g, int64_t kb, int ny, int zb0, int zb1, int yb0,
+                                          int yb1, float yh, float zh, float wy, float wz,
+                                          float2 (*yz)[kNfBlock], int32_t (*pos)[kNfBlock], int t) {
+  int n = 0;
+  for (int zb = zb0; zb <= zb1; ++zb) {
+    const int32_t j0 = g.bin_start[kb + zb * ny + yb0], j1 = g.bin_start[kb + zb * ny + yb1 + 1];
+    for (int32_t j = j0; j < j1; ++j) {
+      const float4 pc = g.pts[j];
+      if (!(fabsf(pc.x - yh) <= wy && fabsf(pc.y - zh) <= wz)) continue;
+      if (n < kNfD) {
+        yz[n][t] = make_float2(pc.x, pc.y);
+        pos[n][t] = j;
+      }
+      ++n;
+    }
+  }
+  return n;
+}
+
+// (D, ju, jd) against the best so far under the order (D, id_u, id_d).
+__device__ __forceinline__ bool nf_better(const Grid& g, float D, int32_t ju, int32_t jd, float bestD,
+                                          int32_t best_ju, int32_t best_jd) {
+  if (best_ju < 0 || D < bestD) return true;
+  if (D != bestD) return false;
+  const int32_t iu = id_of(g.pts[ju]), bu = id_of(g.pts[best_ju]);
+  if (iu != bu) return iu < bu;
+  return id_of(g.pts[jd]) < id_of(g.pts[best_jd]);
+}
 
 __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restrict__ row_begin, Grid g,
                                                          const float* __restrict__ frac, DevParams p,
                                                          int32_t* __restrict__ up_s,
                                                          int32_t* __restrict__ down_s) {
-  __shared__ float dy_l[kNfD][kNfBlock];
-  __shared__ float dz_l[kNfD][kNfBlock];
-  __shared__ int32_t did_l[kNfD][kNfBlock];
-  __shared__ int32_t dpos_l[kNfD][kNfBlock];
+  __shared__ float2 d_yz[kNfD][kNfBlock];
+  __shared__ int32_t d_pos[kNfD][kNfBlock];
+  __shared__ float2 u_yz[kNfD][kNfBlock];
+  __shared__ int32_t u_pos[kNfD][kNfBlock];
   const int k = int(xcd_block());
   const int r = k % g.n_rows;
   const int64_t b = row_begin[k], e = row_begin[k + 1];
@@ -58,55 +94,45 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
     const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
     const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
 
-    // down candidates inside the window
-    int nd = 0;
-    for (int zb = zd0; zb <= zd1; ++zb) {
-      const int32_t j0 = g.bin_start[bd + zb * nyd + yd0], j1 = g.bin_start[bd + zb * nyd + yd1 + 1];
-      for (int32_t j = j0; j < j1; ++j) {
-        const float4 pd = g.pts[j];
-        if (!(fabsf(pd.x - yh) <= wy && fabsf(pd.y - zh) <= wz)) continue;
-        if (nd < kNfD) {
-          dy_l[nd][t] = pd.x;
-          dz_l[nd][t] = pd.y;
-          did_l[nd][t] = id_of(pd);
-          dpos_l[nd][t] = j;
-        }
-        ++nd;
-      }
-    }
+    const int nd = nf_collect(g, bd, nyd, zd0, zd1, yd0, yd1, yh, zh, wy, wz, d_yz, d_pos, t);
+    const int nu = nd > 0 ? nf_collect(g, bu, nyu, zu0, zu1, yu0, yu1, yh, zh, wy, wz, u_yz, u_pos, t) : 0;
     float bestD = 0.0f;
-    int32_t best_u = -1, best_d = -1, best_ju = -1, best_jd = -1;
-    if (nd > 0) {
+    int32_t best_ju = -1, best_jd = -1;
+    auto consider = [&](float yu, float zu, int32_t ju, float yd, float zd, int32_t jd) {
+      const float ey = yh - (yd + (yu - yd) * f);
+      const float ez = zh - (zd + (zu - zd) * f);
+      const float D = ey * ey + ez * ez;
+      if (!(D <= p.d2max)) return;
+      if (nf_better(g, D, ju, jd, bestD, best_ju, best_jd)) {
+        bestD = D;
+        best_ju = ju;
+        best_jd = jd;
+      }
+    };
+    if (nd <= kNfD && nu <= kNfD) {
+      // all (u, d) pairs in one loop: a = up index, c = down index
+      int a = 0, c = 0;
+      for (int q = nu * nd; q > 0; --q) {
+        const float2 U = u_yz[a][t], Dn = d_yz[c][t];
+        consider(U.x, U.y, u_pos[a][t], Dn.x, Dn.y, d_pos[c][t]);
+        if (++c == nd) {
+          c = 0;
+          ++a;
+        }
+      }
+    } else {
+      // more candidates than LDS holds: scan both rows directly
       for (int zb = zu0; zb <= zu1; ++zb) {
         const int32_t j0 = g.bin_start[bu + zb * nyu + yu0], j1 = g.bin_start[bu + zb * nyu + yu1 + 1];
         for (int32_t ju = j0; ju < j1; ++ju) {
           const float4 pu = g.pts[ju];
-          const float yu = pu.x, zu = pu.y;
-          if (!(fabsf(yu - yh) <= wy && fabsf(zu - zh) <= wz)) continue;
-          const int32_t cu = id_of(pu);
-          auto consider = [&](float yd, float zd, int32_t cd, int32_t jd) {
-            const float ey = yh - (yd + (yu - yd) * f);
-            const float ez = zh - (zd + (zu - zd) * f);
-            const float D = ey * ey + ez * ez;
-            if (!(D <= p.d2max)) return;
-            if (best_u < 0 || D < bestD || (D == bestD && (cu < best_u || (cu == best_u && cd < best_d)))) {
-              bestD = D;
-              best_u = cu;
-              best_d = cd;
-              best_ju = ju;
-              best_jd = jd;
-            }
-          };
-          if (nd <= kNfD) {
-            for (int q = 0; q < nd; ++q) consider(dy_l[q][t], dz_l[q][t], did_l[q][t], dpos_l[q][t]);
-          } else {
-            for (int zb2 = zd0; zb2 <= zd1; ++zb2) {
-              const int32_t k0 = g.bin_start[bd + zb2 * nyd + yd0], k1 = g.bin_start[bd + zb2 * nyd + yd1 + 1];
-              for (int32_t jd = k0; jd < k1; ++jd) {
-                const float4 pd = g.pts[jd];
-                if (!(fabsf(pd.x - yh) <= wy && fabsf(pd.y - zh) <= wz)) continue;
-                consider(pd.x, pd.y, id_of(pd), jd);
-              }
+          if (!(fabsf(pu.x - yh) <= wy && fabsf(pu.y - zh) <= wz)) continue;
+          for (int zb2 = zd0; zb2 <= zd1; ++zb2) {
+            const int32_t k0 = g.bin_start[bd + zb2 * nyd + yd0], k1 = g.bin_start[bd + zb2 * nyd + yd1 + 1];
+            for (int32_t jd = k0; jd < k1; ++jd) {
+              const float4 pd = g.pts[jd];
+              if (!(fabsf(pd.x - yh) <= wy && fabsf(pd.y - zh) <= wz)) continue;
+              consider(pu.x, pu.y, ju, pd.x, pd.y, jd);
             }
           }
         }

@@ -13,6 +13,10 @@
 // 1); it propagates to every further cluster's own corrected x and updates,
 // without rejection.  chi2 of a track = sum of the updates' chi2.
 //
+// The refit takes no decision that depends on the last bit of a result, so it
+// uses the hardware square root and reciprocal (within 1 ulp) instead of the
+// correctly rounded ones the tracking needs.
+//
 // The backward pass gives d(sum_t dL/dchi2_t * chi2_t)/d(map coefficients).
 // The forward stores the filter state every kCkpt clusters; the backward
 // recomputes one segment at a time from its checkpoint into a per-lane scratch
@@ -94,8 +98,8 @@ __device__ __forceinline__ HitGeom hit_geom(float xm, float ym, float zm, float 
   h.xm = xm;
   h.ym = ym;
   h.zm = zm;
-  *r = sqrtf(xm * xm + ym * ym);
-  h.inv_r = 1.0f / *r;
+  *r = k_sqrt<true>(xm * xm + ym * ym);
+  h.inv_r = k_rcp<true>(*r);
   h.phi = alpha + atan2f(ym, xm);
   return h;
 }
@@ -266,9 +270,9 @@ __device__ __forceinline__ bool refit_step(KState& q, float xc, float yc, float 
                                            const DevParams& p, float* chi2) {
   float cp = 0.0f, rp = 0.0f;
   bool cached = false;
-  if (!kf_propagate(q, xc, p, cp, rp, cached)) return false;
-  const float iSy = 1.0f / (q.cyy + p.sy2);
-  const float iSz = 1.0f / (q.czz + p.sz2);
+  if (!kf_propagate<true>(q, xc, p, cp, rp, cached)) return false;
+  const float iSy = k_rcp<true>(q.cyy + p.sy2);
+  const float iSz = k_rcp<true>(q.czz + p.sz2);
   *chi2 = *chi2 + kf_update(q, yc, zc, iSy, iSz);
   return true;
 }
@@ -467,14 +471,14 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   const float k = p.kappa * q.w;
   const float kd = k * dx;
   const float s1 = q.s - kd;
-  const float c0 = sqrtf(1.0f - q.s * q.s);
-  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float c0 = k_sqrt<true>(1.0f - q.s * q.s);
+  const float c1 = k_sqrt<true>(1.0f - s1 * s1);
   const float cc = c0 + c1;
   const float ss = q.s + s1;
-  const float icc = 1.0f / cc;
+  const float icc = k_rcp<true>(cc);
   const float tg = ss * icc;
   const float dy = dx * tg;
-  const float dl = sqrtf(dx * dx + dy * dy);
+  const float dl = k_sqrt<true>(dx * dx + dy * dy);
   const float ak = fabsf(k);
   const float u = (ak * dl) * 0.5f;
   const float a1c = 0.16666667f, a2c = 0.075f;
@@ -482,8 +486,8 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   const float A = 1.0f + u2 * (a1c + u2 * a2c);
   const float sgn = dx < 0.0f ? -1.0f : 1.0f;
   const float dS = sgn * (dl * A);
-  const float r0 = q.s / c0;
-  const float r1 = s1 / c1;
+  const float r0 = k_div<true>(q.s, c0);
+  const float r1 = k_div<true>(s1, c1);
   const float icc2 = icc * icc;
   const float na = 2.0f * cc + ss * (r0 + r1);
   const float qa = na * icc2;
@@ -508,7 +512,7 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   const float pzz = Rz + dS * Rt, ptz = Rt, ptt = q.ctt;
   // ---------------- forward: update
   const float ry = my - py, rz = mz - pz;
-  const float iSy = 1.0f / (pyy + p.sy2), iSz = 1.0f / (pzz + p.sz2);
+  const float iSy = k_rcp<true>(pyy + p.sy2), iSz = k_rcp<true>(pzz + p.sz2);
   const float k0 = pyy * iSy, k1 = psy * iSy, k2 = pwy * iSy;
   const float kz0 = pzz * iSz, kz1 = ptz * iSz;
 
@@ -682,10 +686,11 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   // icc2 = icc*icc
   float gicc = 2.0f * icc * gicc2;
   // r1 = s1/c1 ; r0 = s/c0
-  gs1 += gr1 / c1;
-  float gc1 = -gr1 * r1 / c1;
-  os += gr0 / c0;
-  float gc0 = -gr0 * r0 / c0;
+  const float ic1 = k_rcp<true>(c1), ic0 = k_rcp<true>(c0);
+  gs1 += gr1 * ic1;
+  float gc1 = -gr1 * r1 * ic1;
+  os += gr0 * ic0;
+  float gc0 = -gr0 * r0 * ic0;
   // dS = sgn * dl * A ; A = 1 + u2*(a1 + u2*a2) ; u2 = u*u ; u = 0.5*ak*dl
   float gdl = gdS * sgn * A;
   const float gA = gdS * sgn * dl;
@@ -696,8 +701,9 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   float gk = gak * (k < 0.0f ? -1.0f : (k > 0.0f ? 1.0f : 0.0f));
   // dl = sqrt(dx^2 + dy^2)
   if (dl > 0.0f) {
-    gdx += gdl * dx / dl;
-    gdy += gdl * dy / dl;
+    const float idl = k_rcp<true>(dl);
+    gdx += gdl * dx * idl;
+    gdy += gdl * dy * idl;
   }
   // dy = dx*tg ; tg = ss*icc ; icc = 1/cc
   gdx += gdy * tg;
@@ -711,8 +717,8 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   gc0 += gcc;
   gc1 += gcc;
   // c1 = sqrt(1 - s1^2) ; c0 = sqrt(1 - s^2)
-  gs1 += gc1 * (-s1 / c1);
-  os += gc0 * (-q.s / c0);
+  gs1 += gc1 * (-s1 * ic1);
+  os += gc0 * (-q.s * ic0);
   // s1 = s - kd ; kd = k*dx ; k = kappa*w
   os += gs1;
   const float gkd = -gs1;

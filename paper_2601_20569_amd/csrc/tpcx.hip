@@ -152,7 +152,7 @@ BatchRefitLayout carve_batch_refit(void* base, int64_t n_clusters) {
 // Persistent grid of the refit filter: enough blocks for the tracks, at most
 // the tuning's refit_grid (0: kRefitBlocksPerCu per compute unit, the
 // filter's occupancy limit).
-constexpr int kRefitBlocksPerCu = 7;
+constexpr int kRefitBlocksPerCu = 8;
 
 int refit_filter_grid(const tpcx_ctx* c, int64_t n_tracks, int32_t refit_grid) {
   const int64_t per_block = int64_t(kRefitBlock) / kWave * kRefitChunk;
@@ -510,7 +510,7 @@ std::vector<tpcx_tuning> autotune_candidates(const tpcx_ctx* c, const tpcx_tunin
       }
       break;
     case 4:
-      for (int per_cu : {4, 5, 6, 7}) {
+      for (int per_cu : {4, 6, 7, 8}) {
         t = b;
         t.refit_grid = per_cu * c->n_cu;
         add(t);

@@ -29,11 +29,31 @@ __device__ __forceinline__ float arc_chord_ratio(float u) {
   return 1.0f + u2 * (a1 + u2 * a2);
 }
 
+// Square root, reciprocal and quotient: IEEE correctly rounded, or (Fast) the
+// hardware approximations (within 1 ulp), used where no decision of the method
+// depends on the last bit (the refit).
+template <bool Fast>
+__device__ __forceinline__ float k_sqrt(float x) {
+  if constexpr (Fast) return __builtin_amdgcn_sqrtf(x);
+  else return sqrtf(x);
+}
+template <bool Fast>
+__device__ __forceinline__ float k_rcp(float x) {
+  if constexpr (Fast) return __builtin_amdgcn_rcpf(x);
+  else return 1.0f / x;
+}
+template <bool Fast>
+__device__ __forceinline__ float k_div(float a, float b) {
+  if constexpr (Fast) return a * __builtin_amdgcn_rcpf(b);
+  else return a / b;
+}
+
 // Exact circle step to the plane x1 with the linearised covariance transport.
 // Returns false (state unchanged) when |sin(phi)| would reach smax or the
 // chord is too long.  (c_prev, r_prev) = (sqrt(1 - s^2), s / that) of the
 // current s when `cached` (the previous step ended at this s): the values are
 // the ones the step would compute itself, bit for bit.
+template <bool Fast = false>
 __device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParams& p, float& c_prev,
                                              float& r_prev, bool& cached) {
   const float dx = x1 - q.x;
@@ -45,21 +65,21 @@ __device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParam
     c0 = c_prev;
     r0 = r_prev;
   } else {
-    c0 = sqrtf(1.0f - q.s * q.s);
-    r0 = q.s / c0;
+    c0 = k_sqrt<Fast>(1.0f - q.s * q.s);
+    r0 = k_div<Fast>(q.s, c0);
   }
-  const float c1 = sqrtf(1.0f - s1 * s1);
+  const float c1 = k_sqrt<Fast>(1.0f - s1 * s1);
   const float cc = c0 + c1;
   const float ss = q.s + s1;
-  const float icc = 1.0f / cc;
+  const float icc = k_rcp<Fast>(cc);
   const float tg = ss * icc;
   const float dy = dx * tg;
-  const float dl = sqrtf(dx * dx + dy * dy);
+  const float dl = k_sqrt<Fast>(dx * dx + dy * dy);
   const float u = (fabsf(k) * dl) * 0.5f;
   if (!(u <= p.umax)) return false;
   float dS = dl * arc_chord_ratio(u);
   if (dx < 0.0f) dS = -dS;
-  const float r1 = s1 / c1;
+  const float r1 = k_div<Fast>(s1, c1);
   const float icc2 = icc * icc;
   const float a = dx * ((2.0f * cc + ss * (r0 + r1)) * icc2);
   const float e = -(p.kappa * dx);

@@ -132,3 +132,32 @@ def test_batched_refit_equals_standalone_refit():
     ok = job.ok[:job.n_tracks].cpu().numpy()
     np.testing.assert_array_equal(chi2, a["refit_chi2"][sel])
     np.testing.assert_array_equal(ok, a["refit_ok"][sel])
+
+
+def test_autotuned_batched_equals_default_tuning():
+    """The autotuner may pick any tuning; the results must not change."""
+    import torch
+    sets = _sets()[:3]
+    rb, y, z, sectors = pack(sets)
+    n_units = len(sectors)
+    alpha = G.sector_alpha(sectors).astype(np.float32)
+    theta = np.random.default_rng(4).normal(0.0, 0.05, 36720)
+    tr = make_tracker()
+    want = _run_batched(tr, rb, y, z, n_units, alpha, theta)[0]
+    print(f"case: autotune on {n_units} units, {len(y)} clusters", flush=True)
+    dev = torch.device("cuda")
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    rb_t, y_t, z_t = T(rb, torch.int64), T(y, torch.float32), T(z, torch.float32)
+    tr2 = make_tracker()
+    c = want["counts"]
+    bufs = tr2.allocate_batched(n_units, len(y), int(c[0]) + 1, int(c[1]) + 1, int(c[2]) + 1, autotune=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        best = tr2.autotune_batched(rb_t, y_t, z_t, n_units, bufs, s, unit_alpha=T(alpha, torch.float32),
+                                    theta=T(theta, torch.float32), reps=1)
+    s.synchronize()
+    print("tuning:", best)
+    assert 1 <= best["construct_refill"] <= 64 and 1 <= best["refit_refill"] <= 64
+    got = _run_batched(tr2, rb, y, z, n_units, alpha, theta)[0]
+    for k in want:
+        np.testing.assert_array_equal(want[k], got[k], err_msg=f"autotuned run differs in {k}")

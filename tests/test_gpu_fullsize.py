@@ -1,0 +1,80 @@
+"""A full-size time-frame slice (128 collisions, ~57M clusters) through the
+batched form, in the launch configuration the benchmark times (one captured
+graph: tracking plus refit of tracklets with >= 20 clusters), checked against
+the oracle on sampled sector units: the oracle tracks one unit of this input
+in about a second.
+
+Per sampled unit: the kept tracklets (start hit, clusters, rows) bit for bit
+against the float oracle, their parameters, covariances and chi2 bit for bit
+too, and the refit chi2 within 1e-3 (relative) of the FP64 oracle refit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import geometry as G
+
+from gpu_helpers import make_tracker
+
+pytestmark = pytest.mark.gpu
+
+
+def test_full_timeframe_slice_batched_on_sampled_units():
+    import torch
+    cs = synth.timeframe_slice(seed=3000, device="cuda", truth=False)
+    print(f"case: time-frame slice seed 3000, {cs.n_clusters} clusters, batched graph", flush=True)
+    dev = torch.device("cuda")
+    rb = torch.as_tensor(cs.row_begin, device=dev)
+    y = torch.as_tensor(cs.y, device=dev)
+    z = torch.as_tensor(cs.z, device=dev)
+    U = cs.n_units
+    tr = make_tracker()
+    probe = tr.track(rb, y, z, U)
+    ns, nt, nh = probe["n_start"], len(probe["n_hits"]), len(probe["hit_id"])
+    del probe
+    bufs = tr.allocate_batched(U, cs.n_clusters, ns + 1, nt + 1, nh + 1)
+    alpha = torch.as_tensor(G.sector_alpha(cs.unit_sector).astype(np.float32), device=dev)
+    theta = np.random.default_rng(11).normal(0.0, 0.05, oracle.map_ncoef())
+    theta_t = torch.as_tensor(theta, dtype=torch.float32, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        tr.track_batched_into(rb, y, z, U, bufs, s, unit_alpha=alpha, theta=theta_t)
+    s.synchronize()
+    o = bufs["out"]
+    counts = o["counts"].cpu().numpy()
+    assert counts[3] == 0 and counts[1] == nt and counts[2] == nh
+    g = {k: o[k][:nt].cpu().numpy() for k in ("unit", "start", "n_hits", "hit_begin", "param", "cov", "chi2")}
+    g["hit_id"] = o["hit_id"][:nh].cpu().numpy()
+    g["hit_row"] = o["hit_row"][:nh].cpu().numpy()
+    rchi2 = bufs["refit_chi2"][:nt].cpu().numpy()
+    rok = bufs["refit_ok"][:nt].cpu().numpy().astype(bool)
+    del bufs
+    torch.cuda.empty_cache()
+
+    for u in sorted(np.random.default_rng(0).choice(U, 3, replace=False)):
+        print(f"unit {u}", flush=True)
+        ref = oracle.track(cs, units=(int(u), int(u) + 1), n_threads=16)
+        k = oracle.kept_tracklets(ref)
+        gi = np.nonzero(g["unit"] == u)[0]
+        assert len(gi) == len(k["n"]) and len(gi) > 1000
+        np.testing.assert_array_equal(g["start"][gi], k["start"].astype(np.int32))
+        np.testing.assert_array_equal(g["n_hits"][gi], k["n"])
+        hits = np.concatenate([g["hit_id"][g["hit_begin"][i]:g["hit_begin"][i] + g["n_hits"][i]] for i in gi])
+        rows = np.concatenate([g["hit_row"][g["hit_begin"][i]:g["hit_begin"][i] + g["n_hits"][i]] for i in gi])
+        np.testing.assert_array_equal(hits, k["hits"])
+        np.testing.assert_array_equal(rows, k["rows"])
+        np.testing.assert_array_equal(g["param"][gi].astype(np.float64), k["param"])
+        np.testing.assert_array_equal(g["cov"][gi].astype(np.float64), k["cov"])
+        np.testing.assert_array_equal(g["chi2"][gi].astype(np.float64), k["chi2"])
+        # refit of the tracklets with >= 20 clusters against the FP64 oracle
+        tk = oracle.select_tracks(k, 20)
+        want, ok_ref = oracle.refit(cs, tk, theta)
+        sel = gi[g["n_hits"][gi] >= 20]
+        assert len(sel) == len(want)
+        ok = rok[sel]
+        assert (ok == ok_ref).mean() > 0.999
+        both = ok & ok_ref
+        rel = np.abs(rchi2[sel][both] - want[both]) / np.maximum(want[both], 1.0)
+        assert rel.max() < 1e-3, rel.max()
+        assert (rchi2[sel][~ok] == 0).all()
