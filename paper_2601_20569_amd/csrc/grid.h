@@ -111,9 +111,11 @@ __global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float*
   for (int t = t0; t < t1; ++t) {
     const int32_t c = hist[t];
     hist[t] = int32_t(run);
-    bins[base + t] = int32_t(run);
     run += c;
   }
+  __syncthreads();
+  // bin starts out of LDS, coalesced
+  for (int t = threadIdx.x; t < nb; t += blockDim.x) bins[base + t] = hist[t];
   if (threadIdx.x == 0) bins[base + nb] = int32_t(e);
   __syncthreads();
 

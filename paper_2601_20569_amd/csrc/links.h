@@ -19,32 +19,30 @@ namespace tpcx {
 // f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.
 //
 // The candidates of each row inside the window are first collected in LDS
-// (y, z and sorted position; up to kNfD per row), then all pairs are visited
-// in one flat loop, so a wavefront runs max(n_u * n_d) pair steps rather than
-// (scanned up candidates) x max(n_d).  Caller ids are read only to break an
-// exact tie of D.  A cluster with more than kNfD candidates in a row takes
-// the direct double scan instead.
+// (their sorted positions; up to kNfD per row), then all pairs are visited in
+// one flat loop, so a wavefront runs max(n_u * n_d) pair steps rather than
+// (scanned up candidates) x max(n_d); the pair loop re-reads the candidates'
+// records, which are in the cache, so the LDS stays small and occupancy high.
+// Caller ids are read only to break an exact tie of D.  A cluster with more
+// than kNfD candidates in a row takes the direct double scan instead.
 constexpr int kNfD = 8;
-constexpr int kNfBlock = 128;
+constexpr int kNfBlock = 256;
 
 __device__ __forceinline__ int32_t id_of(const float4& p) { return __float_as_int(p.z); }
 __device__ __forceinline__ int32_t cup_of(const float4& p) { return __float_as_int(p.w); }
 
-// Window candidates of row k (grid row) around (yh, zh) into LDS (up to kNfD);
-// returns their number (which may exceed kNfD).
+// Sorted positions of the window candidates of one row around (yh, zh) into
+// LDS (up to kNfD); returns their number (which may exceed kNfD).
 __device__ __forceinline__ int nf_collect(const Grid& g, int64_t kb, int ny, int zb0, int zb1, int yb0,
                                           int yb1, float yh, float zh, float wy, float wz,
-                                          float2 (*yz)[kNfBlock], int32_t (*pos)[kNfBlock], int t) {
+                                          int32_t (*pos)[kNfBlock], int t) {
   int n = 0;
   for (int zb = zb0; zb <= zb1; ++zb) {
     const int32_t j0 = g.bin_start[kb + zb * ny + yb0], j1 = g.bin_start[kb + zb * ny + yb1 + 1];
     for (int32_t j = j0; j < j1; ++j) {
       const float4 pc = g.pts[j];
       if (!(fabsf(pc.x - yh) <= wy && fabsf(pc.y - zh) <= wz)) continue;
-      if (n < kNfD) {
-        yz[n][t] = make_float2(pc.x, pc.y);
-        pos[n][t] = j;
-      }
+      if (n < kNfD) pos[n][t] = j;
       ++n;
     }
   }
@@ -65,9 +63,7 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
                                                          const float* __restrict__ frac, DevParams p,
                                                          int32_t* __restrict__ up_s,
                                                          int32_t* __restrict__ down_s) {
-  __shared__ float2 d_yz[kNfD][kNfBlock];
   __shared__ int32_t d_pos[kNfD][kNfBlock];
-  __shared__ float2 u_yz[kNfD][kNfBlock];
   __shared__ int32_t u_pos[kNfD][kNfBlock];
   const int k = int(xcd_block());
   const int r = k % g.n_rows;
@@ -94,8 +90,8 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
     const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
     const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
 
-    const int nd = nf_collect(g, bd, nyd, zd0, zd1, yd0, yd1, yh, zh, wy, wz, d_yz, d_pos, t);
-    const int nu = nd > 0 ? nf_collect(g, bu, nyu, zu0, zu1, yu0, yu1, yh, zh, wy, wz, u_yz, u_pos, t) : 0;
+    const int nd = nf_collect(g, bd, nyd, zd0, zd1, yd0, yd1, yh, zh, wy, wz, d_pos, t);
+    const int nu = nd > 0 ? nf_collect(g, bu, nyu, zu0, zu1, yu0, yu1, yh, zh, wy, wz, u_pos, t) : 0;
     float bestD = 0.0f;
     int32_t best_ju = -1, best_jd = -1;
     auto consider = [&](float yu, float zu, int32_t ju, float yd, float zd, int32_t jd) {
@@ -113,8 +109,9 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
       // all (u, d) pairs in one loop: a = up index, c = down index
       int a = 0, c = 0;
       for (int q = nu * nd; q > 0; --q) {
-        const float2 U = u_yz[a][t], Dn = d_yz[c][t];
-        consider(U.x, U.y, u_pos[a][t], Dn.x, Dn.y, d_pos[c][t]);
+        const int32_t ja = u_pos[a][t], jc = d_pos[c][t];
+        const float4 U = g.pts[ja], Dn = g.pts[jc];
+        consider(U.x, U.y, ja, Dn.x, Dn.y, jc);
         if (++c == nd) {
           c = 0;
           ++a;

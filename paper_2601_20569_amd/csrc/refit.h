@@ -168,13 +168,21 @@ __device__ __forceinline__ void map_displacement(const Theta& th, const Weights4
   }
 }
 
+// Corrected cluster as (x_c, y_c, z_m, delta z): z_c = z_m + delta z is not
+// formed here, because z_m can be large (drift coordinate in a time frame)
+// and the refit works in z relative to its first cluster (rel_z).
 __device__ __forceinline__ float4 apply_displacement(const HitGeom& h, const float d[3]) {
   return make_float4(h.xm + (d[0] * h.xm - d[1] * h.ym) * h.inv_r,
-                     h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r, h.zm + d[2], 0.0f);
+                     h.ym + (d[0] * h.ym + d[1] * h.xm) * h.inv_r, h.zm, d[2]);
 }
 
-// Corrected cluster (x_c, y_c, z_c, 0); theta == nullptr means no map.  The
-// coefficients must be finite.
+// z_c of a corrected cluster relative to the measured z of the track's first
+// cluster, z_ref: (z_m - z_ref) is exact for clusters of one track, so no
+// digit of delta z is lost to the magnitude of z_m.
+__device__ __forceinline__ float rel_z(const float4& h, float z_ref) { return (h.z - z_ref) + h.w; }
+
+// Corrected cluster (see apply_displacement); theta == nullptr means no map.
+// The coefficients must be finite.
 __device__ __forceinline__ float4 correct_cluster(const float* __restrict__ theta, float xm, float ym,
                                                   float zm, float alpha) {
   float r;
@@ -379,7 +387,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
   int qtried = 0;
   int64_t t = -1, hb = 0, cb = 0;
   int i = 0, n = 0;
-  float chi2 = 0.0f;
+  float chi2 = 0.0f, zref = 0.0f;
   KState q{};
   float4 hn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // corrected cluster of hit i
   int64_t idn = 0;                                  // xyz index of hit i + 1
@@ -425,7 +433,8 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
           } else {
             hb = in.hit_begin[t];
             const float4 h0 = xyz[xyz_index(hb)];
-            seed_state(q, h0.x, h0.y, h0.z, in.seed + 5 * t, p);
+            zref = h0.z;
+            seed_state(q, h0.x, h0.y, rel_z(h0, zref), in.seed + 5 * t, p);
             cb = ckpt_base(in, t);
             if (ckpt) store_state(ckpt + cb * kCkptFloats, q);
             i = 1;
@@ -441,7 +450,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
       const float4 h = hn;
       if (i + 1 < n) hn = xyz[idn];
       if (i + 2 < n) idn = xyz_index(hb + i + 2);
-      const bool ok = refit_step(q, h.x, h.y, h.z, p, &chi2);
+      const bool ok = refit_step(q, h.x, h.y, rel_z(h, zref), p, &chi2);
       if (ok && ckpt && i % kCkpt == 0) store_state(ckpt + (cb + i / kCkpt) * kCkptFloats, q);
       ++i;
       if (!ok || i == n) {
@@ -816,6 +825,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams
     const int64_t cb = ckpt_base(in, t);
     float* scr = ws.scratch + t % ws.n_lanes * (kCkpt * kCkptFloats);
     const float4* xyz = reinterpret_cast<const float4*>(ws.xyz);
+    const float zref = xyz[hb].z;
     KBar g{};
     const int nseg = (n - 2) / kCkpt + 1;  // segments covering steps 1..n-1
     for (int m = nseg - 1; m >= 0; --m) {
@@ -828,7 +838,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams
         if (i + 1 < i_hi) {
           const float4 h = xyz[hb + i + 1];
           float dummy = 0.0f;
-          refit_step(q, h.x, h.y, h.z, p, &dummy);
+          refit_step(q, h.x, h.y, rel_z(h, zref), p, &dummy);
         }
       }
       // reverse sweep over the segment's steps i = i_hi .. i_lo + 1
@@ -836,7 +846,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams
         const KState prev = load_state(scr + (i - 1 - i_lo) * kCkptFloats);
         const float4 h = xyz[hb + i];
         float gx1, gmy, gmz;
-        refit_step_reverse(prev, h.x, h.y, h.z, p, gchi2, g, &gx1, &gmy, &gmz);
+        refit_step_reverse(prev, h.x, h.y, rel_z(h, zref), p, gchi2, g, &gx1, &gmy, &gmz);
         float r;
         const HitGeom hg = hit_geom(in.row_x[in.hit_row[hb + i]], in.y[in.hit_id[hb + i]],
                                     in.z[in.hit_id[hb + i]], alpha, &r);

@@ -80,7 +80,7 @@ struct Layout {
   size_t bytes;
 };
 
-constexpr int kKeepBlocks = 512;
+constexpr int kKeepBlocks = 4096;
 
 int blocks_for(int64_t n, int b) { return int((n + b - 1) / b); }
 
@@ -427,7 +427,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   mark(4);
   hipLaunchKernelGGL(k_keep_count, dim3(kKeepBlocks), dim3(256), 0, stream, out->counts, cap_start,
                      L.tmp.rec, c->dp.min_hits, L.part);
-  hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(64), 0, stream, L.part, kKeepBlocks, out->counts,
+  hipLaunchKernelGGL(k_keep_scan, dim3(1), dim3(kKeepScanThreads), 0, stream, L.part, kKeepBlocks, out->counts,
                      out->cap_tracks, out->cap_hits);
   hipLaunchKernelGGL(k_keep_write, dim3(kKeepBlocks), dim3(kKeepBlock), 0, stream, out->counts,
                      cap_start, L.starts, L.tmp, c->dp.min_hits, L.part, o);

@@ -57,6 +57,32 @@ struct Grid {
   }
 };
 
+// The binning of one grid row k = unit * n_rows + r, read once: a search can
+// load it before the state it searches for is known.
+struct RowView {
+  UnitZ uz;
+  RowInfo ri;
+  int64_t base;  // first bin of the row
+  int nz;
+
+  __device__ __forceinline__ RowView(const Grid& g, int k, int r) {
+    uz = g.row_z[k];
+    ri = g.rows[r];
+    base = int64_t(k / g.n_rows) * g.btot + int64_t(g.nz) * ri.cum_ny + r;
+    nz = g.nz;
+  }
+  __device__ __forceinline__ int zbin(float z) const {
+    float v = (z - uz.zmin) * uz.inv_bz;
+    v = fminf(fmaxf(v, 0.0f), float(nz - 1));
+    return int(v);
+  }
+  __device__ __forceinline__ int ybin(float y) const {
+    float v = (y - ri.y0) * ri.inv_by;
+    v = fminf(fmaxf(v, 0.0f), float(ri.ny - 1));
+    return int(v);
+  }
+};
+
 // Widening of a search box so that it covers every cluster an exact float
 // predicate can accept (absolute plus relative slack on the coordinate).
 __device__ __forceinline__ float box_pad(float v) { return 1e-3f + 1e-6f * fabsf(v); }

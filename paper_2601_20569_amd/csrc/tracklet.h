@@ -139,17 +139,17 @@ __device__ __forceinline__ float kf_update(KState& q, float my, float mz, float 
 // Best cluster of row r (grid row k) by (chi2, caller id) among chi2 <=
 // chi2max, or -1.  The grid box |dy| <= 4 sqrt(Sy), |dz| <= 4 sqrt(Sz) is
 // widened so that it holds every cluster the float chi2 cut can accept.
-__device__ __forceinline__ int32_t kf_search(const Grid& g, int k, int r, const KState& q,
+__device__ __forceinline__ int32_t kf_search(const Grid& g, const RowView& rv, const KState& q,
                                              const DevParams& p, float iSy, float iSz,
                                              float* out_my, float* out_mz) {
   // the hardware square root (within 1 ulp) is enough: the box only has to
   // be large enough, and the 1e-3 relative margin covers its error
   const float hy = __builtin_amdgcn_sqrtf(p.chi2max * (q.cyy + p.sy2)) * 1.001f + box_pad(q.y);
   const float hz = __builtin_amdgcn_sqrtf(p.chi2max * (q.czz + p.sz2)) * 1.001f + box_pad(q.z);
-  const int zb0 = g.zbin(k, q.z - hz), zb1 = g.zbin(k, q.z + hz);
-  const int yb0 = g.ybin(r, q.y - hy), yb1 = g.ybin(r, q.y + hy);
-  const int64_t base = g.row_base(k);
-  const int ny = g.rows[r].ny;
+  const int zb0 = rv.zbin(q.z - hz), zb1 = rv.zbin(q.z + hz);
+  const int yb0 = rv.ybin(q.y - hy), yb1 = rv.ybin(q.y + hy);
+  const int64_t base = rv.base;
+  const int ny = rv.ri.ny;
   int32_t best = -1;
   float bch = 0.0f, bmy = 0.0f, bmz = 0.0f;
   for (int zb = zb0; zb <= zb1; ++zb) {
@@ -218,7 +218,7 @@ constexpr int kConstructBlock = 256;
 constexpr int kHitBuf = 16;
 constexpr int kConstructWaves = kConstructBlock / kWave;
 
-__global__ void __launch_bounds__(kConstructBlock) k_construct(
+__global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
     const int64_t* __restrict__ counts, int64_t cap_start, int32_t* __restrict__ queue, int refill,
     TrackInputs in, Grid g, DevParams p, TrackletTmp out) {
   __shared__ int32_t hbuf[kConstructWaves][kHitBuf][kWave];
@@ -370,6 +370,9 @@ __global__ void __launch_bounds__(kConstructBlock) k_construct(
     const int target = outward ? row + 1
                                : (phase == kDescend ? max(r0, row - p.descent_rows) : row - 1);
     bool ok = target >= 0 && target < R;
+    // the target row's binning does not depend on the propagation: load it first
+    const int trow = min(max(target, 0), R - 1);
+    const RowView rv(g, kbase + trow, trow);
     if (ok) ok = kf_propagate(q, in.row_x[target], p, c_prev, r_prev, cached);
     bool finish = false, to_descend = false;
     if (phase == kDescend) {
@@ -402,7 +405,7 @@ __global__ void __launch_bounds__(kConstructBlock) k_construct(
         c = __float_as_int(P.z);
         chain_next = __float_as_int(P.w);
       } else {
-        c = kf_search(g, kbase + target, target, q, p, iSy, iSz, &my, &mz);
+        c = kf_search(g, rv, q, p, iSy, iSz, &my, &mz);
       }
       row = target;
       if (c >= 0) {
@@ -488,23 +491,39 @@ __global__ void k_keep_count(const int64_t* __restrict__ counts, int64_t cap_sta
   }
 }
 
-__global__ void k_keep_scan(int64_t* __restrict__ part, int nb, int64_t* __restrict__ counts,
-                            int64_t cap_tracks, int64_t cap_hits) {
-  if (threadIdx.x != 0) return;
+// Exclusive scan of the per-block (tracklet, hit) counts, one block of
+// kKeepScanThreads threads, each taking a run of consecutive blocks.
+constexpr int kKeepScanThreads = 1024;
+
+__global__ void __launch_bounds__(kKeepScanThreads) k_keep_scan(int64_t* __restrict__ part, int nb,
+                                                                int64_t* __restrict__ counts,
+                                                                int64_t cap_tracks, int64_t cap_hits) {
+  __shared__ int64_t lds[kKeepScanThreads / kWave];
+  const int per = (nb + kKeepScanThreads - 1) / kKeepScanThreads;
+  const int i0 = min(nb, int(threadIdx.x) * per), i1 = min(nb, i0 + per);
   int64_t t = 0, h = 0;
-  for (int i = 0; i < nb; ++i) {
-    const int64_t a = part[2 * i], c = part[2 * i + 1];
-    part[2 * i] = t;
-    part[2 * i + 1] = h;
-    t += a;
-    h += c;
+  for (int i = i0; i < i1; ++i) {
+    t += part[2 * i];
+    h += part[2 * i + 1];
   }
-  counts[1] = t;
-  counts[2] = h;
-  unsigned long long st = 0;
-  if (t > cap_tracks) st |= 2ull;
-  if (h > cap_hits) st |= 4ull;
-  if (st) atomicOr((unsigned long long*)&counts[3], st);
+  int64_t tt, th;
+  int64_t pt = block_exclusive_scan(t, lds, &tt);
+  int64_t ph = block_exclusive_scan(h, lds, &th);
+  for (int i = i0; i < i1; ++i) {
+    const int64_t a = part[2 * i], c = part[2 * i + 1];
+    part[2 * i] = pt;
+    part[2 * i + 1] = ph;
+    pt += a;
+    ph += c;
+  }
+  if (threadIdx.x == 0) {
+    counts[1] = tt;
+    counts[2] = th;
+    unsigned long long st = 0;
+    if (tt > cap_tracks) st |= 2ull;
+    if (th > cap_hits) st |= 4ull;
+    if (st) atomicOr((unsigned long long*)&counts[3], st);
+  }
 }
 
 struct TrackOut {
