@@ -47,6 +47,40 @@ B_REFIT_PER_REFIT = 24         # refitted tracklet: hit offset, unit, seed (sin 
 B_REFIT_PER_HIT = 13           # id + row of the attached cluster, its measured y, z
 
 
+# kernels of each stage, for the recorded HBM traffic (profiles/)
+STAGE_KERNELS = {"grid": ["k_grid_build"], "neighbours": ["k_neighbours"],
+                 "starts": ["k_clean_starts", "k_write_starts"], "construct": ["k_construct"],
+                 "compact": ["k_keep_count", "k_keep_write"], "refit": ["k_correct_clusters", "k_refit_filter"]}
+
+
+def recorded_traffic(stage, workload):
+    """HBM bytes per launch of a stage's kernels from the committed counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_20569_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    rec, sha = {}, None
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch "):
+            k, v = line[len("traffic_bytes_per_launch "):].split(":")
+            rec[k.strip()] = int(v)
+    if sha != h.hexdigest():
+        return None
+    ks = STAGE_KERNELS.get(stage, [])
+    if not ks or any(k not in rec for k in ks):
+        return None
+    return sum(rec[k] for k in ks)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -173,6 +207,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-forms", action="store_true", help="skip the plain and adjoint comparisons")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed tuning as JSON (the dict an autotuned run prints); skips the autotuner")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one plain 1 GiB device-to-device copy kernel (reference for HBM counters)")
     args = ap.parse_args()
@@ -216,14 +252,18 @@ def main():
     tr = make_tracker(U, N)
     n_start, n_tracks, n_hits = size_run(tr, rb, y, z, U)
     log(f"tracklets: {n_start} start hits, {n_tracks} kept, {n_hits} attached clusters")
-    bufs = tr.allocate_batched(U, N, cap_start=n_start + 1, cap_tracks=n_tracks + 1, cap_hits=n_hits + 1,
-                               autotune=not args.no_autotune)
     alpha = torch.as_tensor(G.sector_alpha(B["sectors"]).astype(np.float32), device=dev)
     theta = torch.as_tensor(np.random.default_rng(1).normal(0.0, 0.05, 36720).astype(np.float32),
                             device=dev)
     stream = torch.cuda.Stream()
     tuning = None
-    if not args.no_autotune:
+    if args.tuning:
+        tuning = json.loads(args.tuning)
+        tr.set_tuning(tuning)
+        log(f"fixed tuning {tuning}")
+    bufs = tr.allocate_batched(U, N, cap_start=n_start + 1, cap_tracks=n_tracks + 1, cap_hits=n_hits + 1,
+                               autotune=not (args.no_autotune or args.tuning))
+    if not (args.no_autotune or args.tuning):
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
             tuning = tr.autotune_batched(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta)
@@ -330,9 +370,10 @@ def main():
     roof = None
     if b is not None:
         gbs = b / (stage_ms[dom] * 1e-3) / 1e9
+        tr_b = recorded_traffic(dom, cfg["workload"])
         roof = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs / HBM_PEAK_GBS, 5), traffic=None, kernel=dom,
-                    kernel_ms=round(stage_ms[dom], 4), alg_bytes=int(b))
+                    frac=round(gbs / HBM_PEAK_GBS, 5), traffic=tr_b, kernel=dom,
+                    kernels=STAGE_KERNELS.get(dom), kernel_ms=round(stage_ms[dom], 4), alg_bytes=int(b))
 
     known = [k for k in stage_ms if stage_bytes.get(k) is not None]
     path = None
