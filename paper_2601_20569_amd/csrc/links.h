@@ -32,19 +32,47 @@ __device__ __forceinline__ int32_t id_of(const float4& p) { return __float_as_in
 __device__ __forceinline__ int32_t cup_of(const float4& p) { return __float_as_int(p.w); }
 
 // Sorted positions of the window candidates of one row around (yh, zh) into
-// LDS (up to kNfD); returns their number (which may exceed kNfD).
+// LDS (up to kNfD); returns their number (which may exceed kNfD).  The bin
+// ranges of up to kNfZ z bins are loaded in one round, then the candidates two
+// at a time, so a lane has several loads in flight.
+constexpr int kNfZ = 6;
+
 __device__ __forceinline__ int nf_collect(const Grid& g, int64_t kb, int ny, int zb0, int zb1, int yb0,
                                           int yb1, float yh, float zh, float wy, float wz,
                                           int32_t (*pos)[kNfBlock], int t) {
   int n = 0;
+  auto take = [&](const float4& pc, int32_t j) {
+    if (!(fabsf(pc.x - yh) <= wy && fabsf(pc.y - zh) <= wz)) return;
+    if (n < kNfD) pos[n][t] = j;
+    ++n;
+  };
+  const int nzb = zb1 - zb0 + 1;
+  if (nzb <= kNfZ) {
+    int32_t s[kNfZ], e[kNfZ];
+#pragma unroll
+    for (int q = 0; q < kNfZ; ++q) {
+      if (q < nzb) {
+        s[q] = g.bin_start[kb + (zb0 + q) * ny + yb0];
+        e[q] = g.bin_start[kb + (zb0 + q) * ny + yb1 + 1];
+      } else {
+        s[q] = e[q] = 0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kNfZ; ++q) {
+      for (int32_t j = s[q]; j < e[q]; j += 2) {
+        const bool two = j + 1 < e[q];
+        const float4 pa = g.pts[j];
+        const float4 pb = g.pts[two ? j + 1 : j];
+        take(pa, j);
+        if (two) take(pb, j + 1);
+      }
+    }
+    return n;
+  }
   for (int zb = zb0; zb <= zb1; ++zb) {
     const int32_t j0 = g.bin_start[kb + zb * ny + yb0], j1 = g.bin_start[kb + zb * ny + yb1 + 1];
-    for (int32_t j = j0; j < j1; ++j) {
-      const float4 pc = g.pts[j];
-      if (!(fabsf(pc.x - yh) <= wy && fabsf(pc.y - zh) <= wz)) continue;
-      if (n < kNfD) pos[n][t] = j;
-      ++n;
-    }
+    for (int32_t j = j0; j < j1; ++j) take(g.pts[j], j);
   }
   return n;
 }

@@ -42,16 +42,6 @@ constexpr int kRefitBlock = 256;
 constexpr int kWinPhi = 8;           // phi nodes held in the LDS accumulation window
 constexpr double kFixScale = 4294967296.0;  // 2^32
 
-__device__ __forceinline__ float bspline3(float t) {
-  const float a = fabsf(t);
-  if (a < 1.0f) return (4.0f - 6.0f * a * a + 3.0f * a * a * a) * (1.0f / 6.0f);
-  if (a < 2.0f) {
-    const float b = 2.0f - a;
-    return b * b * b * (1.0f / 6.0f);
-  }
-  return 0.0f;
-}
-
 __device__ __forceinline__ int map_index(int comp, int i, int j, int k) {
   return ((comp * kMapNPhi + i) * kMapNR + j) * kMapNZ + k;
 }
@@ -62,27 +52,36 @@ struct Weights4 {
   float w[4];
 };
 
-__device__ __forceinline__ Weights4 weights_phi(float phi) {
-  float ph = fmodf(phi, 6.28318530717958647692f);
-  if (ph < 0.0f) ph += 6.28318530717958647692f;
-  const float u = ph / kMapDPhi;
-  const int i0 = int(floorf(u));
+// Weights of the uniform cubic B-spline at the four nodes first .. first+3
+// around u (node spacing 1), from the fractional part f of u: (1-f)^3/6,
+// (3f^3 - 6f^2 + 4)/6, (-3f^3 + 3f^2 + 3f + 1)/6, f^3/6.
+__device__ __forceinline__ Weights4 weights_frac(float u) {
+  const float fl = floorf(u);
+  const float f = u - fl, g = 1.0f - f;
+  const float f2 = f * f, f3 = f2 * f;
   Weights4 W;
-  W.first = i0 - 1;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) W.w[a] = bspline3(u - float(i0 - 1 + a));
+  W.first = int(fl) - 1;
+  W.w[0] = g * g * g * (1.0f / 6.0f);
+  W.w[1] = (3.0f * f3 - 6.0f * f2 + 4.0f) * (1.0f / 6.0f);
+  W.w[2] = (-3.0f * f3 + 3.0f * f2 + 3.0f * f + 1.0f) * (1.0f / 6.0f);
+  W.w[3] = f3 * (1.0f / 6.0f);
   return W;
 }
 
-__device__ __forceinline__ Weights4 weights_lin(float x, float x0, float dx, int n) {
-  const float u = (x - x0) / dx;
-  const int i0 = int(floorf(u));
-  Weights4 W;
-  W.first = i0 - 1;
+// phi nodes: periodic, u = phi / 10 degrees wrapped into [0, 36)
+__device__ __forceinline__ Weights4 weights_phi(float phi) {
+  float u = phi * (1.0f / kMapDPhi);
+  u = u - float(kMapNPhi) * floorf(u * (1.0f / kMapNPhi));
+  return weights_frac(u);
+}
+
+// r or z nodes x0 + i dx, i = 0 .. n-1; nodes outside have weight 0
+__device__ __forceinline__ Weights4 weights_lin(float x, float x0, float inv_dx, int n) {
+  Weights4 W = weights_frac((x - x0) * inv_dx);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    const int i = i0 - 1 + a;
-    W.w[a] = (i >= 0 && i < n) ? bspline3(u - float(i)) : 0.0f;
+    const int i = W.first + a;
+    if (i < 0 || i >= n) W.w[a] = 0.0f;
   }
   return W;
 }
@@ -154,17 +153,17 @@ __device__ __forceinline__ void map_displacement(const Theta& th, const Weights4
       for (int c = 0; c < 4; ++c) {
         const int k = min(max(wz.first + c, 0), kMapNZ - 1);
         const float4 v = th(i, j, k);
-        f0 += v.x * wz.w[c];
-        f1 += v.y * wz.w[c];
-        f2 += v.z * wz.w[c];
+        f0 = __builtin_fmaf(v.x, wz.w[c], f0);
+        f1 = __builtin_fmaf(v.y, wz.w[c], f1);
+        f2 = __builtin_fmaf(v.z, wz.w[c], f2);
       }
-      e0 += f0 * wr.w[b];
-      e1 += f1 * wr.w[b];
-      e2 += f2 * wr.w[b];
+      e0 = __builtin_fmaf(f0, wr.w[b], e0);
+      e1 = __builtin_fmaf(f1, wr.w[b], e1);
+      e2 = __builtin_fmaf(f2, wr.w[b], e2);
     }
-    d[0] += e0 * wp.w[a];
-    d[1] += e1 * wp.w[a];
-    d[2] += e2 * wp.w[a];
+    d[0] = __builtin_fmaf(e0, wp.w[a], d[0]);
+    d[1] = __builtin_fmaf(e1, wp.w[a], d[1]);
+    d[2] = __builtin_fmaf(e2, wp.w[a], d[2]);
   }
 }
 
@@ -189,8 +188,8 @@ __device__ __forceinline__ float4 correct_cluster(const float* __restrict__ thet
   const HitGeom h = hit_geom(xm, ym, zm, alpha, &r);
   float d[3] = {0.0f, 0.0f, 0.0f};
   if (theta)
-    map_displacement(ThetaGlobal{theta}, weights_phi(h.phi), weights_lin(r, kMapR0, kMapDR, kMapNR),
-                     weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ), d);
+    map_displacement(ThetaGlobal{theta}, weights_phi(h.phi), weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR),
+                     weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ), d);
   return apply_displacement(h, d);
 }
 
@@ -353,8 +352,8 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     float r;
     const HitGeom h = hit_geom(x, y[c], z[c], alpha, &r);
     const Weights4 wp = weights_phi(h.phi);
-    const Weights4 wr = weights_lin(r, kMapR0, kMapDR, kMapNR);
-    const Weights4 wz = weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ);
+    const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
+    const Weights4 wz = weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
     float d[3];
     if (ts.covers(wp.first, wr.first))
       map_displacement(ts, wp, wr, wz, d);
@@ -765,8 +764,8 @@ __device__ __forceinline__ void add_hit_gradient(const HitGeom& h, float r, floa
   const float gdp = (-gxc * h.ym + gyc * h.xm) * h.inv_r;
   const float gdz = gzc;
   const Weights4 wp = weights_phi(h.phi);
-  const Weights4 wr = weights_lin(r, kMapR0, kMapDR, kMapNR);
-  const Weights4 wz = weights_lin(h.zm, kMapZ0, kMapDZ, kMapNZ);
+  const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
+  const Weights4 wz = weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
   for (int a = 0; a < 4; ++a) {
     const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
     int rel = i - wref;

@@ -152,22 +152,40 @@ __device__ __forceinline__ int32_t kf_search(const Grid& g, const RowView& rv, c
   const int ny = rv.ri.ny;
   int32_t best = -1;
   float bch = 0.0f, bmy = 0.0f, bmz = 0.0f;
-  for (int zb = zb0; zb <= zb1; ++zb) {
+  auto take = [&](const float4& m) {
+    const float my = m.x, mz = m.y;
+    const float ry = my - q.y;
+    const float rz = mz - q.z;
+    const float ch = (ry * ry) * iSy + (rz * rz) * iSz;
+    if (!(ch <= p.chi2max)) return;
+    const int32_t id = __float_as_int(m.z);
+    if (best < 0 || ch < bch || (ch == bch && id < best)) {
+      best = id;
+      bch = ch;
+      bmy = my;
+      bmz = mz;
+    }
+  };
+  for (int zb = zb0; zb <= zb1; zb += 2) {
+    // two z bins' ranges at once, then their candidates two at a time
+    const bool z2 = zb + 1 <= zb1;
     const int32_t j0 = g.bin_start[base + zb * ny + yb0], j1 = g.bin_start[base + zb * ny + yb1 + 1];
-    for (int32_t j = j0; j < j1; ++j) {
-      const float4 m = g.pts[j];
-      const float my = m.x, mz = m.y;
-      const float ry = my - q.y;
-      const float rz = mz - q.z;
-      const float ch = (ry * ry) * iSy + (rz * rz) * iSz;
-      if (!(ch <= p.chi2max)) continue;
-      const int32_t id = __float_as_int(m.z);
-      if (best < 0 || ch < bch || (ch == bch && id < best)) {
-        best = id;
-        bch = ch;
-        bmy = my;
-        bmz = mz;
-      }
+    const int zc = z2 ? zb + 1 : zb;
+    int32_t k0 = g.bin_start[base + zc * ny + yb0], k1 = g.bin_start[base + zc * ny + yb1 + 1];
+    if (!z2) k1 = k0;
+    for (int32_t j = j0; j < j1; j += 2) {
+      const bool two = j + 1 < j1;
+      const float4 ma = g.pts[j];
+      const float4 mb = g.pts[two ? j + 1 : j];
+      take(ma);
+      if (two) take(mb);
+    }
+    for (int32_t j = k0; j < k1; j += 2) {
+      const bool two = j + 1 < k1;
+      const float4 ma = g.pts[j];
+      const float4 mb = g.pts[two ? j + 1 : j];
+      take(ma);
+      if (two) take(mb);
     }
   }
   *out_my = bmy;
