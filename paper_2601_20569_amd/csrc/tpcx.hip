@@ -436,7 +436,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
 
 void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_tracks* out,
                          const tpcx_batch_refit* refit, const BatchRefitLayout& RL,
-                         const tpcx_tuning& t, hipStream_t stream) {
+                         const tpcx_tuning& t, const float4* pts, hipStream_t stream) {
   RefitIn r;
   r.n_tracks = out->cap_tracks;
   r.n_tracks_dev = out->counts + 1;
@@ -458,7 +458,7 @@ void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_
   if (in->n_clusters > 0)
     hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, stream,
                        c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
-                       refit->theta, RL.corr);
+                       refit->theta, pts, RL.corr);
   hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, out->cap_tracks, t.refit_grid)),
                      dim3(kRefitBlock), 0, stream, r, c->dp, RL.corr, 1, static_cast<float*>(nullptr),
                      RL.queue, t.refit_refill, refit->chi2, refit->ok);
@@ -537,7 +537,7 @@ tpcx_status autotune_run(const tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   const BatchRefitLayout RL = carve_batch_refit(static_cast<char*>(ws) + L.bytes, in->n_clusters);
   if (L.bytes + RL.bytes > ws_bytes) return TPCX_E_ARG;
   enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
-  if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
+  if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
@@ -687,7 +687,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   if (hipEvent_t* ev = next_timing_slot(c)) {
     // timed run: the same sequence launched directly, with stage events
     enqueue_track(c, in, L, t, cap_start, out, stream, ev);
-    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
     (void)hipEventRecord(ev[TPCX_N_STAGES], stream);
     return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
   }
@@ -698,7 +698,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
     enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
-    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipStreamEndCapture(stream, &g);
     if (e1 != hipSuccess || !g) return TPCX_E_HIP;

@@ -130,3 +130,29 @@ def test_autograd_function_uses_the_adjoint():
     (g,) = torch.autograd.grad(loss, theta)
     want = job.backward(ok)
     np.testing.assert_array_equal(g.cpu().numpy(), want.cpu().numpy())
+
+
+def test_adjoint_matches_central_differences_of_fp64_refit():
+    """Directional derivatives of sum_t w_t chi2_t: the GPU adjoint against
+    central finite differences (h = 1e-3 cm) of the FP64 oracle refit."""
+    import torch
+    print("case: adjoint vs central differences, 6 directions", flush=True)
+    cs, tk = _case(n_primaries=1500, stride=3)
+    job, _ = _job(cs, tk)
+    rng = np.random.default_rng(21)
+    theta = rng.normal(0.0, 0.05, oracle.map_ncoef())
+    job.forward(torch.as_tensor(theta, dtype=torch.float32, device="cuda"))
+    ok = job.ok[:job.n_tracks].cpu().numpy().astype(bool)
+    _, ok_ref = oracle.refit(cs, tk, theta)
+    w = rng.uniform(0.5, 1.5, job.n_tracks) * (ok & ok_ref)
+    g = job.backward(torch.as_tensor(w, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    h = 1e-3
+    for _ in range(6):
+        v = rng.normal(size=len(theta))
+        v /= np.linalg.norm(v)
+        cp, okp = oracle.refit(cs, tk, theta + h * v)
+        cm, okm = oracle.refit(cs, tk, theta - h * v)
+        assert (okp == ok_ref).all() and (okm == ok_ref).all()
+        fd = float(w @ (cp - cm)) / (2 * h)
+        print(f"directional derivative: gpu {g @ v:.6g} fd {fd:.6g}")
+        assert abs(g @ v - fd) <= 1e-3 * np.linalg.norm(g), (g @ v, fd)
