@@ -218,7 +218,10 @@ tpcx_status tpcx_refit_backward(tpcx_ctx* ctx, const tpcx_refit_in* in, const fl
  * and the refit of every tracklet with at least refit->min_hits clusters run
  * as one HIP graph: captured on the first call with a given set of arguments,
  * replayed by later calls with the same arguments.  The stream must be one
- * that can be captured (not the legacy default stream).  The persistent
+ * that can be captured (not the legacy default stream).  The correction of
+ * the clusters for the refit needs only the search grid: it runs on a second
+ * stream owned by the context, forked after the grid build and joined before
+ * the refit filter (both branches are in the graph).  The persistent
  * kernels (tracklet constructor, refit) take their work counts from the
  * device, so a replay needs no host synchronisation.
  * ------------------------------------------------------------------------ */
@@ -275,7 +278,7 @@ tpcx_status tpcx_autotune_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* 
 #define TPCX_STAGE_STARTS 2     /* cleaning, start flags, ordered compaction */
 #define TPCX_STAGE_CONSTRUCT 3  /* tracklet constructor */
 #define TPCX_STAGE_COMPACT 4    /* ordered compaction of the kept tracklets */
-#define TPCX_STAGE_REFIT 5      /* refit (batched form only; zero otherwise) */
+#define TPCX_STAGE_REFIT 5      /* refit filter, from the end of the compaction (batched form only) */
 #define TPCX_N_STAGES 6
 
 /* Record HIP events on the call's stream around every stage of the next

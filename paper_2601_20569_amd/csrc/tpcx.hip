@@ -40,6 +40,10 @@ struct tpcx_ctx {
   int32_t timing_max = 0, timing_used = 0;
   // batched form: the graph of the last argument set
   hipGraphExec_t graph = nullptr;
+  // batched form: a second stream for the cluster correction, which needs
+  // only the search grid and runs beside the tracking stages
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<unsigned char> graph_key;
 };
 
@@ -315,7 +319,10 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
             hipMemcpy(c->d_row_x, c->row_x.data(), sizeof(float) * c->n_rows,
                       hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(c->d_frac, c->frac.data(), sizeof(float) * c->n_rows,
-                      hipMemcpyHostToDevice) == hipSuccess;
+                      hipMemcpyHostToDevice) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
   if (!ok || build_rows(c) != TPCX_OK) {
     tpcx_destroy(c);
     return TPCX_E_HIP;
@@ -328,6 +335,9 @@ void tpcx_destroy(tpcx_ctx* c) {
   if (!c) return;
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   if (c->d_row_x) (void)hipFree(c->d_row_x);
   if (c->d_frac) (void)hipFree(c->d_frac);
   if (c->d_rows) (void)hipFree(c->d_rows);
@@ -367,7 +377,8 @@ tpcx_status check_track_args(const tpcx_ctx* c, const tpcx_clusters* in, const v
 // per stage boundary.  No host synchronisation and no memset, so the sequence
 // can be captured into a graph.
 void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, const tpcx_tuning& t,
-                   int64_t cap_start, const tpcx_tracks* out, hipStream_t stream, hipEvent_t* ev) {
+                   int64_t cap_start, const tpcx_tracks* out, hipStream_t stream, hipEvent_t* ev,
+                   hipEvent_t after_grid = nullptr) {
   const int32_t U = in->n_units;
   const int R = c->n_rows;
   const int B = t.block;
@@ -389,6 +400,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
   hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,
                      in->z, g, L.row_z, L.bins, L.pts);
+  if (after_grid) (void)hipEventRecord(after_grid, stream);
   mark(1);
   hipLaunchKernelGGL(k_neighbours, dim3(UR), dim3(kNfBlock), 0, stream, in->row_begin, g,
                      c->d_frac, c->dp, L.up, L.down);
@@ -434,9 +446,21 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   mark(5);
 }
 
+// The batched refit: the cluster correction on c->aux (it needs only the search
+// grid, so it overlaps the tracking stages), the filter on `stream` once both
+// the tracking and the correction are done.  enqueue_track must have recorded
+// c->ev_fork after the grid build.
 void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_tracks* out,
                          const tpcx_batch_refit* refit, const BatchRefitLayout& RL,
                          const tpcx_tuning& t, const float4* pts, hipStream_t stream) {
+  (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
+  const int64_t n_ur = int64_t(in->n_units) * c->n_rows;
+  if (in->n_clusters > 0)
+    hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, c->aux,
+                       c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
+                       refit->theta, pts, RL.corr);
+  (void)hipEventRecord(c->ev_join, c->aux);
+
   RefitIn r;
   r.n_tracks = out->cap_tracks;
   r.n_tracks_dev = out->counts + 1;
@@ -454,11 +478,7 @@ void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_
   r.row_x = c->d_row_x;
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, reinterpret_cast<int64_t*>(RL.queue),
                      int64_t(kXcds), int64_t(0));
-  const int64_t n_ur = int64_t(in->n_units) * c->n_rows;
-  if (in->n_clusters > 0)
-    hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, stream,
-                       c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
-                       refit->theta, pts, RL.corr);
+  (void)hipStreamWaitEvent(stream, c->ev_join, 0);
   hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, out->cap_tracks, t.refit_grid)),
                      dim3(kRefitBlock), 0, stream, r, c->dp, RL.corr, 1, static_cast<float*>(nullptr),
                      RL.queue, t.refit_refill, refit->chi2, refit->ok);
@@ -536,7 +556,7 @@ tpcx_status autotune_run(const tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   const Layout L = carve(c, ws, in->n_units, in->n_clusters, cap_start, t.n_zbins, t.block);
   const BatchRefitLayout RL = carve_batch_refit(static_cast<char*>(ws) + L.bytes, in->n_clusters);
   if (L.bytes + RL.bytes > ws_bytes) return TPCX_E_ARG;
-  enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
+  enqueue_track(c, in, L, t, cap_start, out, stream, nullptr, refit ? c->ev_fork : nullptr);
   if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
@@ -686,7 +706,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
 
   if (hipEvent_t* ev = next_timing_slot(c)) {
     // timed run: the same sequence launched directly, with stage events
-    enqueue_track(c, in, L, t, cap_start, out, stream, ev);
+    enqueue_track(c, in, L, t, cap_start, out, stream, ev, refit ? c->ev_fork : nullptr);
     if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
     (void)hipEventRecord(ev[TPCX_N_STAGES], stream);
     return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
@@ -697,7 +717,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
       c->graph = nullptr;
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
-    enqueue_track(c, in, L, t, cap_start, out, stream, nullptr);
+    enqueue_track(c, in, L, t, cap_start, out, stream, nullptr, refit ? c->ev_fork : nullptr);
     if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipStreamEndCapture(stream, &g);
