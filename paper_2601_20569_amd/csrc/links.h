@@ -174,8 +174,7 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
 // link itself (chain of >= 3).  Writes the row's number of start hits.
 __global__ void k_clean_starts(const int64_t* __restrict__ row_begin, const int32_t* __restrict__ up,
                                const int32_t* __restrict__ down, float4* __restrict__ pts,
-                               int32_t* __restrict__ cdown, uint8_t* __restrict__ flag,
-                               int32_t* __restrict__ row_cnt) {
+                               uint8_t* __restrict__ flag, int32_t* __restrict__ row_cnt) {
   __shared__ int32_t wcnt[1024 / kWave];
   const int k = int(xcd_block());
   const int64_t b = row_begin[k], e = row_begin[k + 1];
@@ -185,7 +184,6 @@ __global__ void k_clean_starts(const int64_t* __restrict__ row_begin, const int3
     const int32_t cu = (u >= 0 && down[u] == i) ? u : -1;
     const int32_t cd = (d >= 0 && up[d] == i) ? d : -1;
     pts[i].w = __int_as_float(cu);
-    cdown[i] = cd;
     bool st = false;
     if (cd < 0 && cu >= 0) {
       const int32_t uu = up[cu];
@@ -283,10 +281,11 @@ __global__ void k_write_starts(const int64_t* __restrict__ row_begin, const floa
   }
 }
 
-// Debug view of the links in caller ids, at the caller's cluster positions.
+// Debug view of the links in caller ids, at the caller's cluster positions
+// (the cleaned down link is recomputed: mutual links only).
 __global__ void k_links_to_caller(int64_t n, const float4* __restrict__ pts,
                                   const int32_t* __restrict__ up, const int32_t* __restrict__ down,
-                                  const int32_t* __restrict__ cdown, int32_t* __restrict__ link_up,
+                                  int32_t* __restrict__ link_up,
                                   int32_t* __restrict__ link_down, int32_t* __restrict__ clean_up,
                                   int32_t* __restrict__ clean_down) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -297,7 +296,10 @@ __global__ void k_links_to_caller(int64_t n, const float4* __restrict__ pts,
   if (link_up) link_up[h] = id(up[i]);
   if (link_down) link_down[h] = id(down[i]);
   if (clean_up) clean_up[h] = id(cup_of(p));
-  if (clean_down) clean_down[h] = id(cdown[i]);
+  if (clean_down) {
+    const int32_t d = down[i];
+    clean_down[h] = id((d >= 0 && up[d] == i) ? d : -1);
+  }
 }
 
 }  // namespace tpcx

@@ -71,7 +71,6 @@ struct Layout {
   float4* pts;
   int32_t* up;
   int32_t* down;
-  int32_t* cdown;
   uint8_t* flag;
   int32_t* row_cnt;
   int32_t* row_off;
@@ -99,7 +98,6 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   L.pts = cv.take<float4>(n);
   L.up = cv.take<int32_t>(n);
   L.down = cv.take<int32_t>(n);
-  L.cdown = cv.take<int32_t>(n);
   L.flag = cv.take<uint8_t>(n);
   L.row_cnt = cv.take<int32_t>(int64_t(n_units) * c->n_rows);
   L.row_off = cv.take<int32_t>(int64_t(n_units) * c->n_rows);
@@ -406,7 +404,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
                      c->d_frac, c->dp, L.up, L.down);
   mark(2);
   hipLaunchKernelGGL(k_clean_starts, dim3(UR), dim3(B), 0, stream, in->row_begin, L.up, L.down,
-                     L.pts, L.cdown, L.flag, L.row_cnt);
+                     L.pts, L.flag, L.row_cnt);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, stream, L.row_cnt, int64_t(UR),
                      L.row_off, out->counts, cap_start, out->counts + 3,
                      int64_t(TPCX_ST_START_OVERFLOW));
@@ -587,7 +585,7 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   if (dbg) {
     if (N > 0 && (dbg->link_up || dbg->link_down || dbg->clean_up || dbg->clean_down))
       hipLaunchKernelGGL(k_links_to_caller, dim3(blocks_for(N, 256)), dim3(256), 0, stream, N,
-                         L.pts, L.up, L.down, L.cdown, dbg->link_up, dbg->link_down, dbg->clean_up,
+                         L.pts, L.up, L.down, dbg->link_up, dbg->link_down, dbg->clean_up,
                          dbg->clean_down);
     if (dbg->starts && cap_start)
       (void)hipMemcpyAsync(dbg->starts, L.starts, size_t(cap_start) * sizeof(int32_t),
