@@ -83,6 +83,10 @@ def lib():
         L.orc_track.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P, P,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_free.argtypes = [P]
+        L.orc_nf_margins.restype = ctypes.c_int64
+        L.orc_nf_margins.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double, P]
+        L.orc_margins.restype = ctypes.c_int64
+        L.orc_margins.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double, P]
         L.orc_len.restype = ctypes.c_int64
         L.orc_len.argtypes = [P, ctypes.c_char_p]
         L.orc_get.restype = ctypes.c_int
@@ -151,6 +155,26 @@ def track(cs, params: Params | None = None, precision=32, brute=False, units=Non
                            window_candidates=int(c[3]), attached=int(c[4]), chain=int(c[5]),
                            box_candidates=int(c[6]))
     return out
+
+
+def nf_margins(cs, eps=1e-5, params: Params | None = None, row_x=None, constructor=False):
+    """Clusters whose neighbour-finder decision lies within eps (relative,
+    at least absolute) of a threshold when evaluated in double: a window
+    test, the D cut, or the gap between the best and second-best D; with
+    constructor=True also the chi2 cut and the best-vs-second gap of every
+    search of the double-precision constructor.  Returns a bool array over the
+    clusters."""
+    from synth import geometry as G
+    params = params or Params()
+    xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
+    rb = np.ascontiguousarray(cs.row_begin, dtype=np.int64)
+    y = np.ascontiguousarray(cs.y, dtype=np.float32)
+    z = np.ascontiguousarray(cs.z, dtype=np.float32)
+    flags = np.zeros(len(y), np.uint8)
+    ps = params.c_struct()
+    fn = lib().orc_margins if constructor else lib().orc_nf_margins
+    fn(_p(xr), len(xr), ctypes.byref(ps), cs.n_units, _p(rb), _p(y), _p(z), float(eps), _p(flags))
+    return flags.astype(bool)
 
 
 def kept_tracklets(res):

@@ -170,6 +170,10 @@ struct Searcher {
   const Unit& un;
   bool brute;
   const Consts<T>& c;
+  // margin check (see orc_margins): when set, candidates whose chi2 lies
+  // within eps of the cut or of the best one are marked
+  uint8_t* margin_flags = nullptr;
+  double eps = 0.0;
   // Best cluster of row r by (chi2, index) among those with chi2 <= chi2max.
   // n_box counts the clusters scanned; n_cand those inside the chi2 box
   // |dy| <= sqrt(chi2max Sy), |dz| <= sqrt(chi2max Sz), which any
@@ -179,19 +183,28 @@ struct Searcher {
     double sy = std::sqrt(double(c.chi2max) * double(st.cyy + c.sy2));
     double hw = sz * (1.0 + kPadRel) + kPadAbs;
     double lo = double(st.z) - hw, hi = double(st.z) + hw;
-    int64_t bi = -1;
-    T bc = T(0);
+    int64_t bi = -1, si = -1;
+    T bc = T(0), sc = T(0);
+    const double mc = eps * std::max(1.0, double(c.chi2max));
     un.scan(r, brute, lo, hi, [&](int64_t i) {
       ++*n_box;
       if (std::fabs(double(un.y[i]) - double(st.y)) <= sy && std::fabs(double(un.z[i]) - double(st.z)) <= sz)
         ++*n_cand;
       T ch = chi2_of(st, T(un.y[i]), T(un.z[i]), c);
+      if (margin_flags && std::fabs(double(ch) - double(c.chi2max)) <= mc) margin_flags[i] = 1;
       if (!(ch <= c.chi2max)) return;
       if (bi < 0 || ch < bc || (ch == bc && i < bi)) {
+        si = bi;
+        sc = bc;
         bi = i;
         bc = ch;
+      } else if (si < 0 || ch < sc) {
+        si = i;
+        sc = ch;
       }
     });
+    if (margin_flags && si >= 0 && double(sc) - double(bc) <= eps * std::max(1.0, double(bc)))
+      margin_flags[bi] = margin_flags[si] = 1;
     *chi2_out = bc;
     return bi;
   }
@@ -214,14 +227,14 @@ bool descend(State<T>& st, const std::vector<T>& xr, int from, int to, int step,
 template <class T>
 Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, const int32_t* cup,
                       int64_t h0, int r0, bool brute, const Consts<T>& c, int max_misses,
-                      int descent_rows) {
+                      int descent_rows, uint8_t* margin_flags = nullptr, double eps = 0.0) {
   const int R = un.n_rows;
   Tracklet<T> tk;
   tk.start = h0;
   tk.unit = unit_id;
   tk.r0 = r0;
   tk.flags = 0;
-  Searcher<T> se{un, brute, c};
+  Searcher<T> se{un, brute, c, margin_flags, eps};
   std::vector<std::pair<int, int32_t>> att;  // (row, cluster)
 
   std::vector<int64_t> chain{h0};
@@ -436,7 +449,7 @@ struct Result {
 template <class T>
 Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
             const int64_t* row_begin, const float* y, const float* z, int unit_lo, int unit_hi,
-            int n_threads) {
+            int n_threads, uint8_t* margin_flags = nullptr, double eps = 0.0) {
   Consts<T> c = make_consts<T>(p);
   std::vector<T> xr(n_rows);
   for (int r = 0; r < n_rows; ++r) xr[r] = T(row_x[r]);
@@ -477,7 +490,8 @@ Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
     for (int64_t h : starts[k]) {
       int r0 = 0;
       while (!(h >= un.rb[r0] && h < un.rb[r0 + 1])) ++r0;
-      tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses, p.descent_rows));
+      tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses, p.descent_rows,
+                                    margin_flags, eps));
     }
   }
   int64_t np = 0, nprop = 0, nsearch = 0, nbox = 0, natt = 0, nchain = 0, ncand = 0;
@@ -523,6 +537,62 @@ int64_t vlen(const V& v) {
   return int64_t(v.size());
 }
 
+// ---------------------------------------------------------------------------
+// neighbour-finder predicates near their thresholds (input check for the
+// comparison of float and double decisions)
+// ---------------------------------------------------------------------------
+// Marks h when, evaluated in double, one of its decisions lies within
+// eps * max(1, threshold) of going the other way: a window test |dy| <= wy or
+// |dz| <= wz against a cluster of rows r +- 1, a pair's D <= d2max, or the gap
+// between its smallest and second-smallest accepted D.
+int64_t nf_margins_unit(const Unit& un, const std::vector<double>& xr, const OrcParams& p, double eps,
+                        uint8_t* flags) {
+  const int R = un.n_rows;
+  const double wy = p.win_y, wz = p.win_z, d2 = p.d2_max;
+  const double mw = eps * std::max(1.0, std::max(wy, wz)), md = eps * std::max(1.0, d2);
+  int64_t n = 0;
+  for (int r = 1; r + 1 < R; ++r) {
+    const double f = (xr[r] - xr[r - 1]) / (xr[r + 1] - xr[r - 1]);
+    std::vector<int64_t> U, D;
+    for (int64_t h = un.rb[r]; h < un.rb[r + 1]; ++h) {
+      const double yh = un.y[h], zh = un.z[h];
+      bool near = false;
+      U.clear();
+      D.clear();
+      const double lo = zh - wz - kPadAbs - mw, hi = zh + wz + kPadAbs + mw;
+      auto window = [&](int64_t c, std::vector<int64_t>& L) {
+        const double dy = std::fabs(double(un.y[c]) - yh), dz = std::fabs(double(un.z[c]) - zh);
+        if (dy > wy + mw || dz > wz + mw) return;
+        if (std::fabs(dy - wy) <= mw || std::fabs(dz - wz) <= mw) near = true;
+        if (dy <= wy && dz <= wz) L.push_back(c);
+      };
+      un.scan(r + 1, false, lo, hi, [&](int64_t c) { window(c, U); });
+      un.scan(r - 1, false, lo, hi, [&](int64_t c) { window(c, D); });
+      double b1 = std::numeric_limits<double>::infinity(), b2 = b1;
+      for (int64_t u : U)
+        for (int64_t d : D) {
+          const double yu = un.y[u], zu = un.z[u], yd = un.y[d], zd = un.z[d];
+          const double ey = yh - (yd + (yu - yd) * f), ez = zh - (zd + (zu - zd) * f);
+          const double v = ey * ey + ez * ez;
+          if (std::fabs(v - d2) <= md) near = true;
+          if (v > d2) continue;
+          if (v < b1) {
+            b2 = b1;
+            b1 = v;
+          } else if (v < b2) {
+            b2 = v;
+          }
+        }
+      if (std::isfinite(b2) && b2 - b1 <= eps * std::max(1.0, b1)) near = true;
+      if (near) {
+        flags[h] = 1;
+        ++n;
+      }
+    }
+  }
+  return n;
+}
+
 }  // namespace
 
 extern "C" {
@@ -535,6 +605,45 @@ void* orc_track(int precision, const float* row_x, int n_rows, const OrcParams* 
   if (precision == 64)
     return run<double>(row_x, n_rows, *p, n_units, row_begin, y, z, unit_lo, unit_hi, n_threads);
   return run<float>(row_x, n_rows, *p, n_units, row_begin, y, z, unit_lo, unit_hi, n_threads);
+}
+
+// Neighbour-finder decisions within eps of their thresholds, in double:
+// flags[h] = 1 for every such cluster (flags has n_clusters entries, zeroed by
+// the caller); returns their number.
+int64_t orc_nf_margins(const float* row_x, int n_rows, const OrcParams* p, int n_units,
+                       const int64_t* row_begin, const float* y, const float* z, double eps,
+                       uint8_t* flags) {
+  std::vector<double> xr(row_x, row_x + n_rows);
+  int64_t total = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+#endif
+  for (int u = 0; u < n_units; ++u) {
+    Unit un;
+    un.n_rows = n_rows;
+    un.rb = row_begin + int64_t(u) * n_rows;
+    un.y = y;
+    un.z = z;
+    un.build();
+    total += nf_margins_unit(un, xr, *p, eps, flags);
+  }
+  return total;
+}
+
+// The margin check of both stages: orc_nf_margins, then the double-precision
+// tracklet constructor, marking every candidate whose chi2 lies within
+// eps * max(1, chi2max) of the cut, and the best and second-best candidates
+// of a search when their chi2 differ by at most eps * max(1, best).  Returns
+// the number of marked clusters.
+int64_t orc_margins(const float* row_x, int n_rows, const OrcParams* p, int n_units,
+                    const int64_t* row_begin, const float* y, const float* z, double eps,
+                    uint8_t* flags) {
+  orc_nf_margins(row_x, n_rows, p, n_units, row_begin, y, z, eps, flags);
+  delete run<double>(row_x, n_rows, *p, n_units, row_begin, y, z, -1, -1, 0, flags, eps);
+  const int64_t N = row_begin[int64_t(n_units) * n_rows];
+  int64_t n = 0;
+  for (int64_t i = 0; i < N; ++i) n += flags[i] ? 1 : 0;
+  return n;
 }
 
 void orc_free(void* h) { delete static_cast<Result*>(h); }

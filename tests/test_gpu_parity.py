@@ -122,3 +122,16 @@ def test_run_twice_bitwise_identical():
     b = run_gpu(cs, tr)
     for key in ("link_up", "link_down", "starts", "hit_id", "param", "cov", "chi2"):
         np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_gpu_links_equal_double_oracle_on_margin_clean_input():
+    """After the generator's margin step, the GPU's (float) neighbour-finder
+    and cleaning decisions equal the double-precision oracle's."""
+    from margins import margin_clean
+    print("case: central event seed 2, margin-clean, against the double oracle", flush=True)
+    cs, _, _ = margin_clean(synth.central_event(seed=2), seed=2)
+    gpu = run_gpu(cs)
+    ref = oracle.track(cs, precision=64, n_threads=16)
+    for k in ("link_up", "link_down", "clean_up", "clean_down"):
+        np.testing.assert_array_equal(gpu[k], ref[k], err_msg=k)
+    np.testing.assert_array_equal(gpu["starts"], ref["starts"].astype(np.int32))
