@@ -7,8 +7,8 @@ all 576 sector units tracked plus the refit of every tracklet with at least 20
 clusters through a distortion-correction map, as one HIP graph.  One step is
 one replay of that graph with the inputs resident in HBM.
 
-The JSON line also carries: the plain form (one tpcx_track call per slice),
-the adjoint refit (forward + hand-written backward) on a central event, the
+The JSON line also carries: the plain form (one tpcx_track call per slice,
+and one per sector unit), the adjoint refit (forward + hand-written backward) on a central event, the
 roofline position of the dominant kernel (HIP events recorded by the library
 on its stream around every stage), and the CPU oracle timed on a bounded
 sample of the same input.
@@ -335,6 +335,28 @@ def main():
             log(f"plain, one call per slice: {plain_ms:.3f} ms per batch (tracking only)")
             del pbufs, views
             torch.cuda.empty_cache()
+        # plain form per sector: one tpcx_track call per unit
+        rb_h = rb.cpu().numpy()
+        R = G.N_ROWS
+        uviews = []
+        for u in range(U):
+            lo, hi = int(rb_h[u * R]), int(rb_h[(u + 1) * R])
+            uviews.append((torch.as_tensor(rb_h[u * R:(u + 1) * R + 1] - lo, device=dev), y[lo:hi], z[lo:hi]))
+        mxu = max(int(v[1].numel()) for v in uviews)
+        ubufs = tr.allocate(1, mxu, cap_start=mxu, cap_tracks=mxu, cap_hits=8 * mxu)
+
+        def plain_units():
+            for rbt, ys, zs in uviews:
+                tr.track_into(rbt, ys, zs, 1, ubufs)
+
+        plain_units()
+        unit_ms = timed(plain_units, 1)
+        assert int(ubufs["out"]["counts"][3]) == 0, "per-sector capacity overflow"
+        forms["plain_per_sector_ms"] = round(unit_ms, 3)
+        forms["batched_speedup_vs_plain_per_sector"] = round(unit_ms / track_ms, 3)
+        log(f"plain, one call per sector ({U} calls): {unit_ms:.3f} ms per batch (tracking only)")
+        del ubufs, uviews
+        torch.cuda.empty_cache()
         adj = adjoint_form(args.steps)
         forms["adjoint"] = adj
         log(f"adjoint refit: forward {adj['forward_ms']} ms, backward {adj['backward_ms']} ms "
