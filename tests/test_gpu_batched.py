@@ -161,3 +161,37 @@ def test_autotuned_batched_equals_default_tuning():
     got = _run_batched(tr2, rb, y, z, n_units, alpha, theta)[0]
     for k in want:
         np.testing.assert_array_equal(want[k], got[k], err_msg=f"autotuned run differs in {k}")
+
+
+def test_batched_overflow_skips_refit_and_empty_input_runs():
+    import torch
+
+    import paper_2601_20569_amd as px
+    dev = torch.device("cuda")
+    sets = _sets()[:1]
+    rb, y, z, sectors = pack(sets)
+    n_units = len(sectors)
+    alpha = torch.as_tensor(G.sector_alpha(sectors).astype(np.float32), device=dev)
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    print("case: batched with too few hit slots", flush=True)
+    tr = make_tracker()
+    bufs = tr.allocate_batched(n_units, len(y), cap_start=len(y), cap_tracks=len(y), cap_hits=100)
+    bufs["refit_chi2"].fill_(-1.0)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        tr.track_batched_into(T(rb, torch.int64), T(y, torch.float32), T(z, torch.float32), n_units, bufs, s,
+                              unit_alpha=alpha)
+    s.synchronize()
+    counts = bufs["out"]["counts"].cpu().numpy()
+    assert counts[3] & px.ST_HIT_OVERFLOW and counts[2] > 100
+    assert (bufs["refit_chi2"].cpu().numpy() == -1.0).all()  # no tracklet refitted
+    print("case: batched on units without clusters", flush=True)
+    rb0 = torch.zeros(n_units * G.N_ROWS + 1, dtype=torch.int64, device=dev)
+    e = torch.zeros(0, dtype=torch.float32, device=dev)
+    tr2 = make_tracker()
+    b2 = tr2.allocate_batched(n_units, 0, 1, 1, 1)
+    with torch.cuda.stream(s):
+        tr2.track_batched_into(rb0, e, e, n_units, b2, s, unit_alpha=alpha)
+    s.synchronize()
+    assert (b2["out"]["counts"].cpu().numpy() == 0).all()
