@@ -104,7 +104,7 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   L.starts = cv.take<int32_t>(cap_start);
   L.start_pos = cv.take<int32_t>(cap_start);
   L.start_k = cv.take<int32_t>(cap_start);
-  L.queue = cv.take<int32_t>(kXcds);
+  L.queue = cv.take<int32_t>(1);
   L.part = cv.take<int64_t>(2 * kKeepBlocks);
   L.tmp.cap = std::max<int64_t>(cap_start, 1);
   L.tmp.stride = (c->n_rows + 15) / 16 * 16;
@@ -393,7 +393,7 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   };
   mark(0);
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, out->counts, int64_t(4), int64_t(0));
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(kXcds), 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(1), 0);
   const int UR = U * R;
   const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
   hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,

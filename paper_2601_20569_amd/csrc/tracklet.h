@@ -268,31 +268,18 @@ __global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
   int32_t next_c = -1;
   int64_t extra_begin = 0, extra_end = 0;
   // wavefront-private pool [pool, pool_end) of start slots, refilled kWave
-  // slots at a time from one of kXcds device queues: queue j hands out the
-  // j-th eighth of the start list.  A wavefront draws from the queue of its
-  // own XCD first (so each XCD works through its own units and keeps them in
-  // its L2), then from the others in turn.
+  // slots at a time from one device queue that hands out the start list in
+  // order: the whole GPU works on neighbouring units at a time, which then
+  // share the Infinity Cache (faster here than giving each XCD its own part).
   int64_t pool = 0, pool_end = 0;
   bool exhausted = false;
-  const int qhome = int(blockIdx.x % kXcds);
-  int qtried = 0;
   auto grab = [&](int64_t& lo, int64_t& hi) {
-    lo = hi = 0;
-    while (qtried < kXcds) {
-      const int j = (qhome + qtried) % kXcds;
-      const int64_t qb = n_start * j / kXcds, qe = n_start * (j + 1) / kXcds;
-      int32_t base = 0;
-      if (lane == 0) base = atomicAdd(queue + j, kWave);
-      base = __shfl(base, 0, kWave);
-      if (qb + base < qe) {
-        lo = qb + base;
-        hi = min(lo + kWave, qe);
-        if (hi == qe) ++qtried;
-        break;
-      }
-      ++qtried;
-    }
-    exhausted = qtried >= kXcds;
+    int32_t base = 0;
+    if (lane == 0) base = atomicAdd(queue, kWave);
+    base = __shfl(base, 0, kWave);
+    lo = min(int64_t(base), n_start);
+    hi = min(int64_t(base) + kWave, n_start);
+    exhausted = hi >= n_start;
   };
 
   while (true) {
