@@ -103,17 +103,20 @@ __device__ __forceinline__ int upper_row(const int64_t* a, int n, int64_t v) {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 // The dispatcher hands workgroups to the 8 XCDs round-robin (workgroup b runs
-// on XCD b % 8).  xcd_block() renumbers them so that every XCD runs one
-// contiguous range of logical blocks: neighbouring (unit, row) blocks then
-// share one L2.  A bijection of [0, gridDim.x) for any grid size.
+// on XCD b % 8).  xcd_block() renumbers them so that each XCD gets runs of
+// kXcdChunk consecutive logical blocks (neighbouring (unit, row) blocks then
+// share one L2), while the 8 XCDs work on neighbouring runs at the same time
+// (and share the Infinity Cache).  A bijection of [0, gridDim.x): the tail
+// that does not fill 8 runs keeps its order.
 constexpr int kXcds = 8;
+constexpr int64_t kXcdChunk = 16;
 
 __device__ __forceinline__ int64_t xcd_block() {
   const int64_t n = gridDim.x, b = blockIdx.x;
-  const int64_t per = (n + kXcds - 1) / kXcds;
+  const int64_t whole = n / (kXcds * kXcdChunk) * (kXcds * kXcdChunk);
+  if (b >= whole) return b;
   const int64_t x = b % kXcds, i = b / kXcds;
-  const int64_t full = n % kXcds == 0 ? kXcds : n % kXcds;
-  return x < full ? x * per + i : full * per + (x - full) * (per - 1) + i;
+  return (i / kXcdChunk) * (kXcds * kXcdChunk) + x * kXcdChunk + (i % kXcdChunk);
 }
 
 __device__ __forceinline__ uint64_t lanes_below() {
