@@ -136,61 +136,108 @@ __device__ __forceinline__ float kf_update(KState& q, float my, float mz, float 
   return chi2;
 }
 
-// Best cluster of row r (grid row k) by (chi2, caller id) among chi2 <=
-// chi2max, or -1.  The grid box |dy| <= 4 sqrt(Sy), |dz| <= 4 sqrt(Sz) is
-// widened so that it holds every cluster the float chi2 cut can accept.
-__device__ __forceinline__ int32_t kf_search(const Grid& g, const RowView& rv, const KState& q,
-                                             const DevParams& p, float iSy, float iSz,
-                                             float* out_my, float* out_mz) {
-  // the hardware square root (within 1 ulp) is enough: the box only has to
-  // be large enough, and the 1e-3 relative margin covers its error
+// The search box of one lane: z bins zb0..zb1 (taken in pairs), y bins
+// yb0..yb1, in the row whose first bin is `base` (ny y bins per z bin).  The
+// box |dy| <= 4 sqrt(Sy), |dz| <= 4 sqrt(Sz) is widened so that it holds
+// every cluster the float chi2 cut can accept; the hardware square root
+// (within 1 ulp) is enough, the 1e-3 relative margin covers its error.
+struct SearchBox {
+  int64_t base;
+  int ny, zb0, zb1, yb0, yb1;
+};
+
+__device__ __forceinline__ SearchBox kf_box(const RowView& rv, const KState& q, const DevParams& p) {
   const float hy = __builtin_amdgcn_sqrtf(p.chi2max * (q.cyy + p.sy2)) * 1.001f + box_pad(q.y);
   const float hz = __builtin_amdgcn_sqrtf(p.chi2max * (q.czz + p.sz2)) * 1.001f + box_pad(q.z);
-  const int zb0 = rv.zbin(q.z - hz), zb1 = rv.zbin(q.z + hz);
-  const int yb0 = rv.ybin(q.y - hy), yb1 = rv.ybin(q.y + hy);
-  const int64_t base = rv.base;
-  const int ny = rv.ri.ny;
-  int32_t best = -1;
-  float bch = 0.0f, bmy = 0.0f, bmz = 0.0f;
-  auto take = [&](const float4& m) {
-    const float my = m.x, mz = m.y;
-    const float ry = my - q.y;
-    const float rz = mz - q.z;
-    const float ch = (ry * ry) * iSy + (rz * rz) * iSz;
-    if (!(ch <= p.chi2max)) return;
-    const int32_t id = __float_as_int(m.z);
-    if (best < 0 || ch < bch || (ch == bch && id < best)) {
-      best = id;
-      bch = ch;
-      bmy = my;
-      bmz = mz;
+  SearchBox b;
+  b.base = rv.base;
+  b.ny = rv.ri.ny;
+  b.zb0 = rv.zbin(q.z - hz);
+  b.zb1 = rv.zbin(q.z + hz);
+  b.yb0 = rv.ybin(q.y - hy);
+  b.yb1 = rv.ybin(q.y + hy);
+  return b;
+}
+
+// Order-preserving map of a float chi2 to an unsigned key (-0 counts as +0).
+__device__ __forceinline__ uint32_t chi2_key(float ch) {
+  const uint32_t u = __float_as_uint(ch == 0.0f ? 0.0f : ch);
+  return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+
+// Best cluster of the search box by (chi2, caller id) among chi2 <= chi2max,
+// or -1, for every lane of the wavefront with `searching` set.  The
+// candidates of all lanes are spread over all 64 lanes (a lane's own box
+// holds 5 candidates on average but the largest box of a wavefront ~17): the candidate ranges of
+// one z-bin pair are numbered by a prefix sum over the lanes, and lane l
+// evaluates candidates l, l + 64, ... of that numbering, for their owner
+// lane's state.  The minimum per owner is an LDS atomic on the 64-bit key
+// (chi2, caller id); after each round the lane holding an owner's current
+// minimum stores its coordinates.  The result does not depend on which lane
+// evaluates which candidate.  Must be called with all 64 lanes active; `sbest` and `scoord` are the
+// wavefront's 64 LDS slots.
+__device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox& b, bool searching,
+                                                  float qy, float qz, float iSy, float iSz,
+                                                  float chi2max, uint64_t* sbest, float2* scoord,
+                                                  float* out_my, float* out_mz) {
+  const int lane = lane_id();
+  sbest[lane] = ~0ull;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  for (int zb = b.zb0;; zb += 2) {
+    const bool act = searching && zb <= b.zb1;
+    if (__ballot(act) == 0ull) break;
+    int32_t a0 = 0, alen = 0, b0 = 0, n = 0;
+    if (act) {
+      const bool z2 = zb + 1 <= b.zb1;
+      const int64_t ra = b.base + int64_t(zb) * b.ny;
+      const int64_t rb = z2 ? ra + b.ny : ra;
+      const int32_t j0 = g.bin_start[ra + b.yb0], j1 = g.bin_start[ra + b.yb1 + 1];
+      const int32_t k0 = g.bin_start[rb + b.yb0], k1 = g.bin_start[rb + b.yb1 + 1];
+      a0 = j0;
+      alen = j1 - j0;
+      b0 = k0;
+      n = alen + (z2 ? k1 - k0 : 0);
     }
-  };
-  for (int zb = zb0; zb <= zb1; zb += 2) {
-    // two z bins' ranges at once, then their candidates two at a time
-    const bool z2 = zb + 1 <= zb1;
-    const int32_t j0 = g.bin_start[base + zb * ny + yb0], j1 = g.bin_start[base + zb * ny + yb1 + 1];
-    const int zc = z2 ? zb + 1 : zb;
-    int32_t k0 = g.bin_start[base + zc * ny + yb0], k1 = g.bin_start[base + zc * ny + yb1 + 1];
-    if (!z2) k1 = k0;
-    for (int32_t j = j0; j < j1; j += 2) {
-      const bool two = j + 1 < j1;
-      const float4 ma = g.pts[j];
-      const float4 mb = g.pts[two ? j + 1 : j];
-      take(ma);
-      if (two) take(mb);
+    int incl = n;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int v = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += v;
     }
-    for (int32_t j = k0; j < k1; j += 2) {
-      const bool two = j + 1 < k1;
-      const float4 ma = g.pts[j];
-      const float4 mb = g.pts[two ? j + 1 : j];
-      take(ma);
-      if (two) take(mb);
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+    const int excl = incl - n;
+    for (int t0 = 0; t0 < total; t0 += kWave) {
+      const int ta = t0 + lane;
+      int oa = 0;
+#pragma unroll
+      for (int st = kWave / 2; st > 0; st >>= 1)
+        if (__shfl(incl, oa + st - 1, kWave) <= ta) oa += st;
+      const int ua = ta - __shfl(excl, oa, kWave);
+      const int la = __shfl(alen, oa, kWave);
+      const int aa = __shfl(a0, oa, kWave), ba = __shfl(b0, oa, kWave);
+      const float ya = __shfl(qy, oa, kWave), za = __shfl(qz, oa, kWave);
+      const float sya = __shfl(iSy, oa, kWave), sza = __shfl(iSz, oa, kWave);
+      const bool va = ta < total;
+      const int pa = ua < la ? aa + ua : ba + (ua - la);
+      float4 ma = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (va) ma = g.pts[pa];
+      const float rya = ma.x - ya, rza = ma.y - za;
+      const float cha = (rya * rya) * sya + (rza * rza) * sza;
+      const bool pa_ok = va && cha <= chi2max;
+      const uint64_t ka = (uint64_t(chi2_key(cha)) << 32) | uint32_t(__float_as_int(ma.z));
+      if (pa_ok) atomicMin(&sbest[oa], (unsigned long long)ka);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (pa_ok && __hip_atomic_load(&sbest[oa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == ka)
+        scoord[oa] = make_float2(ma.x, ma.y);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
   }
-  *out_my = bmy;
-  *out_mz = bmz;
-  return best;
+  const uint64_t key = __hip_atomic_load(&sbest[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  if (!searching || key == ~0ull) return -1;
+  const float2 cc = scoord[lane];
+  *out_my = cc.x;
+  *out_mz = cc.y;
+  return int32_t(uint32_t(key));
 }
 
 // Per-start-hit results before compaction.  One 128-byte record per slot:
@@ -228,8 +275,10 @@ constexpr int kConstructBlock = 256;
 // Every lane runs one tracklet at a time as a sequence of row steps (one
 // propagation each); the four phases share the step so that lanes of a
 // wavefront in different phases still execute together.  Idle lanes take new
-// start hits from the device queue in batches.  Results depend only on the
-// start hit: the order in which lanes pick them up is irrelevant.
+// start hits from the device queue in batches; they take part in the
+// wavefront's cluster search, which spreads the candidates of all searching
+// lanes over all 64 lanes.  Results depend only on the start hit: the order
+// in which lanes pick them up is irrelevant.
 // Attached cluster ids are staged per lane in LDS and written 16 at a time
 // (one full 64-byte line), the row mask is kept in LDS too; the record is
 // written once, as whole lines, when the tracklet ends.
@@ -241,6 +290,8 @@ __global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
     TrackInputs in, Grid g, DevParams p, TrackletTmp out) {
   __shared__ int32_t hbuf[kConstructWaves][kHitBuf][kWave];
   __shared__ uint32_t rmask[kConstructWaves][kMaskWords][kWave];
+  __shared__ uint64_t sbest[kConstructWaves][kWave];
+  __shared__ float2 scoord[kConstructWaves][kWave];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
   const int R = g.n_rows;
   const int lane = lane_id();
@@ -276,7 +327,7 @@ __global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
   auto grab = [&](int64_t& lo, int64_t& hi) {
     int32_t base = 0;
     if (lane == 0) base = atomicAdd(queue, kWave);
-    base = __shfl(base, 0, kWave);
+    base = __builtin_amdgcn_readfirstlane(base);
     lo = min(int64_t(base), n_start);
     hi = min(int64_t(base) + kWave, n_start);
     exhausted = hi >= n_start;
@@ -368,50 +419,66 @@ __global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
         }
       }
     }
-    if (phase == kIdle) continue;
-
-    // ---- one row step
-    const bool outward = phase <= kUp;
-    const int target = outward ? row + 1
-                               : (phase == kDescend ? max(r0, row - p.descent_rows) : row - 1);
-    bool ok = target >= 0 && target < R;
-    // the target row's binning does not depend on the propagation: load it first
-    const int trow = min(max(target, 0), R - 1);
-    const RowView rv(g, kbase + trow, trow);
-    if (ok) ok = kf_propagate(q, in.row_x[target], p, c_prev, r_prev, cached);
-    bool finish = false, to_descend = false;
-    if (phase == kDescend) {
-      if (!ok) {
-        flags |= kFlagDescentFailed;
-        finish = true;
+    // ---- one row step (idle lanes take part in the search only)
+    const bool live = phase != kIdle;
+    bool finish = false, to_descend = false, attach = false, searching = false;
+    int target = 0;
+    float iSy = 0.0f, iSz = 0.0f, my = 0.0f, mz = 0.0f;
+    int32_t c = -1, chain_next = -1;
+    SearchBox box{0, 1, 0, -1, 0, -1};
+    if (live) {
+      const bool outward = phase <= kUp;
+      target = outward ? row + 1 : (phase == kDescend ? max(r0, row - p.descent_rows) : row - 1);
+      bool ok = target >= 0 && target < R;
+      // the target row's binning does not depend on the propagation: load it first
+      const int trow = min(max(target, 0), R - 1);
+      const RowView rv(g, kbase + trow, trow);
+      if (ok) ok = kf_propagate(q, in.row_x[target], p, c_prev, r_prev, cached);
+      if (phase == kDescend) {
+        if (!ok) {
+          flags |= kFlagDescentFailed;
+          finish = true;
+        } else {
+          row = target;
+          if (row == r0) {
+            best = q;
+            best_row = row;
+            misses = 0;
+            phase = kDown;
+          }
+        }
+      } else if (!ok) {
+        if (phase == kDown)
+          finish = true;
+        else
+          to_descend = true;
       } else {
-        row = target;
-        if (row == r0) {
-          best = q;
-          best_row = row;
-          misses = 0;
-          phase = kDown;
+        iSy = 1.0f / (q.cyy + p.sy2);
+        iSz = 1.0f / (q.czz + p.sz2);
+        attach = true;
+        if (phase == kChain) {
+          const float4 P = in.pts[next_c];
+          my = P.x;
+          mz = P.y;
+          c = __float_as_int(P.z);
+          chain_next = __float_as_int(P.w);
+        } else {
+          searching = true;
+          box = kf_box(rv, q, p);
         }
       }
-    } else if (!ok) {
-      if (phase == kDown)
-        finish = true;
-      else
-        to_descend = true;
-    } else {
-      const float iSy = 1.0f / (q.cyy + p.sy2);
-      const float iSz = 1.0f / (q.czz + p.sz2);
-      float my, mz;
-      int32_t c, chain_next = -1;
-      if (phase == kChain) {
-        const float4 P = in.pts[next_c];
-        my = P.x;
-        mz = P.y;
-        c = __float_as_int(P.z);
-        chain_next = __float_as_int(P.w);
-      } else {
-        c = kf_search(g, rv, q, p, iSy, iSz, &my, &mz);
+    }
+    if (__ballot(searching) != 0ull) {
+      float sy = 0.0f, sz = 0.0f;
+      const int32_t sc = kf_search_wave(g, box, searching, q.y, q.z, iSy, iSz, p.chi2max, sbest[wv],
+                                        scoord[wv], &sy, &sz);
+      if (searching) {
+        c = sc;
+        my = sy;
+        mz = sz;
       }
+    }
+    if (attach) {
       row = target;
       if (c >= 0) {
         chi2 = chi2 + kf_update(q, my, mz, iSy, iSz);
