@@ -77,6 +77,33 @@ def _subset(cs, keep):
                             cs.truth_psi[keep], cs.tracks, cs.meta)
 
 
+def _doubled(cs):
+    """Every cluster twice, at the same coordinates, in its own row."""
+    key = cs.unit_of().astype(np.int64) * G.N_ROWS + cs.row_of()
+    idx = np.concatenate([np.arange(cs.n_clusters), np.arange(cs.n_clusters)])
+    idx = idx[np.argsort(np.concatenate([key, key]), kind="stable")]
+    rb = cs.row_begin * 2
+    return synth.ClusterSet(cs.n_units, cs.unit_sector, rb, cs.y[idx], cs.z[idx],
+                            cs.truth_track[idx], cs.truth_y[idx], cs.truth_z[idx],
+                            cs.truth_psi[idx], cs.tracks, cs.meta)
+
+
+def test_exact_ties_between_duplicated_clusters():
+    """Each cluster has a twin with the same coordinates, so every search of
+    the constructor (and every neighbour choice) meets an exact tie, decided
+    by the smaller caller id (Section 2.2 selection rule, ties by index)."""
+    print("case: single sector seed 1, every cluster duplicated", flush=True)
+    cs = _doubled(synth.single_sector(seed=1))
+    gpu, ref = _full_parity(cs)
+    assert len(gpu["n_hits"]) > 100
+    # a row holds its clusters, then their twins: every attached cluster must
+    # be from the first half of its row (the smaller id of each pair)
+    k = oracle.kept_tracklets(ref)
+    counts = np.diff(cs.row_begin)
+    key = np.repeat(np.arange(len(counts)), counts)[k["hits"]]
+    assert np.all(k["hits"] - cs.row_begin[key] < counts[key] // 2)
+
+
 def test_empty_and_tiny_inputs():
     print("case: empty input", flush=True)
     cs = synth.single_sector(seed=3, n_tracks=0, noise_frac=0.0)
