@@ -309,19 +309,17 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_hits(RefitIn in, const 
   }
 }
 
-// Corrected clusters, one per input cluster (caller order), for the batched
-// refit: one block per (unit, row), walking the row in sorted (bin) order, so
-// neighbouring lanes read mostly the same map nodes from LDS; results go to
-// the cluster's caller index.  The block first copies into LDS the map
-// nodes around its sector (phi within +-20 degrees of the centre line,
-// the r nodes of the row's radius range); a cluster whose nodes lie outside
-// that copy reads the coefficient array.  Both give the same arithmetic as
-// correct_cluster.
+// Corrected clusters, one per input cluster, for the batched refit: one block
+// per (unit, row), walking the row in caller order, so the reads of the input
+// and the writes of the results are coalesced (the filter gathers them by
+// caller index).  The block first copies into LDS the map nodes around its
+// sector (phi within +-20 degrees of the centre line, the r nodes of the
+// row's radius range); a cluster whose nodes lie outside that copy reads the
+// coefficient array.  Both give the same arithmetic as correct_cluster.
 __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     int n_rows, const int64_t* __restrict__ row_begin, const float* __restrict__ y,
     const float* __restrict__ z, const float* __restrict__ unit_alpha,
-    const float* __restrict__ row_x, const float* __restrict__ theta, const float4* __restrict__ pts,
-    float4* __restrict__ corr) {
+    const float* __restrict__ row_x, const float* __restrict__ theta, float4* __restrict__ corr) {
   __shared__ float4 stage[kStageNodes];
   const int64_t ur = xcd_block();
   const float alpha = unit_alpha[ur / n_rows];
@@ -352,10 +350,8 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
   }
   __syncthreads();
   for (int64_t c = row_begin[ur] + threadIdx.x; c < e; c += kRefitBlock) {
-    // sorted order: neighbouring lanes read the same map nodes
-    const float4 P = pts[c];
     float r;
-    const HitGeom h = hit_geom(x, P.x, P.y, alpha, &r);
+    const HitGeom h = hit_geom(x, y[c], z[c], alpha, &r);
     const Weights4 wp = weights_phi(h.phi);
     const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
     const Weights4 wz = weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
@@ -364,7 +360,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
       map_displacement(ts, wp, wr, wz, d);
     else
       map_displacement(ThetaGlobal{theta}, wp, wr, wz, d);
-    corr[__float_as_int(P.z)] = apply_displacement(h, d);
+    corr[c] = apply_displacement(h, d);
   }
 }
 

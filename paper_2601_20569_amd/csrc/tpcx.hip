@@ -444,19 +444,20 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   mark(5);
 }
 
-// The batched refit: the cluster correction on c->aux (it needs only the search
-// grid, so it overlaps the tracking stages), the filter on `stream` once both
-// the tracking and the correction are done.  enqueue_track must have recorded
+// The batched refit: the cluster correction on c->aux (it needs only the input
+// clusters, so it overlaps the tracking stages; it starts after the grid build,
+// which is bound by HBM bandwidth), the filter on `stream` once both the
+// tracking and the correction are done.  enqueue_track must have recorded
 // c->ev_fork after the grid build.
 void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_tracks* out,
                          const tpcx_batch_refit* refit, const BatchRefitLayout& RL,
-                         const tpcx_tuning& t, const float4* pts, hipStream_t stream) {
+                         const tpcx_tuning& t, hipStream_t stream) {
   (void)hipStreamWaitEvent(c->aux, c->ev_fork, 0);
   const int64_t n_ur = int64_t(in->n_units) * c->n_rows;
   if (in->n_clusters > 0)
     hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, c->aux,
                        c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
-                       refit->theta, pts, RL.corr);
+                       refit->theta, RL.corr);
   (void)hipEventRecord(c->ev_join, c->aux);
 
   RefitIn r;
@@ -555,7 +556,7 @@ tpcx_status autotune_run(const tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   const BatchRefitLayout RL = carve_batch_refit(static_cast<char*>(ws) + L.bytes, in->n_clusters);
   if (L.bytes + RL.bytes > ws_bytes) return TPCX_E_ARG;
   enqueue_track(c, in, L, t, cap_start, out, stream, nullptr, refit ? c->ev_fork : nullptr);
-  if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
+  if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
@@ -705,7 +706,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
   if (hipEvent_t* ev = next_timing_slot(c)) {
     // timed run: the same sequence launched directly, with stage events
     enqueue_track(c, in, L, t, cap_start, out, stream, ev, refit ? c->ev_fork : nullptr);
-    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
     (void)hipEventRecord(ev[TPCX_N_STAGES], stream);
     return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
   }
@@ -716,7 +717,7 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
     enqueue_track(c, in, L, t, cap_start, out, stream, nullptr, refit ? c->ev_fork : nullptr);
-    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, L.pts, stream);
+    if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
     hipGraph_t g = nullptr;
     const hipError_t e1 = hipStreamEndCapture(stream, &g);
     if (e1 != hipSuccess || !g) return TPCX_E_HIP;
