@@ -227,20 +227,25 @@ __global__ void k_scan_counts(const int32_t* __restrict__ cnt, int64_t nb, int32
 // Start hits of one row in ascending caller id: the row's flagged clusters
 // mark their caller id in an LDS bitmap over the row's id range, and each one's
 // rank is the number of marked ids below it.  Ranges longer than the bitmap
-// are done in segments.
+// are done in segments.  order[] lists the same slots in sorted-position
+// (bin) order, the order in which the constructor takes them so that
+// neighbouring lanes follow neighbouring tracks (written when all start hits
+// fit the capacity).
 constexpr int kSegBits = 65536;
 constexpr int kSegWords = kSegBits / 32;
 
 __global__ void k_write_starts(const int64_t* __restrict__ row_begin, const float4* __restrict__ pts,
                                const uint8_t* __restrict__ flag, const int32_t* __restrict__ row_off,
-                               int64_t cap, int32_t* __restrict__ starts,
-                               int32_t* __restrict__ start_pos, int32_t* __restrict__ start_k) {
+                               const int64_t* __restrict__ n_total, int64_t cap,
+                               int32_t* __restrict__ starts, int32_t* __restrict__ start_pos,
+                               int32_t* __restrict__ start_k, int32_t* __restrict__ order) {
   __shared__ uint32_t bits[kSegWords];
   __shared__ int32_t wpre[kSegWords];
   __shared__ int64_t scan_lds[1024 / kWave];
   const int k = int(xcd_block());
   const int64_t b = row_begin[k], e = row_begin[k + 1];
   int64_t seg_base = row_off[k];
+  const bool all_fit = *n_total <= cap;
   for (int64_t lo = b; lo < e; lo += kSegBits) {
     const int64_t hi = min(e, lo + kSegBits);
     const int nw = int((hi - lo + 31) / 32);
@@ -264,8 +269,15 @@ __global__ void k_write_starts(const int64_t* __restrict__ row_begin, const floa
       run += __popc(bits[w]);
     }
     __syncthreads();
-    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-      if (!flag[i]) continue;
+    // srank: the start hit's rank in sorted-position order within the row
+    int64_t srun = row_off[k];
+    for (int64_t i0 = b; i0 < e; i0 += blockDim.x) {
+      const int64_t i = i0 + threadIdx.x;
+      const bool fl = i < e && flag[i];
+      int64_t ftot;
+      const int64_t srank = srun + block_exclusive_scan(fl ? 1 : 0, scan_lds, &ftot);
+      srun += ftot;
+      if (!fl) continue;
       const int64_t h = id_of(pts[i]);
       if (h < lo || h >= hi) continue;
       const int64_t o = h - lo;
@@ -275,6 +287,7 @@ __global__ void k_write_starts(const int64_t* __restrict__ row_begin, const floa
         start_pos[pos] = int32_t(i);
         start_k[pos] = k;
       }
+      if (all_fit) order[srank] = int32_t(pos);
     }
     seg_base += tot;
     __syncthreads();

@@ -77,6 +77,7 @@ struct Layout {
   int32_t* starts;
   int32_t* start_pos;
   int32_t* start_k;
+  int32_t* order;
   int32_t* queue;
   int64_t* part;
   TrackletTmp tmp;
@@ -104,6 +105,7 @@ Layout carve(const tpcx_ctx* c, void* ws, int32_t n_units, int64_t n, int64_t ca
   L.starts = cv.take<int32_t>(cap_start);
   L.start_pos = cv.take<int32_t>(cap_start);
   L.start_k = cv.take<int32_t>(cap_start);
+  L.order = cv.take<int32_t>(cap_start);
   L.queue = cv.take<int32_t>(1);
   L.part = cv.take<int64_t>(2 * kKeepBlocks);
   L.tmp.cap = std::max<int64_t>(cap_start, 1);
@@ -409,12 +411,13 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
                      L.row_off, out->counts, cap_start, out->counts + 3,
                      int64_t(TPCX_ST_START_OVERFLOW));
   hipLaunchKernelGGL(k_write_starts, dim3(UR), dim3(B), 0, stream, in->row_begin, L.pts, L.flag,
-                     L.row_off, cap_start, L.starts, L.start_pos, L.start_k);
+                     L.row_off, out->counts, cap_start, L.starts, L.start_pos, L.start_k, L.order);
 
   TrackInputs ti;
   ti.pts = L.pts;
   ti.start_pos = L.start_pos;
   ti.start_k = L.start_k;
+  ti.order = L.order;
   ti.row_x = c->d_row_x;
   mark(3);
   hipLaunchKernelGGL(k_construct, dim3(t.construct_grid), dim3(kConstructBlock), 0, stream,

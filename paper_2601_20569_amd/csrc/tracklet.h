@@ -263,6 +263,7 @@ struct TrackInputs {
   const float4* pts;         // sorted clusters (y, z, caller id, cleaned up-link)
   const int32_t* start_pos;  // sorted position of every start hit
   const int32_t* start_k;    // its unit * n_rows + row
+  const int32_t* order;      // slots in sorted-position order (used when all start hits fit)
   const float* row_x;        // [n_rows]
 };
 
@@ -293,6 +294,7 @@ __global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
   __shared__ uint64_t sbest[kConstructWaves][kWave];
   __shared__ float2 scoord[kConstructWaves][kWave];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
+  const bool ordered = counts[0] <= cap_start;
   const int R = g.n_rows;
   const int lane = lane_id();
   const int wv = threadIdx.x / kWave;
@@ -370,9 +372,9 @@ __global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
       if (phase == kIdle) {
         if (sidx >= 0) {
           // 2-point seed at the second cluster of the chain
-          slot = sidx;
-          const float4 P0 = in.pts[in.start_pos[sidx]];
-          const int kk = in.start_k[sidx];
+          slot = ordered ? in.order[sidx] : sidx;
+          const float4 P0 = in.pts[in.start_pos[slot]];
+          const int kk = in.start_k[slot];
           r0 = kk % R;
           kbase = kk - r0;
           const float4 P1 = in.pts[__float_as_int(P0.w)];
@@ -544,6 +546,7 @@ __global__ void k_keep_count(const int64_t* __restrict__ counts, int64_t cap_sta
                              int64_t* __restrict__ part) {
   __shared__ int64_t lds[1024 / kWave];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
+  const bool ordered = counts[0] <= cap_start;
   int64_t b, e;
   chunk_of(n_start, &b, &e);
   int64_t ct = 0, ch = 0;
@@ -629,6 +632,7 @@ __global__ void __launch_bounds__(kKeepBlock) k_keep_write(
   __shared__ int32_t s_nu[kKeepBlock];
   __shared__ uint32_t s_mask[kMaskWords][kKeepBlock];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
+  const bool ordered = counts[0] <= cap_start;
   int64_t b, e;
   chunk_of(n_start, &b, &e);
   int64_t t_run = part[2 * blockIdx.x], h_run = part[2 * blockIdx.x + 1];
