@@ -251,7 +251,7 @@ void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t) {
   int nz = int(per_row / 30.0);
   t->n_zbins = std::max(4, std::min(nz, 4096));
   t->block = 256;
-  t->construct_grid = 1280;  // 5 blocks of 4 wavefronts per CU, persistent
+  t->construct_grid = 1024;  // 4 blocks of 4 wavefronts per CU, persistent
   t->construct_refill = 16;
   t->refit_grid = 0;
   t->refit_refill = 16;
@@ -518,7 +518,8 @@ std::vector<tpcx_tuning> autotune_candidates(const tpcx_ctx* c, const tpcx_tunin
       }
       break;
     case 2:
-      for (int per_cu : {3, 4, 5, 6}) {
+      // at most 4 constructor blocks are resident per CU (its register use)
+      for (int per_cu : {2, 3, 4}) {
         t = b;
         t.construct_grid = per_cu * c->n_cu;
         add(t);

@@ -286,7 +286,7 @@ constexpr int kConstructBlock = 256;
 constexpr int kHitBuf = 16;
 constexpr int kConstructWaves = kConstructBlock / kWave;
 
-__global__ void __launch_bounds__(kConstructBlock, 5) k_construct(
+__global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     const int64_t* __restrict__ counts, int64_t cap_start, int32_t* __restrict__ queue, int refill,
     TrackInputs in, Grid g, DevParams p, TrackletTmp out) {
   __shared__ int32_t hbuf[kConstructWaves][kHitBuf][kWave];
