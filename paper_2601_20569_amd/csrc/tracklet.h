@@ -206,29 +206,41 @@ __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox
     }
     const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
     const int excl = incl - n;
-    for (int t0 = 0; t0 < total; t0 += kWave) {
-      const int ta = t0 + lane;
-      int oa = 0;
+    for (int t0 = 0; t0 < total; t0 += 2 * kWave) {
+      // two candidates per lane: t0 + lane and t0 + 64 + lane
+      const int ta = t0 + lane, tb = ta + kWave;
+      int oa = 0, ob = 0;
 #pragma unroll
-      for (int st = kWave / 2; st > 0; st >>= 1)
-        if (__shfl(incl, oa + st - 1, kWave) <= ta) oa += st;
-      const int ua = ta - __shfl(excl, oa, kWave);
-      const int la = __shfl(alen, oa, kWave);
-      const int aa = __shfl(a0, oa, kWave), ba = __shfl(b0, oa, kWave);
-      const float ya = __shfl(qy, oa, kWave), za = __shfl(qz, oa, kWave);
-      const float sya = __shfl(iSy, oa, kWave), sza = __shfl(iSz, oa, kWave);
-      const bool va = ta < total;
+      for (int st = kWave / 2; st > 0; st >>= 1) {
+        const int va = __shfl(incl, oa + st - 1, kWave);
+        const int vb = __shfl(incl, ob + st - 1, kWave);
+        if (va <= ta) oa += st;
+        if (vb <= tb) ob += st;
+      }
+      const int ua = ta - __shfl(excl, oa, kWave), ub = tb - __shfl(excl, ob, kWave);
+      const int la = __shfl(alen, oa, kWave), lb = __shfl(alen, ob, kWave);
+      const int aa = __shfl(a0, oa, kWave), ab = __shfl(a0, ob, kWave);
+      const int ba = __shfl(b0, oa, kWave), bb = __shfl(b0, ob, kWave);
       const int pa = ua < la ? aa + ua : ba + (ua - la);
-      float4 ma = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      const int pb = ub < lb ? ab + ub : bb + (ub - lb);
+      const bool va = ta < total, vb = tb < total;
+      float4 ma = make_float4(0.0f, 0.0f, 0.0f, 0.0f), mb = ma;
       if (va) ma = g.pts[pa];
-      const float rya = ma.x - ya, rza = ma.y - za;
-      const float cha = (rya * rya) * sya + (rza * rza) * sza;
-      const bool pa_ok = va && cha <= chi2max;
+      if (vb) mb = g.pts[pb];
+      const float rya = ma.x - __shfl(qy, oa, kWave), rza = ma.y - __shfl(qz, oa, kWave);
+      const float cha = (rya * rya) * __shfl(iSy, oa, kWave) + (rza * rza) * __shfl(iSz, oa, kWave);
+      const float ryb = mb.x - __shfl(qy, ob, kWave), rzb = mb.y - __shfl(qz, ob, kWave);
+      const float chb = (ryb * ryb) * __shfl(iSy, ob, kWave) + (rzb * rzb) * __shfl(iSz, ob, kWave);
+      const bool oka = va && cha <= chi2max, okb = vb && chb <= chi2max;
       const uint64_t ka = (uint64_t(chi2_key(cha)) << 32) | uint32_t(__float_as_int(ma.z));
-      if (pa_ok) atomicMin(&sbest[oa], (unsigned long long)ka);
+      const uint64_t kb = (uint64_t(chi2_key(chb)) << 32) | uint32_t(__float_as_int(mb.z));
+      if (oka) atomicMin(&sbest[oa], (unsigned long long)ka);
+      if (okb) atomicMin(&sbest[ob], (unsigned long long)kb);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (pa_ok && __hip_atomic_load(&sbest[oa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == ka)
+      if (oka && __hip_atomic_load(&sbest[oa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == ka)
         scoord[oa] = make_float2(ma.x, ma.y);
+      if (okb && __hip_atomic_load(&sbest[ob], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == kb)
+        scoord[ob] = make_float2(mb.x, mb.y);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
   }
