@@ -168,13 +168,14 @@ __device__ __forceinline__ uint32_t chi2_key(float ch) {
 // Best cluster of the search box by (chi2, caller id) among chi2 <= chi2max,
 // or -1, for every lane of the wavefront with `searching` set.  The
 // candidates of all lanes are spread over all 64 lanes (a lane's own box
-// holds 5 candidates on average but the largest box of a wavefront ~17): the candidate ranges of
-// one z-bin pair are numbered by a prefix sum over the lanes, and lane l
-// evaluates candidates l, l + 64, ... of that numbering, for their owner
-// lane's state.  The minimum per owner is an LDS atomic on the 64-bit key
-// (chi2, caller id); after each round the lane holding an owner's current
-// minimum stores its coordinates.  The result does not depend on which lane
-// evaluates which candidate.  Must be called with all 64 lanes active; `sbest` and `scoord` are the
+// holds 5 candidates on average, the largest box of a wavefront ~17): the
+// candidate ranges of one z-bin pair are numbered by a prefix sum over the
+// lanes, and lane l evaluates candidates l, l + 64, l + 128, ... of that
+// numbering (two per round), for their owner lane's state.  The minimum per
+// owner is an LDS atomic on the 64-bit key (chi2, caller id); after each
+// round the lane holding an owner's current minimum stores its coordinates.
+// The result does not depend on which lane evaluates which candidate.  Must
+// be called with all 64 lanes active; `sbest` and `scoord` are the
 // wavefront's 64 LDS slots.
 __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox& b, bool searching,
                                                   float qy, float qz, float iSy, float iSz,
@@ -558,7 +559,6 @@ __global__ void k_keep_count(const int64_t* __restrict__ counts, int64_t cap_sta
                              int64_t* __restrict__ part) {
   __shared__ int64_t lds[1024 / kWave];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
-  const bool ordered = counts[0] <= cap_start;
   int64_t b, e;
   chunk_of(n_start, &b, &e);
   int64_t ct = 0, ch = 0;
@@ -644,7 +644,6 @@ __global__ void __launch_bounds__(kKeepBlock) k_keep_write(
   __shared__ int32_t s_nu[kKeepBlock];
   __shared__ uint32_t s_mask[kMaskWords][kKeepBlock];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
-  const bool ordered = counts[0] <= cap_start;
   int64_t b, e;
   chunk_of(n_start, &b, &e);
   int64_t t_run = part[2 * blockIdx.x], h_run = part[2 * blockIdx.x + 1];
