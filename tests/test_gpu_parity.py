@@ -141,6 +141,20 @@ def test_capacity_overflow_reports_required_sizes():
     assert res["status"] == 0 and len(res["n_hits"]) == len(k["n"])
 
 
+def test_start_capacity_exactly_full():
+    """With exactly as many start slots as start hits the constructor still
+    takes its work in sorted-position order (the order list is written when
+    all start hits fit); results equal the oracle's."""
+    print("case: central event seed 7, start capacity = number of start hits", flush=True)
+    cs = synth.central_event(seed=7, n_primaries=2000)
+    ref = oracle.track(cs)
+    n_start = len(ref["starts"])
+    gpu = run_gpu(cs, make_tracker(), cap_start=n_start)
+    assert gpu["status"] == 0 and gpu["n_start"] == n_start
+    k, gi = compare_decisions(gpu, ref)
+    compare_numbers(gpu, gi, k, oracle.replay(cs, k))
+
+
 def test_run_twice_bitwise_identical():
     print("case: determinism", flush=True)
     cs = synth.central_event(seed=11, n_primaries=3000)
