@@ -398,6 +398,13 @@ def main():
                     kernels=STAGE_KERNELS.get(dom), kernel_ms=round(stage_ms[dom], 4), alg_bytes=int(b))
 
     known = [k for k in stage_ms if stage_bytes.get(k) is not None]
+    # every stage against HBM: algorithmic bytes over its measured time, and
+    # the counted traffic of its kernels where a current summary holds it
+    stages_roof = {k: dict(alg_bytes=int(stage_bytes[k]),
+                           GBs=round(stage_bytes[k] / (stage_ms[k] * 1e-3) / 1e9, 2),
+                           frac=round(stage_bytes[k] / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                           traffic=recorded_traffic(k, cfg["workload"]))
+                   for k in known if stage_ms[k] > 0}
     path = None
     if len(known) == len(stage_ms):
         tot_b = sum(stage_bytes[k] for k in known)
@@ -412,7 +419,8 @@ def main():
                             attached=n_hits, refitted=n_refit, refitted_clusters=n_refit_hits,
                             tuning=tuning or "default"),
                 roofline=roof, cpu_baseline=cpu,
-                stages_ms={k: round(v, 4) for k, v in stage_ms.items()}, path_roofline=path,
+                stages_ms={k: round(v, 4) for k, v in stage_ms.items()}, stages_roofline=stages_roof,
+                path_roofline=path,
                 forms=forms)
     print(json.dumps(line), flush=True)
     if args.copy_calibration:
