@@ -1,8 +1,9 @@
 """Pins of the refit oracle: the B-spline distortion map, the refit chi2, and
 its FP64 gradient with respect to the map coefficients.
 
-* basis: partition of unity (periodic phi; interior r and z), exact
-  reproduction of linear functions, linearity of the map in theta;
+* basis: weights equal to products of scipy's cubic B-spline basis elements,
+  partition of unity (periodic phi; interior r and z), exact reproduction of
+  linear functions, linearity of the map in theta;
 * refit: zero chi2 for exact helices seeded with the truth, chi2/ndf = 1 on
   smeared tracks, and a least-squares map fitted to the exact inverse of the
   generator's radial distortion removes the distortion's chi2;
@@ -46,6 +47,47 @@ def test_basis_partition_of_unity_and_linear_reproduction():
     # outside the node ranges the basis is cut, not renormalised
     idx, w = oracle.map_basis(80.0, 0.3, 0.0)
     assert w.sum() < 1.0
+
+
+def test_basis_weights_are_scipy_cubic_bspline_products():
+    """Each weight is the product of three uniform cubic B-spline basis
+    elements (scipy's definition from the knots), one per coordinate, centred
+    on the node, with phi periodic; and every node whose product is non-zero
+    is listed.  Partition of unity and linear reproduction alone would also
+    admit linear (hat) B-splines: this pins the order."""
+    from scipy.interpolate import BSpline
+    cubic = BSpline.basis_element(np.arange(-2.0, 3.0), extrapolate=False)
+
+    def b(t):
+        v = cubic(t)
+        return 0.0 if np.isnan(v) else float(v)
+
+    dphi = 2.0 * math.pi / NPHI
+    dz = 500.0 / 19.0
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        phi = rng.uniform(-10, 10)
+        r = rng.uniform(70.0, 260.0)
+        z = rng.uniform(-280.0, 280.0)
+        idx, w = oracle.map_basis(r, phi, z)
+        got = {tuple(int(v) for v in row): wt for row, wt in zip(idx, w)}
+        want = {}
+        for i in range(NPHI):
+            tp = math.remainder(phi - i * dphi, 2.0 * math.pi) / dphi
+            bi = b(tp)
+            if bi == 0.0:
+                continue
+            for j in range(NR):
+                bj = b((r - R_NODES[j]) / 10.0)
+                if bj == 0.0:
+                    continue
+                for k in range(NZ):
+                    bk = b((z - Z_NODES[k]) / dz)
+                    if bk != 0.0:
+                        want[(i, j, k)] = bi * bj * bk
+        assert set(got) == set(want)
+        for key, wt in want.items():
+            assert abs(got[key] - wt) < 1e-12
 
 
 def test_map_is_linear_in_theta_and_matches_basis():
