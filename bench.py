@@ -119,6 +119,17 @@ def gen_batch(device):
                 first=first, ncoll=ncoll)
 
 
+def order_rows_by_z(rb, y, z):
+    """The same clusters with each (unit, row) range sorted by z (stable)."""
+    import torch
+    counts = rb[1:] - rb[:-1]
+    key = torch.repeat_interleave(torch.arange(len(counts), device=y.device), counts)
+    o1 = torch.sort(z, stable=True).indices
+    order = o1[torch.sort(key[o1], stable=True).indices]
+    del o1, key
+    return y[order].contiguous(), z[order].contiguous()
+
+
 def make_tracker(n_units, n):
     import paper_2601_20569_amd as px
     from synth import geometry as G
@@ -209,6 +220,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
     ap.add_argument("--tuning", default=None,
                     help="fixed tuning as JSON (the dict an autotuned run prints); skips the autotuner")
+    ap.add_argument("--in-row-order", default="generated", choices=["generated", "z"],
+                    help="order of the clusters inside each row of the batch: as generated "
+                         "(random), or by z as a pad/time-ordered cluster finder delivers them")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one plain 1 GiB device-to-device copy kernel (reference for HBM counters)")
     args = ap.parse_args()
@@ -235,6 +249,11 @@ def main():
         first = B["first"]
         cfg = dict(workload="timeframe-slice-batch", slices=16, collisions=int(sum(B["ncoll"])),
                    seeds="4000-4015", form="batched graph: tracking + refit of tracklets >= 20 clusters")
+        if args.in_row_order == "z":
+            y, z = order_rows_by_z(rb, y, z)
+            B["y"], B["z"] = y, z
+            cfg["in_row_order"] = "z"
+            log("clusters ordered by z inside each row")
     else:
         gen = {"timeframe": lambda: synth.timeframe_slice(seed=3000, device="cuda"),
                "central": lambda: synth.central_event(seed=2, device="cuda"),

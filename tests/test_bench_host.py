@@ -43,3 +43,18 @@ def test_committed_summary_names_every_timed_kernel():
     for stage in ("grid", "neighbours", "construct", "refit"):
         for k in bench.STAGE_KERNELS[stage]:
             assert f"traffic_bytes_per_launch {k}:" in text
+
+
+def test_order_rows_by_z_sorts_within_rows_only():
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(0)
+    counts = np.array([5, 0, 7, 1, 9])
+    rb = torch.as_tensor(np.concatenate([[0], np.cumsum(counts)]))
+    y = torch.as_tensor(rng.normal(size=counts.sum()).astype(np.float32))
+    z = torch.as_tensor(rng.normal(size=counts.sum()).astype(np.float32))
+    y2, z2 = bench.order_rows_by_z(rb, y, z)
+    for b, e in zip(rb[:-1].tolist(), rb[1:].tolist()):
+        # the same (y, z) pairs in each row, now in ascending z
+        want = sorted(zip(z[b:e].tolist(), y[b:e].tolist()))
+        assert list(zip(z2[b:e].tolist(), y2[b:e].tolist())) == want
