@@ -30,21 +30,27 @@ sys.path.insert(0, ROOT)
 METRIC = "TPC clusters/s tracked (1 GPU, % HBM roofline); batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 
-# algorithmic bytes (compulsory traffic of the method's own passes)
-B_GRID_PER_CLUSTER = 24        # read y, z (+ row range); write sorted y, z, id
-B_NF_PER_CLUSTER = 20          # read own y, z, id; write two links (neighbour rows via cache)
-B_STARTS_PER_CLUSTER = 17      # read two links, write two cleaned links and a flag
-B_STARTS_PER_START = 4         # write the start id
-B_CON_PER_START = 88           # read start id, write the tracklet record (x, 5 p, 9 cov, chi2, counts)
-B_CON_PER_CHAIN_HIT = 12       # link, y, z of every chain cluster
-B_CON_PER_CANDIDATE = 12       # y, z, id of every cluster inside the chi2 box of a searched row
+# algorithmic bytes: the compulsory traffic of the method's own passes (each
+# array read once and written once; data-dependent counts from the oracle's
+# counters), per pass of the hot path
+B_GRID_PER_CLUSTER = 24        # read y, z, id (12 B); write sorted y, z, perm (12 B)
+B_NF_PER_CLUSTER = 16          # read y, z (8 B; neighbour rows reused); write up, down links (8 B)
+B_STARTS_PER_CLUSTER = 16      # read two links (8 B), write two cleaned links (8 B)
+B_STARTS_PER_START = 8         # write the start hit (id and position)
+B_CON_PER_TRACKLET = 104       # tracklet record: x_ref, 5 parameters, covariance, chi2, n, ndf, offsets
+B_CON_PER_CHAIN_HIT = 12       # chain step: the link (4 B) and y, z (8 B) of the next chain cluster
+B_CON_PER_SEARCH = 8           # following step: the bin offsets of the search box
+B_CON_PER_CANDIDATE = 8        # y, z of every cluster inside the chi2 box of a searched row
 B_CON_PER_ATTACHED = 5         # write id and row of every attached cluster
-B_OUT_PER_START = 4            # read n
-B_OUT_PER_TRACK = 88 + 104     # read the record, write the output record
-B_OUT_PER_HIT = 10             # read and write id + row
-B_REFIT_PER_TRACK = 12        # every kept tracklet: read n, write chi2 and ok
-B_REFIT_PER_REFIT = 24         # refitted tracklet: hit offset, unit, seed (sin phi, dz/ds, q/pT)
-B_REFIT_PER_HIT = 13           # id + row of the attached cluster, its measured y, z
+B_OUT_PER_TRACK = 2 * 104      # read the tracklet record, write the kept one
+B_OUT_PER_HIT = 2 * 5          # read and write id + row of every kept cluster
+B_REFIT_PER_TRACK = 104        # refitted tracklet: its record (seed, offsets) and result
+B_REFIT_PER_HIT = 12           # refitted cluster: id, y, z
+B_SEL_PER_TRACK = 25           # ambiguity solving: unit, n, offset, chi2, ndf read; kept flag written
+B_SEL_PER_HIT = 4              # the cluster id of every attached cluster
+B_SEL_PER_CLUSTER = 20         # owner key written and read (8 + 8), assignment written (4)
+B_FIT_PER_TRACK = 128          # fit: seed, x_ref, offsets read; parameters, covariance, chi2, counts written
+B_FIT_PER_HIT = 62             # id, row, y, z read; 16-byte record written once and read twice; flag written
 
 
 # kernels of each stage, for the recorded HBM traffic (profiles/)
@@ -160,17 +166,87 @@ def cpu_baseline(cs, n_units_sample, threads):
                 sample=f"sectors {lo}-{hi - 1} of the first slice: {n} clusters, {dt:.1f} s"), res
 
 
-def timed(fn, steps, stream=None):
+def timed(fn, steps, stream=None, per_step=None):
+    """Mean ms per call of fn over `steps` calls, between events on `stream`.
+    per_step (a list): receives each call's own ms (events between calls)."""
     import torch
     s = stream or torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     sync()
-    e0.record(s)
-    for _ in range(steps):
+    ev[0].record(s)
+    for i in range(steps):
         fn()
-    e1.record(s)
+        ev[i + 1].record(s)
     sync()
-    return e0.elapsed_time(e1) / steps
+    if per_step is not None:
+        per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    return ev[0].elapsed_time(ev[steps]) / steps
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """GB/s of a plain device-to-device copy (read + write), same run."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ms = timed(lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, stream):
+    """The steps after the sector tracking on its output: ambiguity solving
+    and the three-iteration fit with interpolation rejection, both on every
+    tracklet of the batch, each timed on its own, with its algorithmic bytes
+    against the HBM peak."""
+    import torch
+    res = {}
+    o = bufs["out"]
+    sel = tr.allocate_select(n_units, n_clusters, bufs["cap_tracks"])
+    with torch.cuda.stream(stream):
+        tr.select_into(bufs, n_units, n_clusters, sel, stream=stream)
+        sync()
+        ms = timed(lambda: tr.select_into(bufs, n_units, n_clusters, sel, stream=stream), steps, stream)
+    kept = int(sel["counts"][0])
+    b = B_SEL_PER_TRACK * n_tracks + B_SEL_PER_HIT * n_hits + B_SEL_PER_CLUSTER * n_clusters
+    res["select"] = dict(ms=round(ms, 3), tracklets=n_tracks, kept=kept, shared="10%", alg_bytes=int(b),
+                         GBs=round(b / (ms * 1e-3) / 1e9, 2), frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
+    log(f"ambiguity solving: {ms:.3f} ms, {kept} of {n_tracks} tracklets kept")
+    del sel
+    torch.cuda.empty_cache()
+    # every kept tracklet (their hits are contiguous in the output)
+    hb = torch.empty(n_tracks + 1, dtype=torch.int64, device=y.device)
+    hb[:n_tracks] = o["hit_begin"][:n_tracks]
+    hb[n_tracks] = n_hits
+    args = (hb, o["hit_id"][:n_hits], o["hit_row"][:n_hits], o["param"][:n_tracks].contiguous(),
+            o["x_ref"][:n_tracks], y, z)
+    with torch.cuda.stream(stream):
+        r = tr.fit(*args, stream=stream)
+        sync()
+        del r
+        ms = timed(lambda: tr.fit(*args, stream=stream), steps, stream)
+        r = tr.fit(*args, stream=stream)
+        sync()
+    nt, nhf = n_tracks, n_hits
+    b = B_FIT_PER_TRACK * nt + B_FIT_PER_HIT * nhf
+    res["fit"] = dict(ms=round(ms, 3), tracks=nt, clusters=nhf, ok=int(r["ok"].sum()),
+                      rejected=int(r["reject"].sum()), alg_bytes=int(b), GBs=round(b / (ms * 1e-3) / 1e9, 2),
+                      frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
+    log(f"three-iteration fit: {ms:.3f} ms, {nt} tracks, {res['fit']['rejected']} clusters rejected")
+    del r, args
+    torch.cuda.empty_cache()
+    return res
 
 
 def adjoint_form(steps):
@@ -218,6 +294,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-forms", action="store_true", help="skip the plain and adjoint comparisons")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tuning")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the ambiguity solving and three-iteration fit legs")
     ap.add_argument("--tuning", default=None,
                     help="fixed tuning as JSON (the dict an autotuned run prints); skips the autotuner")
     ap.add_argument("--in-row-order", default="generated", choices=["generated", "z"],
@@ -274,6 +352,10 @@ def main():
     alpha = torch.as_tensor(G.sector_alpha(B["sectors"]).astype(np.float32), device=dev)
     theta = torch.as_tensor(np.random.default_rng(1).normal(0.0, 0.05, 36720).astype(np.float32),
                             device=dev)
+    # time frames: the drift coordinate is not z, so the map is evaluated at a
+    # fixed z (its r and phi dependence acts); single events: at the cluster's z
+    map_z = 0.0 if cfg["workload"].startswith("timeframe") else None
+    cfg["map_z"] = "0 cm (time frame)" if map_z is not None else "measured z"
     stream = torch.cuda.Stream()
     tuning = None
     if args.tuning:
@@ -285,12 +367,13 @@ def main():
     if not (args.no_autotune or args.tuning):
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
-            tuning = tr.autotune_batched(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta, reps=2)
+            tuning = tr.autotune_batched(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta, reps=2,
+                                         map_z=map_z)
         log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
     log(f"workspace {bufs['ws_bytes'] / 2**30:.1f} GiB; capturing the graph")
 
     def step():
-        tr.track_batched_into(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta)
+        tr.track_batched_into(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta, map_z=map_z)
 
     with torch.cuda.stream(stream):
         for _ in range(max(1, args.warmup)):
@@ -303,8 +386,10 @@ def main():
         n_refit, n_refit_hits = int(sel.sum()), int(nh[sel].to(torch.int64).sum())
         n_refit_ok = int(bufs["refit_ok"][:n_tracks].sum())
         log(f"warm-up done; {n_refit} tracklets refitted ({n_refit_hits} clusters, {n_refit_ok} ok)")
-        ms = timed(step, args.steps, stream)
-        log(f"timed {args.steps} graph replays: {ms:.3f} ms/step")
+        replay_ms = []
+        ms = timed(step, args.steps, stream, per_step=replay_ms)
+        log(f"timed {args.steps} graph replays: {ms:.3f} ms/step (median {np.median(replay_ms):.3f}, "
+            f"min {min(replay_ms):.3f}, max {max(replay_ms):.3f})")
         # per-stage kernel times: the same sequence launched directly with events
         tr.timing_enable(args.steps)
         for _ in range(args.steps):
@@ -327,6 +412,8 @@ def main():
         forms["batched_ms"] = round(ms, 3)
         forms["batched_tracking_only_ms"] = round(track_ms, 3)
         log(f"batched graph without the refit: {track_ms:.3f} ms/step")
+    if not args.no_next:
+        forms.update(next_steps(tr, bufs, U, N, n_tracks, n_hits, y, z, args.steps, stream))
     del bufs
     torch.cuda.empty_cache()
 
@@ -381,6 +468,9 @@ def main():
         log(f"adjoint refit: forward {adj['forward_ms']} ms, backward {adj['backward_ms']} ms "
             f"({adj['tracks']} tracks)")
 
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.1f} GB/s (read + write)")
+
     # ----- CPU baseline (oracle) on a bounded sample of the same input
     cpu = None
     per_start_con = None
@@ -389,10 +479,14 @@ def main():
         nu = args.cpu_units or threads
         log(f"oracle on {nu} sectors with {threads} threads")
         cpu, ores = cpu_baseline(first, nu, threads)
+        one, _ = cpu_baseline(first, 1, 1)
+        cpu["one_core"] = dict(value=one["value"], sample=one["sample"])
+        cpu["cpu_model"] = cpu_model()
+        cpu["host_cpus"] = os.cpu_count()
         c = ores["counters"]
         s = max(len(ores["starts"]), 1)
-        per_start_con = (B_CON_PER_START * s + B_CON_PER_CHAIN_HIT * c["chain"] +
-                         B_CON_PER_CANDIDATE * c["box_candidates"] +
+        per_start_con = (B_CON_PER_TRACKLET * s + B_CON_PER_CHAIN_HIT * c["chain"] +
+                         B_CON_PER_SEARCH * c["searches"] + B_CON_PER_CANDIDATE * c["box_candidates"] +
                          B_CON_PER_ATTACHED * c["attached"]) / s
         log(f"oracle: {cpu['value']:.3e} clusters/s ({cpu['sample']}); "
             f"constructor bytes per start hit {per_start_con:.1f}")
@@ -403,8 +497,8 @@ def main():
         "neighbours": B_NF_PER_CLUSTER * N,
         "starts": B_STARTS_PER_CLUSTER * N + B_STARTS_PER_START * n_start,
         "construct": (per_start_con * n_start) if per_start_con else None,
-        "compact": B_OUT_PER_START * n_start + B_OUT_PER_TRACK * n_tracks + B_OUT_PER_HIT * n_hits,
-        "refit": B_REFIT_PER_TRACK * n_tracks + B_REFIT_PER_REFIT * n_refit + B_REFIT_PER_HIT * n_refit_hits,
+        "compact": B_OUT_PER_TRACK * n_tracks + B_OUT_PER_HIT * n_hits,
+        "refit": B_REFIT_PER_TRACK * n_refit + B_REFIT_PER_HIT * n_refit_hits,
     }
     dom = max(stage_ms, key=stage_ms.get)
     b = stage_bytes.get(dom)
@@ -413,7 +507,8 @@ def main():
         gbs = b / (stage_ms[dom] * 1e-3) / 1e9
         tr_b = recorded_traffic(dom, cfg["workload"])
         roof = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(gbs / HBM_PEAK_GBS, 5), traffic=tr_b, kernel=dom,
+                    frac=round(gbs / HBM_PEAK_GBS, 5), traffic=tr_b,
+                    copy_GBs=round(copy_gbs, 1), frac_of_copy=round(gbs / copy_gbs, 5), kernel=dom,
                     kernels=STAGE_KERNELS.get(dom), kernel_ms=round(stage_ms[dom], 4), alg_bytes=int(b))
 
     known = [k for k in stage_ms if stage_bytes.get(k) is not None]
@@ -428,10 +523,13 @@ def main():
     if len(known) == len(stage_ms):
         tot_b = sum(stage_bytes[k] for k in known)
         path = dict(alg_bytes=int(tot_b), GBs=round(tot_b / (ms * 1e-3) / 1e9, 2),
-                    frac=round(tot_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
+                    frac=round(tot_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                    frac_of_copy=round(tot_b / (ms * 1e-3) / 1e9 / copy_gbs, 5))
 
     line = dict(metric=METRIC, value=N / (ms * 1e-3), unit="clusters/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=round(ms, 4),
+                replay_ms=dict(median=round(float(np.median(replay_ms)), 4),
+                               min=round(min(replay_ms), 4), max=round(max(replay_ms), 4)),
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
                 data="synthetic",
                 config=dict(cfg, clusters=N, units=U, start_hits=n_start, tracklets=n_tracks,

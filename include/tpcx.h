@@ -51,11 +51,13 @@ typedef int32_t tpcx_status;
 #define TPCX_E_CAPACITY (-2) /* reported by tpcx_poll: a device capacity was exceeded */
 #define TPCX_E_HIP (-3)      /* a HIP runtime call failed */
 #define TPCX_E_DEVICE (-4)   /* current device is not gfx950 */
+#define TPCX_E_INPUT (-5)    /* reported by tpcx_poll: some cluster coordinates were not finite */
 
 /* device status bits, counts[3] of tpcx_tracks */
 #define TPCX_ST_START_OVERFLOW 1 /* more start hits than cap_start */
 #define TPCX_ST_TRACK_OVERFLOW 2 /* more tracklets than cap_tracks */
 #define TPCX_ST_HIT_OVERFLOW 4   /* more attached clusters than cap_hits */
+#define TPCX_ST_NONFINITE 8      /* a cluster's y or z is not finite: it joins nothing; results otherwise complete */
 
 typedef struct tpcx_ctx tpcx_ctx;
 
@@ -156,7 +158,8 @@ tpcx_status tpcx_track(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t 
                        hipStream_t stream);
 
 /* Waits for the stream and returns TPCX_E_CAPACITY if the last tpcx_track on
- * it overflowed a capacity, TPCX_E_HIP on a runtime error, else TPCX_OK. */
+ * it overflowed a capacity, else TPCX_E_INPUT if some cluster coordinate was
+ * not finite, TPCX_E_HIP on a runtime error, else TPCX_OK. */
 tpcx_status tpcx_poll(tpcx_ctx* ctx, const tpcx_tracks* out, hipStream_t stream);
 
 const char* tpcx_strerror(tpcx_status s);
@@ -184,6 +187,7 @@ const char* tpcx_strerror(tpcx_status s);
 
 typedef struct {
   int64_t n_tracks;
+  int64_t n_hits;            /* host copy of hit_begin[n_tracks] (sizes the workspace) */
   const int64_t* hit_begin;  /* [n_tracks + 1] offsets into hit_id / hit_row */
   const int32_t* hit_id;     /* cluster ids (indices into y, z), ascending rows per track */
   const uint8_t* hit_row;    /* rows of those clusters */
@@ -194,7 +198,9 @@ typedef struct {
   const float* unit_alpha;   /* [n_units] azimuth of each unit's sector centre line, rad */
 } tpcx_refit_in;
 
-/* Workspace of tpcx_refit + tpcx_refit_backward (shared by the pair). */
+/* Workspace of tpcx_refit + tpcx_refit_backward (shared by the pair).  Both
+ * calls enqueue and return without waiting: the hit count comes from
+ * in->n_hits. */
 size_t tpcx_refit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_tracks, int64_t n_hits);
 
 /* Forward refit: chi2[n_tracks], ok[n_tracks].  theta may be NULL (no
@@ -217,7 +223,11 @@ tpcx_status tpcx_refit_backward(tpcx_ctx* ctx, const tpcx_refit_in* in, const fl
  * slice's tracklets are those of its unit range).  The whole tracking sequence
  * and the refit of every tracklet with at least refit->min_hits clusters run
  * as one HIP graph: captured on the first call with a given set of arguments,
- * replayed by later calls with the same arguments.  The stream must be one
+ * replayed by later calls with the same arguments.  In a time frame the
+ * drift coordinate of a cluster mixes its z with its collision's time, which
+ * the tracking does not know; for such input the map is evaluated at one
+ * fixed z (map_z_fixed = 1), i.e. only its dependence on r and phi acts.
+ * The stream must be one
  * that can be captured (not the legacy default stream).  The correction of
  * the clusters for the refit needs only the search grid: it runs on a second
  * stream owned by the context, forked after the grid build and joined before
@@ -227,6 +237,8 @@ tpcx_status tpcx_refit_backward(tpcx_ctx* ctx, const tpcx_refit_in* in, const fl
  * ------------------------------------------------------------------------ */
 typedef struct {
   int32_t min_hits;         /* refit tracklets with at least this many clusters (>= 2) */
+  int32_t map_z_fixed;      /* 0: map evaluated at each cluster's measured z; 1: at z = map_z */
+  float map_z;              /* cm; the z of the map evaluation when map_z_fixed (a time frame) */
   const float* theta;       /* map coefficients [TPCX_MAP_NCOEF], or NULL for no correction */
   const float* unit_alpha;  /* [n_units] azimuth of each unit's sector centre line, rad */
   float* chi2;              /* [cap_tracks] refit chi2 (0 when not refitted) */
@@ -236,12 +248,114 @@ typedef struct {
 size_t tpcx_batched_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters,
                                     int64_t cap_start, int64_t cap_tracks, int64_t cap_hits);
 
-/* Tracking of every unit of `in` plus the refit (refit may be NULL).  Outputs
- * as tpcx_track; out->counts[3] non-zero means an overflow, and then no
+/* The batched form of the sector tracking (paper, Section 2), over many
+ * units at once, with the autotuned launch shapes of Section 5's tuning:
+ * tracking of every unit of `in` plus the refit (refit may be NULL).
+ * Outputs as tpcx_track; an overflow bit in out->counts[3] means no
  * tracklet is refitted. */
 tpcx_status tpcx_track_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t ws_bytes,
                                int64_t cap_start, const tpcx_tracks* out,
                                const tpcx_batch_refit* refit, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Ambiguity solving (paper, Section 2: tracks are found several times; the
+ * best instance of each track keeps its clusters and the clones are removed,
+ * a configurable fraction of a track's clusters -- 10 % by default, 20 %
+ * after the loosening the paper describes -- may be shared with other
+ * tracks; Section 3, Phase I: among tracks competing for a cluster the one
+ * with the smaller global chi2 has priority, the track length weighing less,
+ * and shared clusters are counted starting at the outermost pad row).
+ *
+ * Rank: a tracklet ranks above another when its q = chi2/ndf (binary32
+ * quotient) is smaller, then when it has more clusters, then when it comes
+ * first in its unit.  Every cluster is owned by the highest-ranked tracklet
+ * containing it.  A tracklet is kept when, walking its clusters from the
+ * outermost row inwards, after every step k the number s(k) of clusters seen
+ * that another tracklet owns satisfies shared_den * s(k) <= shared_num * k.
+ * Every cluster is then assigned to the highest-ranked kept tracklet that
+ * contains it.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace of tpcx_select (8 bytes per cluster and per unit). */
+size_t tpcx_select_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters);
+
+/* Ambiguity solving of the tracklets a tpcx_track or tpcx_track_batched call
+ * wrote to `tracks` (unit, n_hits, hit_begin, hit_id, chi2, ndf and counts
+ * are read; the tracklet count is counts[1]; nothing is selected when
+ * counts[3] reports an overflow).  n_units and n_clusters are those of the
+ * tracking input.  Writes keep[cap_tracks] (1: kept; 0 for a clone and for
+ * every slot beyond the count), assign[n_clusters] (index of the kept
+ * tracklet a cluster is assigned to, or -1) and sel_counts[2] on the device:
+ * [0] kept tracklets, [1] status (1: a unit holds more than 2^24 tracklets,
+ * beyond the rank's index field).  shared_num / shared_den is the allowed
+ * shared fraction (shared_den >= 1).  ws: tpcx_select_workspace_bytes bytes,
+ * 256-byte aligned.  Enqueues and returns. */
+tpcx_status tpcx_select(tpcx_ctx* ctx, const tpcx_tracks* tracks, int32_t n_units, int64_t n_clusters,
+                        int32_t shared_num, int32_t shared_den, uint8_t* keep, int32_t* assign,
+                        int64_t* sel_counts, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Three-iteration track fit with interpolation-based cluster rejection
+ * (paper, Section 2, track fit: three iterations, inwards, outwards,
+ * inwards, the cluster chi2 cut taken against the interpolation between one
+ * iteration's state and the position and covariance another iteration stored
+ * per pad row in reduced precision; Section 3, Phase I: the first, inward
+ * iteration stores, the second, outward one interpolates and cuts, the third
+ * applies the rejection).
+ *
+ * Per track (clusters innermost first, y and z relative to the outermost):
+ *   1. from the tracking result at x_ref, propagate out to the outermost
+ *      cluster, take its y, z and a diagonal covariance (sy^2, sz^2, var_s,
+ *      var_t, var_w), then inwards: at every cluster store the predicted
+ *      residual (y - m_y, z - m_z) and predicted C_yy, C_zz as bfloat16
+ *      (round to nearest even), update;
+ *   2. restart at the innermost cluster (its y, z; sin(phi), dz/ds, q/pT of
+ *      iteration 1; diagonal covariance), outwards: per coordinate the
+ *      inverse-variance combination r = (d_in C_out + d_out C_in) / (C_in +
+ *      C_out), C = C_in C_out / (C_in + C_out) of the outward prediction and
+ *      the stored inward one (one of them alone at the two ends); reject the
+ *      cluster when r_y^2/(C_y + sy^2) + r_z^2/(C_z + sz^2) > chi2_cut; update
+ *      with every cluster;
+ *   3. from iteration 2's state, propagate back to the outermost kept
+ *      cluster, take its y, z and the diagonal covariance, then inwards over
+ *      the kept clusters.  Result at the innermost kept cluster; chi2 of the
+ *      kept clusters' updates; ndf = 2 n_kept - 5.
+ * A fit fails (ok = 0, zero results, nothing rejected) when a propagation
+ * guard stops a step or fewer than 3 clusters are kept.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  float chi2_cut;              /* interpolation chi2 cut (2 degrees of freedom) */
+  float var_s, var_t, var_w;   /* restart variances of sin(phi), dz/ds, q/pT */
+} tpcx_fit_params;
+
+typedef struct {
+  int64_t n_tracks;
+  int64_t n_hits;              /* host copy of hit_begin[n_tracks] */
+  const int64_t* hit_begin;    /* [n_tracks + 1] */
+  const int32_t* hit_id;       /* cluster ids, rows ascending per track */
+  const uint8_t* hit_row;
+  const float* seed;           /* [n_tracks][5] tracking result y, z, sin(phi), dz/ds, q/pT */
+  const float* x_ref;          /* [n_tracks] its plane */
+  const float* y;              /* clusters */
+  const float* z;
+} tpcx_fit_in;
+
+typedef struct {
+  float* param;     /* [n_tracks][5] at x_out */
+  float* cov;       /* [n_tracks][15] lower triangle */
+  float* chi2;      /* [n_tracks] */
+  float* x_out;     /* [n_tracks] plane of the innermost kept cluster */
+  int32_t* n_kept;  /* [n_tracks] */
+  int32_t* ok;      /* [n_tracks] */
+  uint8_t* reject;  /* [n_hits] 1: cluster rejected */
+} tpcx_fit_out;
+
+/* Workspace of tpcx_fit: 16 bytes per hit (the stored iteration-1 record). */
+size_t tpcx_fit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_hits);
+
+/* Enqueues the fit of every track of `in`; ws 256-byte aligned. */
+tpcx_status tpcx_fit(tpcx_ctx* ctx, const tpcx_fit_in* in, const tpcx_fit_params* params,
+                     const tpcx_fit_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Tuning and autotuning.  No tuning changes any result (every selection of
@@ -257,7 +371,8 @@ tpcx_status tpcx_set_tuning(tpcx_ctx* ctx, const tpcx_tuning* t);
 size_t tpcx_autotune_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters,
                                      int64_t cap_start, int64_t cap_tracks, int64_t cap_hits);
 
-/* Autotuner of the batched form.  Times the batched sequence (tracking, plus
+/* Autotuner of the batched form (paper, Section 5: launch parameters are
+ * tuned automatically per GPU).  Times the batched sequence (tracking, plus
  * the refit when refit is set) on the caller's input for candidate tunings,
  * one parameter at a time in a fixed order: z bins of the search grid, block
  * size of the per-row kernels, grid and refill threshold of the persistent

@@ -21,7 +21,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tpc_oracle.cpp")
-SOURCES = [SRC, os.path.join(HERE, "tpc_refit.cpp")]
+SOURCES = [SRC, os.path.join(HERE, "tpc_refit.cpp"), os.path.join(HERE, "tpc_select.cpp"),
+           os.path.join(HERE, "tpc_fit.cpp")]
 HEADERS = [os.path.join(HERE, "kalman.h")]
 LIB = os.path.join(HERE, "libtpc_oracle.so")
 
@@ -86,23 +87,31 @@ def lib():
         L.orc_nf_margins.restype = ctypes.c_int64
         L.orc_nf_margins.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double, P]
         L.orc_margins.restype = ctypes.c_int64
-        L.orc_margins.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double, P]
+        L.orc_margins.argtypes = [P, ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_double,
+                                  ctypes.c_double, P]
         L.orc_len.restype = ctypes.c_int64
         L.orc_len.argtypes = [P, ctypes.c_char_p]
         L.orc_get.restype = ctypes.c_int
         L.orc_get.argtypes = [P, ctypes.c_char_p, P]
         L.orc_replay.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P, ctypes.c_int64, P, P, P,
-                                 P, P, P, P, P, P, P]
+                                 P, P, P, P, P, P, P, P]
         L.orc_propagate.restype = ctypes.c_int
         L.orc_propagate.argtypes = [ctypes.c_int, P, P, ctypes.c_double]
         L.orc_update.restype = ctypes.c_double
         L.orc_update.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double]
         L.orc_map_ncoef.restype = ctypes.c_int
         L.orc_map_eval.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
+        L.orc_map_correct.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, P]
         L.orc_map_basis.restype = ctypes.c_int
         L.orc_map_basis.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
-        L.orc_refit.argtypes = [P, P, ctypes.c_int64] + [P] * 11
+        L.orc_refit.argtypes = [P, P, ctypes.c_int64] + [P] * 9 + [ctypes.c_int32, ctypes.c_double, P, P]
         L.orc_refit_grad.argtypes = [P, P, ctypes.c_int64] + [P] * 12
+        L.orc_fit.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, ctypes.c_float, ctypes.c_int64] + [P] * 14
+        L.orc_select.restype = ctypes.c_int64
+        L.orc_select.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.c_int32, P, P]
         _lib = L
     return _lib
 
@@ -157,13 +166,14 @@ def track(cs, params: Params | None = None, precision=32, brute=False, units=Non
     return out
 
 
-def nf_margins(cs, eps=1e-5, params: Params | None = None, row_x=None, constructor=False):
+def nf_margins(cs, eps=1e-5, params: Params | None = None, row_x=None, constructor=False,
+               eps_gap=1e-3):
     """Clusters whose neighbour-finder decision lies within eps (relative,
     at least absolute) of a threshold when evaluated in double: a window
     test, the D cut, or the gap between the best and second-best D; with
-    constructor=True also the chi2 cut and the best-vs-second gap of every
-    search of the double-precision constructor.  Returns a bool array over the
-    clusters."""
+    constructor=True also the chi2 cut and the propagation guards (within eps)
+    and the best-vs-second chi2 gap (within eps_gap) of every search of the
+    double-precision constructor.  Returns a bool array over the clusters."""
     from synth import geometry as G
     params = params or Params()
     xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
@@ -172,8 +182,12 @@ def nf_margins(cs, eps=1e-5, params: Params | None = None, row_x=None, construct
     z = np.ascontiguousarray(cs.z, dtype=np.float32)
     flags = np.zeros(len(y), np.uint8)
     ps = params.c_struct()
-    fn = lib().orc_margins if constructor else lib().orc_nf_margins
-    fn(_p(xr), len(xr), ctypes.byref(ps), cs.n_units, _p(rb), _p(y), _p(z), float(eps), _p(flags))
+    if constructor:
+        lib().orc_margins(_p(xr), len(xr), ctypes.byref(ps), cs.n_units, _p(rb), _p(y), _p(z),
+                          float(eps), float(eps_gap), _p(flags))
+    else:
+        lib().orc_nf_margins(_p(xr), len(xr), ctypes.byref(ps), cs.n_units, _p(rb), _p(y), _p(z),
+                             float(eps), _p(flags))
     return flags.astype(bool)
 
 
@@ -197,7 +211,8 @@ def replay(cs, tk, params: Params | None = None, precision=64, row_x=None):
     """Re-run the constructor arithmetic with the given decisions forced.
 
     ``tk`` is a dict as returned by kept_tracklets (hit_begin, hits, rows, r0,
-    flags).  Returns param [n,5], cov [n,15], chi2, xref and ok flags.
+    flags).  Returns param [n,5], cov [n,15], chi2, xref, ok flags and smax,
+    the largest |sin(phi)| the replayed trajectory reaches.
     """
     from synth import geometry as G
     params = params or Params()
@@ -215,11 +230,12 @@ def replay(cs, tk, params: Params | None = None, precision=64, row_x=None):
     chi2 = np.zeros(n)
     xref = np.zeros(n)
     ok = np.zeros(n, dtype=np.int32)
+    smax = np.zeros(n)
     ps = params.c_struct()
     lib().orc_replay(precision, _p(xr), len(xr), ctypes.byref(ps), _p(y), _p(z), n, _p(hb),
                      _p(hits), _p(rows), _p(r0), _p(fl), _p(param), _p(cov), _p(chi2), _p(xref),
-                     _p(ok))
-    return dict(param=param, cov=cov, chi2=chi2, xref=xref, ok=ok.astype(bool))
+                     _p(ok), _p(smax))
+    return dict(param=param, cov=cov, chi2=chi2, xref=xref, ok=ok.astype(bool), smax=smax)
 
 
 STATE_FIELDS = ("x", "y", "z", "s", "t", "w", "cyy", "csy", "css", "cwy", "cws", "cww",
@@ -259,6 +275,16 @@ def map_eval(theta, r, phi, z):
     return out
 
 
+def map_correct(theta, x, y, z, alpha):
+    """Corrected (x, y, z) of a cluster measured at (x, y, z) in the frame of a
+    sector centred at azimuth alpha, as the refit corrects it."""
+    th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_map_correct(_p(th) if th is not None else None, float(x), float(y), float(z),
+                          float(alpha), _p(out))
+    return out
+
+
 def map_basis(r, phi, z):
     """Non-zero basis terms at a point: (node indices [n,3] (phi, r, z), weights [n])."""
     idx = np.zeros(3 * 64, np.int32)
@@ -285,16 +311,18 @@ def _refit_args(cs, tk, params, row_x, unit_alpha):
     return params.c_struct(), keep
 
 
-def refit(cs, tk, theta=None, params: Params | None = None, row_x=None, unit_alpha=None):
+def refit(cs, tk, theta=None, params: Params | None = None, row_x=None, unit_alpha=None, map_z=None):
     """FP64 refit chi2 of every track in tk (hit lists sorted by row; seeds from
-    tk["param"]).  Returns (chi2 [n], ok [n])."""
+    tk["param"]).  map_z: evaluate the map at this z for every cluster (time
+    frames) instead of the measured z.  Returns (chi2 [n], ok [n])."""
     ps, (xr, hb, hits, rows, unit, ua, seed, y, z) = _refit_args(cs, tk, params, row_x, unit_alpha)
     n = len(hb) - 1
     th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
     chi2 = np.zeros(n)
     ok = np.zeros(n, np.int32)
     lib().orc_refit(_p(xr), ctypes.byref(ps), n, _p(hb), _p(hits), _p(rows), _p(unit), _p(ua),
-                    _p(seed), _p(y), _p(z), _p(th) if th is not None else None, _p(chi2), _p(ok))
+                    _p(seed), _p(y), _p(z), _p(th) if th is not None else None,
+                    0 if map_z is None else 1, 0.0 if map_z is None else float(map_z), _p(chi2), _p(ok))
     return chi2, ok.astype(bool)
 
 
@@ -328,3 +356,58 @@ def select_tracks(tk, min_hits=20, index=None):
     rows = np.concatenate([tk["rows"][hb[i]:hb[i + 1]] for i in sel]) if len(sel) else np.zeros(0, np.uint8)
     return dict(index=sel, unit=tk["unit"][sel], n=tk["n"][sel], hit_begin=nb, hits=hits, rows=rows,
                 param=tk["param"][sel])
+
+
+def select(tk, n_clusters, shared=(1, 10)):
+    """Ambiguity solving of kept tracklets (kept_tracklets layout: unit, n,
+    hit_begin, hits sorted by row, chi2, ndf): returns (keep [n_tracklets]
+    bool, assign [n_clusters] int32: the selected tracklet each cluster is
+    assigned to, or -1).  shared = (num, den): the allowed fraction of shared
+    clusters, counted from the outermost row."""
+    n_tr = len(tk["n"])
+    unit = np.ascontiguousarray(tk["unit"], dtype=np.int32)
+    n = np.ascontiguousarray(tk["n"], dtype=np.int32)
+    hb = np.ascontiguousarray(tk["hit_begin"], dtype=np.int64)
+    hits = np.ascontiguousarray(tk["hits"], dtype=np.int32)
+    chi2 = np.ascontiguousarray(tk["chi2"], dtype=np.float32)
+    ndf = np.ascontiguousarray(tk["ndf"], dtype=np.int32)
+    keep = np.zeros(n_tr, np.uint8)
+    assign = np.zeros(n_clusters, np.int32)
+    lib().orc_select(n_tr, _p(unit), _p(n), _p(hb), _p(hits), _p(chi2), _p(ndf), int(n_clusters),
+                     int(shared[0]), int(shared[1]), _p(keep), _p(assign))
+    return keep.astype(bool), assign
+
+
+FIT_DEFAULTS = dict(chi2_cut=16.0, vs=1e-2, vt=1e-2, vw=1.0)
+
+
+def fit(cs, tk, precision=32, reject=None, params: Params | None = None, row_x=None, **fit_params):
+    """Three-iteration fit with interpolation-based cluster rejection of the
+    tracks in tk (kept_tracklets layout: hit_begin, hits, rows, param, xref).
+    precision 32 takes the rejection decisions; pass ``reject`` (uint8 per
+    hit) with precision 64 to replay given decisions in FP64.  Returns a dict:
+    param [n,5], cov [n,15], chi2, x_out, n_kept, ok, reject [hits]."""
+    from synth import geometry as G
+    params = params or Params()
+    fp = dict(FIT_DEFAULTS, **fit_params)
+    xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
+    hb = np.ascontiguousarray(tk["hit_begin"], dtype=np.int64)
+    hits = np.ascontiguousarray(tk["hits"], dtype=np.int32)
+    rows = np.ascontiguousarray(tk["rows"], dtype=np.uint8)
+    seed = np.ascontiguousarray(tk["param"], dtype=np.float32)
+    xref = np.ascontiguousarray(tk["xref"], dtype=np.float32)
+    y = np.ascontiguousarray(cs.y, dtype=np.float32)
+    z = np.ascontiguousarray(cs.z, dtype=np.float32)
+    n = len(hb) - 1
+    decide = reject is None
+    rej = np.zeros(len(hits), np.uint8) if decide else np.ascontiguousarray(reject, dtype=np.uint8).copy()
+    out = dict(param=np.zeros((n, 5)), cov=np.zeros((n, 15)), chi2=np.zeros(n), x_out=np.zeros(n),
+               n_kept=np.zeros(n, np.int32), ok=np.zeros(n, np.int32))
+    ps = params.c_struct()
+    lib().orc_fit(precision, 1 if decide else 0, _p(xr), ctypes.byref(ps), fp["chi2_cut"], fp["vs"], fp["vt"],
+                  fp["vw"], n, _p(hb), _p(hits), _p(rows), _p(seed), _p(xref), _p(y), _p(z), _p(rej),
+                  _p(out["param"]), _p(out["cov"]), _p(out["chi2"]), _p(out["x_out"]), _p(out["n_kept"]),
+                  _p(out["ok"]))
+    out["ok"] = out["ok"].astype(bool)
+    out["reject"] = rej
+    return out

@@ -106,13 +106,56 @@ inline Dual arc_over_chord(Dual u) {
 }
 
 // Track state at the plane x: (y, z, s = sin(phi), t = dz/ds_xy, w = q/pT) and
-// the two diagonal blocks of the covariance, (y, s, w) and (z, t).
+// the two diagonal blocks of the covariance, (y, s, w) and (z, t), each held
+// as a U D U^T factorisation (U unit upper triangular, D diagonal; Bierman,
+// "Factorization Methods for Discrete Sequential Estimation", 1977):
+//   (y, s, w):  U = [[1, uys, uyw], [0, 1, usw], [0, 0, 1]],  D = diag(dy, ds, dw)
+//   (z, t):     U = [[1, uzt], [0, 1]],                       D = diag(dz, dt)
+// The transport Jacobians are unit upper triangular, so the transport only
+// adds to U, and the measurement update forms no difference of nearly equal
+// covariances (the textbook C - K H C loses about log2(C_yy / sigma^2) bits
+// in float when the predicted variance of y is far above the cluster error).
 template <class T>
 struct State {
   T x, y, z, s, t, w;
-  T cyy, csy, css, cwy, cws, cww;
-  T czz, ctz, ctt;
+  T uys, uyw, usw, dy, ds, dw;
+  T uzt, dz, dt;
 };
+
+// Covariance entries of a state, lower triangle of each block.
+template <class T>
+struct Cov9 {
+  T cyy, csy, css, cwy, cws, cww, czz, ctz, ctt;
+};
+
+template <class T>
+Cov9<T> covariance(const State<T>& st) {
+  Cov9<T> c;
+  c.cww = st.dw;
+  c.cws = st.usw * st.dw;
+  c.cwy = st.uyw * st.dw;
+  c.css = st.ds + st.usw * c.cws;
+  c.csy = st.uys * st.ds + st.uyw * c.cws;
+  c.cyy = (st.dy + st.uys * (st.uys * st.ds)) + st.uyw * c.cwy;
+  c.ctt = st.dt;
+  c.ctz = st.uzt * st.dt;
+  c.czz = st.dz + st.uzt * c.ctz;
+  return c;
+}
+
+// The factorisation of given covariance blocks (positive definite).
+template <class T>
+void set_covariance(State<T>& st, const Cov9<T>& c) {
+  st.dw = c.cww;
+  st.uyw = c.cwy / st.dw;
+  st.usw = c.cws / st.dw;
+  st.ds = c.css - st.usw * st.usw * st.dw;
+  st.uys = (c.csy - st.uyw * st.usw * st.dw) / st.ds;
+  st.dy = c.cyy - st.uys * st.uys * st.ds - st.uyw * st.uyw * st.dw;
+  st.dt = c.ctt;
+  st.uzt = c.ctz / st.dt;
+  st.dz = c.czz - st.uzt * st.uzt * st.dt;
+}
 
 // Propagate to the plane x1 along the circle of curvature -kappa*w.  Returns
 // false (state untouched) when |sin(phi)| would reach smax or the chord is too
@@ -137,30 +180,19 @@ bool propagate(State<T>& st, T x1, const Consts<T>& c) {
   if (!(u <= c.umax)) return false;
   T dS = dl * arc_over_chord(u);
   if (dx < T(0)) dS = -dS;
-  // Jacobian of (y, s) with respect to (s, w); z couples to t only.
+  // Jacobian of (y, s, w): [[1, a, b], [0, 1, e], [0, 0, 1]]; of (z, t):
+  // [[1, dS], [0, 1]] (z couples to t only).
   T r0 = st.s / c0;
   T r1 = s1 / c1;
   T icc2 = icc * icc;
   T a = dx * ((T(2) * cc + ss * (r0 + r1)) * icc2);
   T e = -(c.kappa * dx);
   T b = (dx * e) * ((cc + ss * r1) * icc2);
-  // C' = J C J^T, y-block
-  T Py = (st.cyy + a * st.csy) + b * st.cwy;
-  T Ps = (st.csy + a * st.css) + b * st.cws;
-  T Pw = (st.cwy + a * st.cws) + b * st.cww;
-  T Qy = st.csy + e * st.cwy;
-  T Qs = st.css + e * st.cws;
-  T Qw = st.cws + e * st.cww;
-  st.cyy = (Py + a * Ps) + b * Pw;
-  st.csy = (Qy + a * Qs) + b * Qw;
-  st.cwy = Pw;
-  st.css = Qs + e * Qw;
-  st.cws = Qw;
-  // z-block
-  T Rz = st.czz + dS * st.ctz;
-  T Rt = st.ctz + dS * st.ctt;
-  st.czz = Rz + dS * Rt;
-  st.ctz = Rt;
+  // C' = J U D U^T J^T = (J U) D (J U)^T: J U is unit upper triangular again
+  st.uyw = (st.uyw + a * st.usw) + b;
+  st.uys = st.uys + a;
+  st.usw = st.usw + e;
+  st.uzt = st.uzt + dS;
   // state
   st.y = st.y + dy;
   st.z = st.z + st.t * dS;
@@ -169,44 +201,115 @@ bool propagate(State<T>& st, T x1, const Consts<T>& c) {
   return true;
 }
 
+// Residual variances of a cluster measurement, S_y = C_yy + sy^2 and
+// S_z = C_zz + sz^2, as sums of non-negative terms of the factorisation; the
+// partial sums a1, a2 (and z1) are the ones the update needs.
+template <class T>
+struct Innov {
+  T v2, v3, a1, a2, sy;  // sy = S_y
+  T vz, z1, sz;          // sz = S_z
+};
+
+template <class T>
+Innov<T> innovation(const State<T>& st, const Consts<T>& c) {
+  Innov<T> q;
+  q.v2 = st.ds * st.uys;
+  q.v3 = st.dw * st.uyw;
+  q.a1 = c.sy2 + st.dy;
+  q.a2 = q.a1 + q.v2 * st.uys;
+  q.sy = q.a2 + q.v3 * st.uyw;
+  q.vz = st.dt * st.uzt;
+  q.z1 = c.sz2 + st.dz;
+  q.sz = q.z1 + q.vz * st.uzt;
+  return q;
+}
+
 // chi2 of the cluster (my, mz): squared residuals times the inverse
 // residual variances (cluster error plus track error).
 template <class T>
 T chi2_of(const State<T>& st, T my, T mz, const Consts<T>& c) {
+  const Innov<T> q = innovation(st, c);
   T ry = my - st.y;
   T rz = mz - st.z;
-  T iSy = T(1) / (st.cyy + c.sy2);
-  T iSz = T(1) / (st.czz + c.sz2);
+  T iSy = T(1) / q.sy;
+  T iSz = T(1) / q.sz;
   return (ry * ry) * iSy + (rz * rz) * iSz;
 }
 
 // Kalman update with the cluster (my, mz); returns the cluster's chi2.
+// Measurement of the first component of each block, processed as in
+// Bierman's scalar update: with f = U^T h = (1, uys, uyw) and v = D f, the
+// partial sums a1 = sy^2 + dy, a2 = a1 + v2 uys, S_y = a2 + v3 uyw give
+//   D' = (dy sy^2/a1, ds a1/a2, dw a2/S_y),
+//   uys' = uys sy^2/a1, uyw' = uyw sy^2/a2, usw' = usw - v2 uyw/a2,
+// and the gain S_y^-1 (C_yy, C_sy, C_wy) with C_yy = dy + uys v2 + uyw v3,
+// C_sy = v2 + usw v3, C_wy = v3 (the first column of the prior covariance).
+// The (z, t) block is the same with two components.
 template <class T>
 T update(State<T>& st, T my, T mz, const Consts<T>& c) {
+  const Innov<T> q = innovation(st, c);
   T ry = my - st.y;
   T rz = mz - st.z;
-  T iSy = T(1) / (st.cyy + c.sy2);
-  T iSz = T(1) / (st.czz + c.sz2);
+  T iSy = T(1) / q.sy;
+  T iSz = T(1) / q.sz;
   T chi2 = (ry * ry) * iSy + (rz * rz) * iSz;
-  T k0 = st.cyy * iSy, k1 = st.csy * iSy, k2 = st.cwy * iSy;
-  st.y = st.y + k0 * ry;
-  st.s = st.s + k1 * ry;
-  st.w = st.w + k2 * ry;
-  T cyy = st.cyy, csy = st.csy, cwy = st.cwy;
-  st.cyy = cyy - k0 * cyy;
-  st.csy = csy - k1 * cyy;
-  st.cwy = cwy - k2 * cyy;
-  st.css = st.css - k1 * csy;
-  st.cws = st.cws - k2 * csy;
-  st.cww = st.cww - k2 * cwy;
-  T kz0 = st.czz * iSz, kz1 = st.ctz * iSz;
-  st.z = st.z + kz0 * rz;
-  st.t = st.t + kz1 * rz;
-  T czz = st.czz, ctz = st.ctz;
-  st.czz = czz - kz0 * czz;
-  st.ctz = ctz - kz1 * czz;
-  st.ctt = st.ctt - kz1 * ctz;
+  T i1 = T(1) / q.a1;
+  T i2 = T(1) / q.a2;
+  T b1 = (st.dy + st.uys * q.v2) + st.uyw * q.v3;
+  T b2 = q.v2 + st.usw * q.v3;
+  T g = ry * iSy;
+  st.y = st.y + b1 * g;
+  st.s = st.s + b2 * g;
+  st.w = st.w + q.v3 * g;
+  T f1 = c.sy2 * i1;
+  st.usw = st.usw - q.v2 * (st.uyw * i2);
+  st.uyw = st.uyw * (c.sy2 * i2);
+  st.uys = st.uys * f1;
+  st.dw = st.dw * (q.a2 * iSy);
+  st.ds = st.ds * (q.a1 * i2);
+  st.dy = st.dy * f1;
+  T j1 = T(1) / q.z1;
+  T bz1 = st.dz + st.uzt * q.vz;
+  T gz = rz * iSz;
+  st.z = st.z + bz1 * gz;
+  st.t = st.t + q.vz * gz;
+  T fz = c.sz2 * j1;
+  st.uzt = st.uzt * fz;
+  st.dt = st.dt * (q.z1 * iSz);
+  st.dz = st.dz * fz;
   return chi2;
+}
+
+// The 2-point seed's covariance for a chord of length dl (1/dl = idl)
+// between two clusters of errors sy, sz: C_yy = sy^2, C_sy = sy^2/dl,
+// C_ss = 2 sy^2/dl^2 (likewise for z, t), var(q/pT) = cww0, no other
+// correlation.  Factorised: uys = dl/2, dy = sy^2/2, ds = C_ss.
+template <class T>
+void seed_covariance(State<T>& st, T dl, T idl, const Consts<T>& c) {
+  T idl2 = idl * idl;
+  st.uys = dl * T(0.5);
+  st.uyw = T(0);
+  st.usw = T(0);
+  st.dy = c.sy2 * T(0.5);
+  st.ds = (c.sy2 + c.sy2) * idl2;
+  st.dw = c.cww0;
+  st.uzt = dl * T(0.5);
+  st.dz = c.sz2 * T(0.5);
+  st.dt = (c.sz2 + c.sz2) * idl2;
+}
+
+// A diagonal covariance diag(vy, vz, vs, vt, vw).
+template <class T>
+void diagonal_covariance(State<T>& st, T vy, T vz, T vs, T vt, T vw) {
+  st.uys = T(0);
+  st.uyw = T(0);
+  st.usw = T(0);
+  st.dy = vy;
+  st.ds = vs;
+  st.dw = vw;
+  st.uzt = T(0);
+  st.dz = vz;
+  st.dt = vt;
 }
 
 

@@ -65,7 +65,12 @@ struct Unit {
       auto& v = idx[r].by_z;
       v.clear();
       for (int64_t i = rb[r]; i < rb[r + 1]; ++i) v.push_back(i);
+      // (is NaN, z, index): a strict weak order also with NaN coordinates,
+      // which go last (they pass no window test)
       std::sort(v.begin(), v.end(), [&](int64_t a, int64_t b) {
+        const bool na = std::isnan(z[a]), nb = std::isnan(z[b]);
+        if (na != nb) return nb;
+        if (na) return a < b;
         return z[a] < z[b] || (z[a] == z[b] && a < b);
       });
     }
@@ -174,23 +179,27 @@ struct Searcher {
   // within eps of the cut or of the best one are marked
   uint8_t* margin_flags = nullptr;
   double eps = 0.0;
+  double eps_gap = 0.0;  // margin of the best-vs-second chi2 gap
   // Best cluster of row r by (chi2, index) among those with chi2 <= chi2max.
   // n_box counts the clusters scanned; n_cand those inside the chi2 box
   // |dy| <= sqrt(chi2max Sy), |dz| <= sqrt(chi2max Sz), which any
   // implementation must examine (a work measure, not part of the result).
-  int64_t best(const State<T>& st, int r, T* chi2_out, int64_t* n_box, int64_t* n_cand) const {
-    double sz = std::sqrt(double(c.chi2max) * double(st.czz + c.sz2));
-    double sy = std::sqrt(double(c.chi2max) * double(st.cyy + c.sy2));
+  // The state's y and z are relative to the tracklet's origin (oy, oz).
+  int64_t best(const State<T>& st, T oy, T oz, int r, T* chi2_out, int64_t* n_box, int64_t* n_cand) const {
+    const Innov<T> iv = innovation(st, c);
+    double sz = std::sqrt(double(c.chi2max) * double(iv.sz));
+    double sy = std::sqrt(double(c.chi2max) * double(iv.sy));
     double hw = sz * (1.0 + kPadRel) + kPadAbs;
-    double lo = double(st.z) - hw, hi = double(st.z) + hw;
+    const double cy = double(oy) + double(st.y), cz = double(oz) + double(st.z);
+    double lo = cz - hw, hi = cz + hw;
     int64_t bi = -1, si = -1;
     T bc = T(0), sc = T(0);
     const double mc = eps * std::max(1.0, double(c.chi2max));
     un.scan(r, brute, lo, hi, [&](int64_t i) {
       ++*n_box;
-      if (std::fabs(double(un.y[i]) - double(st.y)) <= sy && std::fabs(double(un.z[i]) - double(st.z)) <= sz)
+      if (std::fabs(double(un.y[i]) - cy) <= sy && std::fabs(double(un.z[i]) - cz) <= sz)
         ++*n_cand;
-      T ch = chi2_of(st, T(un.y[i]), T(un.z[i]), c);
+      T ch = chi2_of(st, T(un.y[i]) - oy, T(un.z[i]) - oz, c);
       if (margin_flags && std::fabs(double(ch) - double(c.chi2max)) <= mc) margin_flags[i] = 1;
       if (!(ch <= c.chi2max)) return;
       if (bi < 0 || ch < bc || (ch == bc && i < bi)) {
@@ -203,7 +212,7 @@ struct Searcher {
         sc = ch;
       }
     });
-    if (margin_flags && si >= 0 && double(sc) - double(bc) <= eps * std::max(1.0, double(bc)))
+    if (margin_flags && si >= 0 && double(sc) - double(bc) <= eps_gap * std::max(1.0, double(bc)))
       margin_flags[bi] = margin_flags[si] = 1;
     *chi2_out = bc;
     return bi;
@@ -211,31 +220,56 @@ struct Searcher {
 };
 
 // Propagate from row `from` down to row `to` (< from) in steps of at most
-// `step` rows.  False if a step fails.
-template <class T>
-bool descend(State<T>& st, const std::vector<T>& xr, int from, int to, int step, const Consts<T>& c,
+// `step` rows, with prop(st, x) (a propagation).  False if a step fails.
+template <class T, class Prop>
+bool descend(State<T>& st, const std::vector<T>& xr, int from, int to, int step, Prop&& prop,
              int64_t* n_prop) {
   for (int rr = from; rr > to;) {
     const int next = std::max(to, rr - step);
     ++*n_prop;
-    if (!propagate(st, xr[next], c)) return false;
+    if (!prop(st, xr[next])) return false;
     rr = next;
   }
   return true;
 }
 
+// Whether a propagation of st to x1 evaluates one of its guards within eps of
+// the threshold: |sin(phi)| against smax, or the chord's u = |C| dl / 2
+// against umax (the same quantities propagate() tests).
+template <class T>
+bool guard_near(const State<T>& st, T x1, const Consts<T>& c, double eps) {
+  const double dx = double(x1) - double(st.x);
+  const double k = double(c.kappa) * double(st.w);
+  const double s0 = double(st.s), s1 = s0 - k * dx;
+  const double smax = double(c.smax), umax = double(c.umax);
+  if (std::fabs(std::fabs(s1) - smax) <= eps * std::max(1.0, smax)) return true;
+  if (!(std::fabs(s1) < smax)) return false;
+  const double c0 = std::sqrt(1.0 - s0 * s0), c1 = std::sqrt(1.0 - s1 * s1);
+  const double dy = dx * (s0 + s1) / (c0 + c1);
+  const double u = 0.5 * std::fabs(k) * std::sqrt(dx * dx + dy * dy);
+  return std::fabs(u - umax) <= eps * std::max(1.0, umax);
+}
+
 template <class T>
 Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, const int32_t* cup,
                       int64_t h0, int r0, bool brute, const Consts<T>& c, int max_misses,
-                      int descent_rows, uint8_t* margin_flags = nullptr, double eps = 0.0) {
+                      int descent_rows, uint8_t* margin_flags = nullptr, double eps = 0.0,
+                      double eps_gap = 0.0) {
   const int R = un.n_rows;
   Tracklet<T> tk;
   tk.start = h0;
   tk.unit = unit_id;
   tk.r0 = r0;
   tk.flags = 0;
-  Searcher<T> se{un, brute, c, margin_flags, eps};
+  Searcher<T> se{un, brute, c, margin_flags, eps, eps_gap};
   std::vector<std::pair<int, int32_t>> att;  // (row, cluster)
+
+  // with margin_flags set: a propagation guard evaluated within eps of its
+  // threshold marks the cluster attached last (it fixed the state)
+  auto prop = [&](State<T>& s, T x1) {
+    if (margin_flags && !att.empty() && guard_near(s, x1, c, eps)) margin_flags[att.back().second] = 1;
+    return propagate(s, x1, c);
+  };
 
   std::vector<int64_t> chain{h0};
   while (cup[chain.back()] >= 0) chain.push_back(cup[chain.back()]);
@@ -247,23 +281,19 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
   T dx = xr[r0 + 1] - xr[r0];
   T dy = T(un.y[c1]) - T(un.y[c0]);
   T dz = T(un.z[c1]) - T(un.z[c0]);
-  T idl = T(1) / std::sqrt(dx * dx + dy * dy);
-  T idl2 = idl * idl;
+  T dl = std::sqrt(dx * dx + dy * dy);
+  T idl = T(1) / dl;
+  // y and z of the state are kept relative to the seed cluster c1: their
+  // rounding then scales with the distance travelled, not with the absolute
+  // coordinate (z reaches thousands of cm in a time frame)
+  const T oy = T(un.y[c1]), oz = T(un.z[c1]);
   st.x = xr[r0 + 1];
-  st.y = T(un.y[c1]);
-  st.z = T(un.z[c1]);
+  st.y = T(0);
+  st.z = T(0);
   st.s = dy * idl;
   st.t = dz * idl;
   st.w = T(0);
-  st.cyy = c.sy2;
-  st.csy = c.sy2 * idl;
-  st.css = (c.sy2 + c.sy2) * idl2;
-  st.cwy = T(0);
-  st.cws = T(0);
-  st.cww = c.cww0;
-  st.czz = c.sz2;
-  st.ctz = c.sz2 * idl;
-  st.ctt = (c.sz2 + c.sz2) * idl2;
+  seed_covariance(st, dl, idl, c);
   T chi2 = T(0);
   int n = 2;
   att.push_back({r0, int32_t(c0)});
@@ -275,11 +305,11 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
   for (size_t j = 2; j < chain.size(); ++j) {
     int rr = r0 + int(j);
     ++tk.n_prop;
-    if (!propagate(st, xr[rr], c)) {
+    if (!prop(st, xr[rr])) {
       up_ok = false;
       break;
     }
-    chi2 = chi2 + update(st, T(un.y[chain[j]]), T(un.z[chain[j]]), c);
+    chi2 = chi2 + update(st, T(un.y[chain[j]]) - oy, T(un.z[chain[j]]) - oz, c);
     ++n;
     att.push_back({rr, int32_t(chain[j])});
     row = rr;
@@ -292,12 +322,12 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
     int misses = 0;
     for (int rr = row + 1; rr < R; ++rr) {
       ++tk.n_prop;
-      if (!propagate(st, xr[rr], c)) break;
+      if (!prop(st, xr[rr])) break;
       ++tk.n_search;
       T ch;
-      int64_t hi = se.best(st, rr, &ch, &tk.n_box, &tk.n_cand);
+      int64_t hi = se.best(st, oy, oz, rr, &ch, &tk.n_box, &tk.n_cand);
       if (hi >= 0) {
-        chi2 = chi2 + update(st, T(un.y[hi]), T(un.z[hi]), c);
+        chi2 = chi2 + update(st, T(un.y[hi]) - oy, T(un.z[hi]) - oz, c);
         ++n;
         att.push_back({rr, int32_t(hi)});
         best = st;
@@ -312,7 +342,7 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
   // back to the start row (no search, steps of at most descent_rows rows),
   // then following inwards
   st = best;
-  bool down_ok = descend(st, xr, best_row, r0, descent_rows, c, &tk.n_prop);
+  bool down_ok = descend(st, xr, best_row, r0, descent_rows, prop, &tk.n_prop);
   State<T> out = best;
   int out_row = best_row;
   if (!down_ok) {
@@ -323,12 +353,12 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
     int misses = 0;
     for (int rr = r0 - 1; rr >= 0; --rr) {
       ++tk.n_prop;
-      if (!propagate(st, xr[rr], c)) break;
+      if (!prop(st, xr[rr])) break;
       ++tk.n_search;
       T ch;
-      int64_t hi = se.best(st, rr, &ch, &tk.n_box, &tk.n_cand);
+      int64_t hi = se.best(st, oy, oz, rr, &ch, &tk.n_box, &tk.n_cand);
       if (hi >= 0) {
-        chi2 = chi2 + update(st, T(un.y[hi]), T(un.z[hi]), c);
+        chi2 = chi2 + update(st, T(un.y[hi]) - oy, T(un.z[hi]) - oz, c);
         ++n;
         att.push_back({rr, int32_t(hi)});
         out = st;
@@ -346,6 +376,8 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
     tk.rows.push_back(uint8_t(a.first));
   }
   tk.n = n;
+  out.y = oy + out.y;
+  out.z = oz + out.z;
   tk.st = out;
   tk.row_ref = out_row;
   tk.chi2 = chi2;
@@ -358,7 +390,16 @@ Tracklet<T> construct(const Unit& un, int unit_id, const std::vector<T>& xr, con
 template <class T>
 bool replay(const std::vector<T>& xr, const float* y, const float* z, const int32_t* hits,
             const uint8_t* rows, int n, int r0, int flags, int descent_rows, const Consts<T>& c,
-            State<T>* out_st, int* out_row, T* out_chi2) {
+            State<T>* out_st, int* out_row, T* out_chi2, double* out_smax = nullptr) {
+  // the largest |sin(phi)| the replayed trajectory reaches (a conditioning
+  // measure: near |sin(phi)| = 1 the step's dy/d(sin phi) grows as 1/cos^3)
+  double smax = 0.0;
+  auto prop = [&](State<T>& s, T x1) {
+    const bool ok = propagate(s, x1, c);
+    if (ok) smax = std::max(smax, std::fabs(value(s.s)));
+    if (out_smax) *out_smax = smax;
+    return ok;
+  };
   int k0 = -1;  // first hit at or above r0
   for (int i = 0; i < n; ++i)
     if (rows[i] == r0) {
@@ -371,33 +412,28 @@ bool replay(const std::vector<T>& xr, const float* y, const float* z, const int3
   T dx = xr[r0 + 1] - xr[r0];
   T dy = T(y[c1]) - T(y[c0]);
   T dz = T(z[c1]) - T(z[c0]);
-  T idl = T(1) / std::sqrt(dx * dx + dy * dy);
-  T idl2 = idl * idl;
+  T dl = std::sqrt(dx * dx + dy * dy);
+  T idl = T(1) / dl;
+  const T oy = T(y[c1]), oz = T(z[c1]);
   st.x = xr[r0 + 1];
-  st.y = T(y[c1]);
-  st.z = T(z[c1]);
+  st.y = T(0);
+  st.z = T(0);
   st.s = dy * idl;
   st.t = dz * idl;
   st.w = T(0);
-  st.cyy = c.sy2;
-  st.csy = c.sy2 * idl;
-  st.css = (c.sy2 + c.sy2) * idl2;
-  st.cwy = T(0);
-  st.cws = T(0);
-  st.cww = c.cww0;
-  st.czz = c.sz2;
-  st.ctz = c.sz2 * idl;
-  st.ctt = (c.sz2 + c.sz2) * idl2;
+  seed_covariance(st, dl, idl, c);
   T chi2 = T(0);
   int row = r0 + 1;
   for (int i = k0 + 2; i < n; ++i) {
     for (int rr = row + 1; rr <= rows[i]; ++rr)
-      if (!propagate(st, xr[rr], c)) return false;
-    chi2 = chi2 + update(st, T(y[hits[i]]), T(z[hits[i]]), c);
+      if (!prop(st, xr[rr])) return false;
+    chi2 = chi2 + update(st, T(y[hits[i]]) - oy, T(z[hits[i]]) - oz, c);
     row = rows[i];
   }
   State<T> best = st;
   int best_row = row;
+  best.y = oy + best.y;
+  best.z = oz + best.z;
   if (flags & kFlagDescentFailed) {
     *out_st = best;
     *out_row = best_row;
@@ -405,18 +441,20 @@ bool replay(const std::vector<T>& xr, const float* y, const float* z, const int3
     return k0 == 0;
   }
   int64_t np = 0;
-  if (!descend(st, xr, best_row, r0, descent_rows, c, &np)) return false;
+  if (!descend(st, xr, best_row, r0, descent_rows, prop, &np)) return false;
   row = r0;
   State<T> out = st;
   int orow = r0;
   for (int i = k0 - 1; i >= 0; --i) {
     for (int rr = row - 1; rr >= rows[i]; --rr)
-      if (!propagate(st, xr[rr], c)) return false;
-    chi2 = chi2 + update(st, T(y[hits[i]]), T(z[hits[i]]), c);
+      if (!prop(st, xr[rr])) return false;
+    chi2 = chi2 + update(st, T(y[hits[i]]) - oy, T(z[hits[i]]) - oz, c);
     row = rows[i];
     out = st;
     orow = row;
   }
+  out.y = oy + out.y;
+  out.z = oz + out.z;
   *out_st = out;
   *out_row = orow;
   *out_chi2 = chi2;
@@ -425,7 +463,8 @@ bool replay(const std::vector<T>& xr, const float* y, const float* z, const int3
 
 // 15 lower-triangle entries (row-major) of the 5x5 covariance of (y,z,s,t,w).
 template <class T>
-void cov15(const State<T>& s, double* o) {
+void cov15(const State<T>& st, double* o) {
+  const Cov9<T> s = covariance(st);
   const double v[15] = {double(s.cyy), 0.0, double(s.czz), double(s.csy), 0.0, double(s.css),
                         0.0, double(s.ctz), 0.0, double(s.ctt), double(s.cwy), 0.0, double(s.cws),
                         0.0, double(s.cww)};
@@ -449,7 +488,8 @@ struct Result {
 template <class T>
 Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
             const int64_t* row_begin, const float* y, const float* z, int unit_lo, int unit_hi,
-            int n_threads, uint8_t* margin_flags = nullptr, double eps = 0.0) {
+            int n_threads, uint8_t* margin_flags = nullptr, double eps = 0.0,
+            double eps_gap = 0.0) {
   Consts<T> c = make_consts<T>(p);
   std::vector<T> xr(n_rows);
   for (int r = 0; r < n_rows; ++r) xr[r] = T(row_x[r]);
@@ -491,7 +531,7 @@ Result* run(const float* row_x, int n_rows, const OrcParams& p, int n_units,
       int r0 = 0;
       while (!(h >= un.rb[r0] && h < un.rb[r0 + 1])) ++r0;
       tks[k].push_back(construct<T>(un, u, xr, cup, h, r0, p.brute != 0, c, p.max_misses, p.descent_rows,
-                                    margin_flags, eps));
+                                    margin_flags, eps, eps_gap));
     }
   }
   int64_t np = 0, nprop = 0, nsearch = 0, nbox = 0, natt = 0, nchain = 0, ncand = 0;
@@ -632,14 +672,19 @@ int64_t orc_nf_margins(const float* row_x, int n_rows, const OrcParams* p, int n
 
 // The margin check of both stages: orc_nf_margins, then the double-precision
 // tracklet constructor, marking every candidate whose chi2 lies within
-// eps * max(1, chi2max) of the cut, and the best and second-best candidates
-// of a search when their chi2 differ by at most eps * max(1, best).  Returns
-// the number of marked clusters.
+// eps * max(1, chi2max) of the cut, the best and second-best candidates of a
+// search when their chi2 differ by at most eps_gap * max(1, best) (an argmin
+// between two clusters is decided on a state that float carries with a
+// relative error of up to ~1e-4 after many steps, so its margin is wider than
+// that of a fixed threshold), and the cluster
+// attached last before a propagation whose sin(phi) or chord guard lies within
+// eps * max(1, threshold) of its threshold.  Returns the number of marked
+// clusters.
 int64_t orc_margins(const float* row_x, int n_rows, const OrcParams* p, int n_units,
                     const int64_t* row_begin, const float* y, const float* z, double eps,
-                    uint8_t* flags) {
+                    double eps_gap, uint8_t* flags) {
   orc_nf_margins(row_x, n_rows, p, n_units, row_begin, y, z, eps, flags);
-  delete run<double>(row_x, n_rows, *p, n_units, row_begin, y, z, -1, -1, 0, flags, eps);
+  delete run<double>(row_x, n_rows, *p, n_units, row_begin, y, z, -1, -1, 0, flags, eps, eps_gap);
   const int64_t N = row_begin[int64_t(n_units) * n_rows];
   int64_t n = 0;
   for (int64_t i = 0; i < N; ++i) n += flags[i] ? 1 : 0;
@@ -712,7 +757,7 @@ int orc_get(void* h, const char* name, void* dst) {
 void orc_replay(int precision, const float* row_x, int n_rows, const OrcParams* p, const float* y,
                 const float* z, int64_t n_tracks, const int64_t* hit_begin, const int32_t* hits,
                 const uint8_t* rows, const int32_t* r0, const int32_t* flags, double* param,
-                double* cov, double* chi2, double* xref, int32_t* ok) {
+                double* cov, double* chi2, double* xref, int32_t* ok, double* smax) {
   auto go = [&](auto tag) {
     using T = decltype(tag);
     Consts<T> c = make_consts<T>(*p);
@@ -725,7 +770,7 @@ void orc_replay(int precision, const float* row_x, int n_rows, const OrcParams* 
       int64_t b = hit_begin[i];
       int n = int(hit_begin[i + 1] - b);
       bool good = replay<T>(xr, y, z, hits + b, rows + b, n, r0[i], flags[i], p->descent_rows, c, &st,
-                             &orow, &ch);
+                             &orow, &ch, smax ? smax + i : nullptr);
       ok[i] = good ? 1 : 0;
       const double pv[5] = {double(st.y), double(st.z), double(st.s), double(st.t), double(st.w)};
       std::memcpy(param + 5 * i, pv, sizeof pv);
@@ -741,20 +786,28 @@ void orc_replay(int precision, const float* row_x, int n_rows, const OrcParams* 
 }
 
 // Single propagation step (for closed-form pins).  state: x,y,z,s,t,w then
-// the 9 covariance numbers (yy, sy, ss, wy, ws, ww, zz, tz, tt).  Returns 1 on
+// the 9 covariance numbers (yy, sy, ss, wy, ws, ww, zz, tz, tt), factorised on
+// entry and multiplied out on exit.  Returns 1 on
 // success, 0 when a guard stops it.
 int orc_propagate(int precision, const OrcParams* p, double* state, double x1) {
   auto go = [&](auto tag) {
     using T = decltype(tag);
     Consts<T> c = make_consts<T>(*p);
-    State<T> st{T(state[0]), T(state[1]), T(state[2]), T(state[3]), T(state[4]), T(state[5]),
-                T(state[6]), T(state[7]), T(state[8]), T(state[9]), T(state[10]), T(state[11]),
-                T(state[12]), T(state[13]), T(state[14])};
+    State<T> st{};
+    st.x = T(state[0]);
+    st.y = T(state[1]);
+    st.z = T(state[2]);
+    st.s = T(state[3]);
+    st.t = T(state[4]);
+    st.w = T(state[5]);
+    set_covariance(st, Cov9<T>{T(state[6]), T(state[7]), T(state[8]), T(state[9]), T(state[10]),
+                               T(state[11]), T(state[12]), T(state[13]), T(state[14])});
     bool ok = propagate(st, T(x1), c);
+    const Cov9<T> cv = covariance(st);
     const double v[15] = {double(st.x), double(st.y), double(st.z), double(st.s), double(st.t),
-                          double(st.w), double(st.cyy), double(st.csy), double(st.css),
-                          double(st.cwy), double(st.cws), double(st.cww), double(st.czz),
-                          double(st.ctz), double(st.ctt)};
+                          double(st.w), double(cv.cyy), double(cv.csy), double(cv.css),
+                          double(cv.cwy), double(cv.cws), double(cv.cww), double(cv.czz),
+                          double(cv.ctz), double(cv.ctt)};
     std::memcpy(state, v, sizeof v);
     return ok ? 1 : 0;
   };
@@ -766,14 +819,21 @@ double orc_update(int precision, const OrcParams* p, double* state, double my, d
   auto go = [&](auto tag) {
     using T = decltype(tag);
     Consts<T> c = make_consts<T>(*p);
-    State<T> st{T(state[0]), T(state[1]), T(state[2]), T(state[3]), T(state[4]), T(state[5]),
-                T(state[6]), T(state[7]), T(state[8]), T(state[9]), T(state[10]), T(state[11]),
-                T(state[12]), T(state[13]), T(state[14])};
+    State<T> st{};
+    st.x = T(state[0]);
+    st.y = T(state[1]);
+    st.z = T(state[2]);
+    st.s = T(state[3]);
+    st.t = T(state[4]);
+    st.w = T(state[5]);
+    set_covariance(st, Cov9<T>{T(state[6]), T(state[7]), T(state[8]), T(state[9]), T(state[10]),
+                               T(state[11]), T(state[12]), T(state[13]), T(state[14])});
     T ch = update(st, T(my), T(mz), c);
+    const Cov9<T> cv = covariance(st);
     const double v[15] = {double(st.x), double(st.y), double(st.z), double(st.s), double(st.t),
-                          double(st.w), double(st.cyy), double(st.csy), double(st.css),
-                          double(st.cwy), double(st.cws), double(st.cww), double(st.czz),
-                          double(st.ctz), double(st.ctt)};
+                          double(st.w), double(cv.cyy), double(cv.csy), double(cv.css),
+                          double(cv.cwy), double(cv.cws), double(cv.cww), double(cv.czz),
+                          double(cv.ctz), double(cv.ctt)};
     std::memcpy(state, v, sizeof v);
     return double(ch);
   };

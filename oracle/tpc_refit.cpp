@@ -108,9 +108,11 @@ struct Hit {
   double xc, yc, zc;          // corrected
 };
 
-void correct(const double* theta, Hit& h) {
+// z_map: the z at which the map is evaluated (the measured z, or a fixed z
+// for time-frame input, whose drift coordinate is not z)
+void correct(const double* theta, Hit& h, double z_map) {
   double d[3];
-  map_eval(theta, h.r, h.phi, h.zm, d);
+  map_eval(theta, h.r, h.phi, z_map, d);
   h.xc = h.xm + (d[0] * h.xm - d[1] * h.ym) / h.r;
   h.yc = h.ym + (d[0] * h.ym + d[1] * h.xm) / h.r;
   h.zc = h.zm + d[2];
@@ -127,15 +129,7 @@ bool refit(const T* xc, const T* yc, const T* zc, int n, double s0, double t0, d
   st.s = T(s0);
   st.t = T(t0);
   st.w = T(w0);
-  st.cyy = c.sy2;
-  st.csy = T(0);
-  st.css = T(1e-2);
-  st.cwy = T(0);
-  st.cws = T(0);
-  st.cww = T(1);
-  st.czz = c.sz2;
-  st.ctz = T(0);
-  st.ctt = T(1e-2);
+  diagonal_covariance(st, c.sy2, c.sz2, T(1e-2), T(1e-2), T(1));
   T chi2 = T(0);
   for (int i = 1; i < n; ++i) {
     if (!propagate(st, xc[i], c)) return false;
@@ -157,9 +151,12 @@ struct RefitInput {
   const float* seed;  // [n][5] y, z, sin(phi), dz/ds, q/pT of the tracking result
   const float* y;
   const float* z;
+  int z_fixed = 0;     // 1: the map is evaluated at z_map for every cluster
+  double z_map = 0.0;
 };
 
 std::vector<Hit> track_hits(const RefitInput& in, int64_t t, const double* theta) {
+  const bool fixed = in.z_fixed != 0;
   std::vector<Hit> hs;
   const double alpha = in.unit_alpha[in.unit[t]];
   for (int64_t q = in.hit_begin[t]; q < in.hit_begin[t + 1]; ++q) {
@@ -169,7 +166,7 @@ std::vector<Hit> track_hits(const RefitInput& in, int64_t t, const double* theta
     h.zm = double(in.z[in.hit_id[q]]);
     h.r = std::sqrt(h.xm * h.xm + h.ym * h.ym);
     h.phi = alpha + std::atan2(h.ym, h.xm);
-    correct(theta, h);
+    correct(theta, h, fixed ? in.z_map : h.zm);
     hs.push_back(h);
   }
   return hs;
@@ -185,17 +182,35 @@ void orc_map_eval(const double* theta, double r, double phi, double z, double* o
   map_eval(theta, r, phi, z, out3);
 }
 
+// Corrected position of a cluster measured at (x, y, z) in the frame of a
+// sector whose centre line lies at azimuth alpha (the refit's correction):
+// out3 = (x_c, y_c, z_c).
+void orc_map_correct(const double* theta, double x, double y, double z, double alpha, double* out3) {
+  Hit h;
+  h.xm = x;
+  h.ym = y;
+  h.zm = z;
+  h.r = std::sqrt(x * x + y * y);
+  h.phi = alpha + std::atan2(y, x);
+  correct(theta, h, h.zm);
+  out3[0] = h.xc;
+  out3[1] = h.yc;
+  out3[2] = h.zc;
+}
+
 // Basis terms at a point: node indices (phi, r, z) and weights; returns count.
 int orc_map_basis(double r, double phi, double z, int32_t* idx3, double* w) {
   return basis_terms(r, phi, z, idx3, w);
 }
 
 // FP64 refit chi2 per track (ok[t] = 0 when a propagation failed; chi2 = 0).
+// z_fixed = 1: the map is evaluated at z = z_map for every cluster.
 void orc_refit(const float* row_x, const OrcParams* p, int64_t n_tracks, const int64_t* hit_begin,
                const int32_t* hit_id, const uint8_t* hit_row, const int32_t* unit,
                const float* unit_alpha, const float* seed, const float* y, const float* z,
-               const double* theta, double* chi2, int32_t* ok) {
-  RefitInput in{row_x, p, n_tracks, hit_begin, hit_id, hit_row, unit, unit_alpha, seed, y, z};
+               const double* theta, int32_t z_fixed, double z_map, double* chi2, int32_t* ok) {
+  RefitInput in{row_x, p, n_tracks, hit_begin, hit_id, hit_row, unit, unit_alpha, seed, y, z,
+                z_fixed, z_map};
   const Consts<double> c = make_consts<double>(*p);
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 16)

@@ -18,6 +18,7 @@ TPCX_E_ARG = -1
 TPCX_E_CAPACITY = -2
 TPCX_E_HIP = -3
 TPCX_E_DEVICE = -4
+TPCX_E_INPUT = -5
 ST_START_OVERFLOW, ST_TRACK_OVERFLOW, ST_HIT_OVERFLOW = 1, 2, 4
 
 
@@ -63,7 +64,7 @@ class Tracks(ctypes.Structure):
 
 
 class RefitInput(ctypes.Structure):
-    _fields_ = [("n_tracks", ctypes.c_int64), ("hit_begin", ctypes.c_void_p),
+    _fields_ = [("n_tracks", ctypes.c_int64), ("n_hits", ctypes.c_int64), ("hit_begin", ctypes.c_void_p),
                 ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p),
                 ("unit", ctypes.c_void_p), ("seed", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("z", ctypes.c_void_p), ("unit_alpha", ctypes.c_void_p)]
@@ -72,8 +73,26 @@ class RefitInput(ctypes.Structure):
 MAP_NCOEF = 36720
 
 
+class FitParams(ctypes.Structure):
+    _fields_ = [("chi2_cut", ctypes.c_float), ("var_s", ctypes.c_float), ("var_t", ctypes.c_float),
+                ("var_w", ctypes.c_float)]
+
+
+class FitInput(ctypes.Structure):
+    _fields_ = [("n_tracks", ctypes.c_int64), ("n_hits", ctypes.c_int64), ("hit_begin", ctypes.c_void_p),
+                ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p), ("seed", ctypes.c_void_p),
+                ("x_ref", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class FitOutput(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("cov", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
+                ("x_out", ctypes.c_void_p), ("n_kept", ctypes.c_void_p), ("ok", ctypes.c_void_p),
+                ("reject", ctypes.c_void_p)]
+
+
 class BatchRefit(ctypes.Structure):
-    _fields_ = [("min_hits", ctypes.c_int32), ("theta", ctypes.c_void_p),
+    _fields_ = [("min_hits", ctypes.c_int32), ("map_z_fixed", ctypes.c_int32), ("map_z", ctypes.c_float),
+                ("theta", ctypes.c_void_p),
                 ("unit_alpha", ctypes.c_void_p), ("chi2", ctypes.c_void_p), ("ok", ctypes.c_void_p)]
 
 
@@ -125,6 +144,16 @@ def lib():
                                          ctypes.c_int64, ctypes.POINTER(Tracks),
                                          ctypes.POINTER(BatchRefit), P]
         L.tpcx_track_batched.restype = ctypes.c_int32
+        L.tpcx_fit_workspace_bytes.argtypes = [P, ctypes.c_int64]
+        L.tpcx_fit_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_fit.argtypes = [P, ctypes.POINTER(FitInput), ctypes.POINTER(FitParams),
+                               ctypes.POINTER(FitOutput), P, ctypes.c_size_t, P]
+        L.tpcx_fit.restype = ctypes.c_int32
+        L.tpcx_select_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
+        L.tpcx_select_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_select.argtypes = [P, ctypes.POINTER(Tracks), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_int32, P, P, P, P, ctypes.c_size_t, P]
+        L.tpcx_select.restype = ctypes.c_int32
         L.tpcx_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
         L.tpcx_set_tuning.restype = ctypes.c_int32
         L.tpcx_autotune_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
@@ -289,6 +318,76 @@ class SectorTracker:
         self._last = (tr, s)
         return tr
 
+    def fit(self, hit_begin, hit_id, hit_row, seed, x_ref, y, z, chi2_cut=16.0, var_s=1e-2, var_t=1e-2,
+            var_w=1.0, stream=None):
+        """Three-iteration fit with interpolation-based rejection (tpcx_fit) of
+        the tracks given by device tensors (hit_begin int64 [n+1], hit_id int32,
+        hit_row uint8, seed float32 [n,5], x_ref float32 [n], clusters y, z).
+        Returns a dict of device tensors: param, cov, chi2, x_out, n_kept, ok,
+        reject (no sync)."""
+        import torch
+        n = int(hit_begin.numel()) - 1
+        nh = int(hit_id.numel())
+        for v, dt in ((hit_begin, torch.int64), (hit_id, torch.int32), (hit_row, torch.uint8),
+                      (seed, torch.float32), (x_ref, torch.float32), (y, torch.float32), (z, torch.float32)):
+            if v.dtype != dt or not v.is_cuda or not v.is_contiguous():
+                raise TpcxError("fit inputs must be contiguous device tensors of the documented types")
+        dev = hit_begin.device
+        f32, i32 = torch.float32, torch.int32
+        out = dict(param=torch.zeros((max(n, 1), 5), dtype=f32, device=dev),
+                   cov=torch.zeros((max(n, 1), 15), dtype=f32, device=dev),
+                   chi2=torch.zeros(max(n, 1), dtype=f32, device=dev),
+                   x_out=torch.zeros(max(n, 1), dtype=f32, device=dev),
+                   n_kept=torch.zeros(max(n, 1), dtype=i32, device=dev),
+                   ok=torch.zeros(max(n, 1), dtype=i32, device=dev),
+                   reject=torch.zeros(max(nh, 1), dtype=torch.uint8, device=dev))
+        nb = int(lib().tpcx_fit_workspace_bytes(self._h, nh))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        fi = FitInput(n, nh, _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(seed), _ptr(x_ref), _ptr(y),
+                      _ptr(z))
+        fo = FitOutput(*[_ptr(out[k]) for k in ("param", "cov", "chi2", "x_out", "n_kept", "ok", "reject")])
+        fp = FitParams(chi2_cut, var_s, var_t, var_w)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().tpcx_fit(self._h, ctypes.byref(fi), ctypes.byref(fp), ctypes.byref(fo),
+                              ctypes.c_void_p(ws.data_ptr() + off), nb, ctypes.c_void_p(s.cuda_stream)),
+               "tpcx_fit")
+        out["_ws"] = ws
+        res = {k: v[:n] for k, v in out.items() if k not in ("reject", "_ws")}
+        res["reject"] = out["reject"][:nh]
+        res["_ws"] = ws
+        return res
+
+    def allocate_select(self, n_units, n_clusters, cap_tracks):
+        """Buffers of tpcx_select: keep flags, cluster assignment, counts, workspace."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        nb = int(lib().tpcx_select_workspace_bytes(self._h, n_units, n_clusters))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        return dict(keep=torch.empty(max(cap_tracks, 1), dtype=torch.uint8, device=dev),
+                    assign=torch.empty(max(n_clusters, 1), dtype=torch.int32, device=dev),
+                    counts=torch.zeros(2, dtype=torch.int64, device=dev), ws=ws,
+                    ws_off=(-ws.data_ptr()) % 256, ws_bytes=nb)
+
+    def select_into(self, bufs, n_units, n_clusters, sel, shared=(1, 10), stream=None):
+        """Enqueue tpcx_select on the tracklets a track_into / track_batched_into
+        call wrote to bufs (no sync)."""
+        import torch
+        tr = self._tracks_struct(bufs)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        st = lib().tpcx_select(self._h, ctypes.byref(tr), n_units, n_clusters, int(shared[0]), int(shared[1]),
+                               _ptr(sel["keep"]), _ptr(sel["assign"]), _ptr(sel["counts"]),
+                               ctypes.c_void_p(sel["ws"].data_ptr() + sel["ws_off"]), sel["ws_bytes"],
+                               ctypes.c_void_p(s.cuda_stream))
+        _check(st, "tpcx_select")
+
+    def _tracks_struct(self, bufs):
+        o = bufs["out"]
+        return Tracks(bufs["cap_tracks"], bufs["cap_hits"], _ptr(o["counts"]), _ptr(o["unit"]),
+                      _ptr(o["start"]), _ptr(o["n_hits"]), _ptr(o["hit_begin"]), _ptr(o["hit_id"]),
+                      _ptr(o["hit_row"]), _ptr(o["x_ref"]), _ptr(o["param"]), _ptr(o["cov"]),
+                      _ptr(o["chi2"]), _ptr(o["ndf"]))
+
     def allocate_batched(self, n_units, n_clusters, cap_start, cap_tracks, cap_hits, refit=True,
                          autotune=False):
         """Buffers for tpcx_track_batched: workspace (tracking + refit), outputs
@@ -307,7 +406,8 @@ class SectorTracker:
             bufs["refit_ok"] = torch.zeros(max(bufs["cap_tracks"], 1), dtype=torch.int32, device=dev)
         return bufs
 
-    def _batched_args(self, row_begin, y, z, n_units, bufs, unit_alpha, theta, refit_min_hits):
+    def _batched_args(self, row_begin, y, z, n_units, bufs, unit_alpha, theta, refit_min_hits,
+                      map_z=None):
         import torch
         n = int(y.numel())
         cl = Clusters(n_units, n, _ptr(row_begin), _ptr(y), _ptr(z))
@@ -320,35 +420,38 @@ class SectorTracker:
         if unit_alpha is not None:
             if theta is not None and (theta.dtype != torch.float32 or theta.numel() != MAP_NCOEF):
                 raise TpcxError("theta must be float32 with 36720 coefficients")
-            rf = BatchRefit(int(refit_min_hits), _ptr(theta) if theta is not None else None,
+            rf = BatchRefit(int(refit_min_hits), 0 if map_z is None else 1,
+                            0.0 if map_z is None else float(map_z),
+                            _ptr(theta) if theta is not None else None,
                             _ptr(unit_alpha), _ptr(bufs["refit_chi2"]), _ptr(bufs["refit_ok"]))
             bufs["_refit_keep"] = (theta, unit_alpha)
         ws = ctypes.c_void_p(bufs["ws"].data_ptr() + bufs["ws_off"])
         return cl, tr, rf, ws
 
     def track_batched_into(self, row_begin, y, z, n_units, bufs, stream, unit_alpha=None,
-                           theta=None, refit_min_hits=20):
+                           theta=None, refit_min_hits=20, map_z=None):
         """Enqueue tpcx_track_batched (graph captured on the first call with
         these buffers, replayed afterwards).  ``stream`` must be a non-default
         torch stream.  With ``unit_alpha`` the tracklets with at least
         ``refit_min_hits`` clusters are refitted (results in bufs["refit_chi2"],
-        bufs["refit_ok"])."""
+        bufs["refit_ok"]); ``map_z`` (cm): evaluate the map at this z for every
+        cluster (time frames), else at the measured z."""
         if stream is None or stream.cuda_stream == 0:
             raise TpcxError("the batched form needs a non-default stream (graph capture)")
         cl, tr, rf, ws = self._batched_args(row_begin, y, z, n_units, bufs, unit_alpha, theta,
-                                            refit_min_hits)
+                                            refit_min_hits, map_z)
         st = lib().tpcx_track_batched(self._h, ctypes.byref(cl), ws, bufs["ws_bytes"], bufs["cap_start"],
                                       ctypes.byref(tr), ctypes.byref(rf) if rf is not None else None,
                                       ctypes.c_void_p(stream.cuda_stream))
         _check(st, "tpcx_track_batched")
 
     def autotune_batched(self, row_begin, y, z, n_units, bufs, stream, unit_alpha=None, theta=None,
-                         refit_min_hits=20, reps=1):
+                         refit_min_hits=20, reps=1, map_z=None):
         """Run tpcx_autotune_batched on this input (buffers from
         allocate_batched(..., autotune=True)); the chosen tuning stays in the
         context and is returned as a dict."""
         cl, tr, rf, ws = self._batched_args(row_begin, y, z, n_units, bufs, unit_alpha, theta,
-                                            refit_min_hits)
+                                            refit_min_hits, map_z)
         best = Tuning()
         st = lib().tpcx_autotune_batched(self._h, ctypes.byref(cl), ws, bufs["ws_bytes"], bufs["cap_start"],
                                          ctypes.byref(tr), ctypes.byref(rf) if rf is not None else None,
@@ -382,7 +485,7 @@ class SectorTracker:
             self.track_into(row_begin, y, z, n_units, bufs, dbg)
             counts = bufs["out"]["counts"].cpu().tolist()
             n_start, n_tr, n_hits, status = counts
-            if status == 0:
+            if status & 7 == 0:  # no capacity overflow (bit 8: non-finite input, reported)
                 break
             cap_start = max(bufs["cap_start"], n_start)
             cap_tracks = max(bufs["cap_tracks"], n_tr)
@@ -425,8 +528,9 @@ class RefitJob:
                 raise TpcxError(f"refit input {k} must be a contiguous device {dt} tensor")
         self.n_tracks = int(hit_begin.numel()) - 1
         self.n_hits = int(hit_id.numel())
-        self.c = RefitInput(self.n_tracks, _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(unit),
-                            _ptr(seed), _ptr(y), _ptr(z), _ptr(unit_alpha))
+        self.c = RefitInput(self.n_tracks, self.n_hits, _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row),
+                            _ptr(unit), _ptr(seed), _ptr(y), _ptr(z), _ptr(unit_alpha))
+        self.n_forward = 0  # forward() calls so far (backward works on the last one's workspace)
         nb = int(lib().tpcx_refit_workspace_bytes(tracker._h, self.n_tracks, self.n_hits))
         dev = hit_begin.device
         self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
@@ -450,6 +554,7 @@ class RefitJob:
         _check(lib().tpcx_refit(self.tracker._h, ctypes.byref(self.c), _ptr(th) if th is not None else None,
                                 _ptr(self.chi2), _ptr(self.ok), self._ws(), self.ws_bytes,
                                 ctypes.c_void_p(s.cuda_stream)), "tpcx_refit")
+        self.n_forward += 1
         return self.chi2[:self.n_tracks]
 
     def backward(self, dL_dchi2, stream=None):
@@ -477,11 +582,22 @@ def _make_refit_chi2():
         @staticmethod
         def forward(ctx, theta, job):
             ctx.job = job
-            return job.forward(theta.detach()).clone()
+            th = theta.detach().clone()
+            ctx.save_for_backward(th)
+            chi2 = job.forward(th).clone()
+            ctx.forward_id = job.n_forward
+            return chi2
 
         @staticmethod
         def backward(ctx, grad_chi2):
-            return ctx.job.backward(grad_chi2), None
+            (th,) = ctx.saved_tensors
+            job = ctx.job
+            if job.n_forward != ctx.forward_id:
+                # another forward on this job replaced the workspace (corrected
+                # clusters, checkpoints, ok flags): redo this node's forward
+                job.forward(th)
+                ctx.forward_id = job.n_forward
+            return job.backward(grad_chi2), None
 
     return RefitChi2
 

@@ -1,0 +1,254 @@
+// Three-iteration track fit with interpolation-based cluster rejection
+// (paper, Section 2, track fit: inwards, outwards, inwards; the cluster chi2
+// cut against the interpolation of two iterations' states, the position and
+// covariance of one iteration kept in reduced precision; Section 3, Phase I:
+// the first, inward iteration stores, the second, outward one interpolates
+// and cuts, the third applies the rejection).
+//
+// One lane per track.  Iteration 1 walks from the tracking result at x_ref
+// out to the outermost cluster, restarts there (y, z of the cluster, diagonal
+// covariance) and goes inwards; at every cluster it stores, per hit, the
+// cluster relative to the track's origin (its outermost cluster) and the
+// predicted residual and variances of y and z as bfloat16 (one 16-byte
+// record).  Iteration 2 restarts at the innermost cluster and goes outwards;
+// the inverse-variance combination of its prediction with the stored one
+// gives the interpolation, whose chi2 above the cut rejects the cluster; it
+// updates with every cluster.  Iteration 3 restarts at the outermost kept
+// cluster and goes inwards over the kept ones.  IEEE binary32, no
+// contraction, correctly rounded divide and square root: every decision is
+// reproducible bit for bit.
+#pragma once
+
+#include "tpcx_common.h"
+#include "tracklet.h"
+
+namespace tpcx {
+
+struct FitIn {
+  int64_t n_tracks;
+  const int64_t* hit_begin;
+  const int32_t* hit_id;
+  const uint8_t* hit_row;
+  const float* seed;   // [n][5]
+  const float* x_ref;  // [n]
+  const float* y;
+  const float* z;
+  const float* row_x;
+};
+
+struct FitOut {
+  float* param;   // [n][5]
+  float* cov;     // [n][15]
+  float* chi2;
+  float* x_out;
+  int32_t* n_kept;
+  int32_t* ok;
+  uint8_t* reject;  // [hits]
+};
+
+struct FitConsts {
+  float chi2_cut, vs, vt, vw;
+};
+
+// bfloat16 storage: the float's 16 high bits, rounded to nearest (ties to even).
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+__device__ __forceinline__ void fit_reset_cov(KState& q, const DevParams& p, const FitConsts& f) {
+  q.uys = 0.0f;
+  q.uyw = 0.0f;
+  q.usw = 0.0f;
+  q.dy = p.sy2;
+  q.ds = f.vs;
+  q.dw = f.vw;
+  q.uzt = 0.0f;
+  q.dz = p.sz2;
+  q.dt = f.vt;
+}
+
+// Propagation without a cached (cos, sin/cos) of the current state.
+__device__ __forceinline__ bool fit_prop(KState& q, float x1, const DevParams& p) {
+  float cp = 0.0f, rp = 0.0f;
+  bool cached = false;
+  return kf_propagate<false>(q, x1, p, cp, rp, cached);
+}
+
+__device__ __forceinline__ float fit_update(KState& q, float my, float mz, const DevParams& p) {
+  const KInnov n = kf_innov(q, p);
+  const float iSy = 1.0f / n.sy;
+  const float iSz = 1.0f / n.sz;
+  return kf_update<false>(q, my, mz, n, iSy, iSz, p);
+}
+
+// C_yy and C_zz of the factorised covariance (as multiplied out for output).
+__device__ __forceinline__ float fit_cyy(const KState& q) {
+  const float cwy = q.uyw * q.dw;
+  return (q.dy + q.uys * (q.uys * q.ds)) + q.uyw * cwy;
+}
+__device__ __forceinline__ float fit_czz(const KState& q) {
+  const float ctz = q.uzt * q.dt;
+  return q.dz + q.uzt * ctz;
+}
+
+// rec[q] = (cluster y, z relative to the origin, bf16 (d_y | d_z), bf16 (C_yy | C_zz)).
+__global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts f, float4* __restrict__ rec,
+                                               FitOut out) {
+  const int64_t t = int64_t(blockIdx.x) * kWave + threadIdx.x;
+  if (t >= in.n_tracks) return;
+  const int64_t b = in.hit_begin[t];
+  const int n = int(in.hit_begin[t + 1] - b);
+  float4* R = rec + b;
+  uint8_t* rej = out.reject + b;
+  bool good = n >= 3;
+  int kept = 0;
+  float chi2 = 0.0f;
+  KState last{};
+  const float oy = in.y[in.hit_id[b + n - 1]], oz = in.z[in.hit_id[b + n - 1]];
+  auto X = [&](int i) { return in.row_x[in.hit_row[b + i]]; };
+  if (good) {
+    // ---- iteration 1: inwards, storing the predictions
+    const float* sd = in.seed + 5 * t;
+    const float xref = in.x_ref[t];
+    KState q{};
+    q.x = xref;
+    q.y = sd[0] - oy;
+    q.z = sd[1] - oz;
+    q.s = sd[2];
+    q.t = sd[3];
+    q.w = sd[4];
+    fit_reset_cov(q, p, f);
+    int first = 0;
+    while (first < n && !(X(first) > xref)) ++first;
+    for (int i = first; i < n && good; ++i)
+      if (!(q.x == X(i))) good = fit_prop(q, X(i), p);
+    if (good && !(q.x == X(n - 1))) good = fit_prop(q, X(n - 1), p);
+    if (good) {
+      q.y = 0.0f;  // the outermost cluster is the origin
+      q.z = 0.0f;
+      fit_reset_cov(q, p, f);
+      R[n - 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      for (int i = n - 2; i >= 0 && good; --i) {
+        good = fit_prop(q, X(i), p);
+        if (!good) break;
+        const int32_t c = in.hit_id[b + i];
+        const float ry = in.y[c] - oy, rz = in.z[c] - oz;
+        const uint32_t dd = bf16_bits(q.y - ry) | (bf16_bits(q.z - rz) << 16);
+        const uint32_t cc = bf16_bits(fit_cyy(q)) | (bf16_bits(fit_czz(q)) << 16);
+        R[i] = make_float4(ry, rz, __uint_as_float(dd), __uint_as_float(cc));
+        fit_update(q, ry, rz, p);
+      }
+    }
+    // ---- iteration 2: outwards, interpolation and chi2 cut
+    if (good) {
+      const float4 r0 = R[0];
+      const float s1 = q.s, t1 = q.t, w1 = q.w;
+      q = KState{};
+      q.x = X(0);
+      q.y = r0.x;
+      q.z = r0.y;
+      q.s = s1;
+      q.t = t1;
+      q.w = w1;
+      fit_reset_cov(q, p, f);
+      for (int i = 0; i < n && good; ++i) {
+        if (i > 0) {
+          good = fit_prop(q, X(i), p);
+          if (!good) break;
+        }
+        const float4 ri = R[i];
+        const float ry = i == n - 1 ? 0.0f : ri.x, rz = i == n - 1 ? 0.0f : ri.y;
+        float dy, dz, vy, vz;
+        if (i == 0) {
+          const uint32_t dd = __float_as_uint(ri.z), cc = __float_as_uint(ri.w);
+          dy = bf16_lo(dd);
+          dz = bf16_hi(dd);
+          vy = bf16_lo(cc);
+          vz = bf16_hi(cc);
+        } else {
+          const float cy = fit_cyy(q), cz = fit_czz(q);
+          const float dout = q.y - ry, eout = q.z - rz;
+          if (i == n - 1) {
+            dy = dout;
+            dz = eout;
+            vy = cy;
+            vz = cz;
+          } else {
+            const uint32_t dd = __float_as_uint(ri.z), cc = __float_as_uint(ri.w);
+            const float din = bf16_lo(dd), ein = bf16_hi(dd), cin = bf16_lo(cc), kin = bf16_hi(cc);
+            const float iy = 1.0f / (cin + cy);
+            const float iz = 1.0f / (kin + cz);
+            dy = (din * cy + dout * cin) * iy;
+            dz = (ein * cz + eout * kin) * iz;
+            vy = (cin * cy) * iy;
+            vz = (kin * cz) * iz;
+          }
+        }
+        const float c2 = (dy * dy) / (vy + p.sy2) + (dz * dz) / (vz + p.sz2);
+        rej[i] = c2 > f.chi2_cut ? 1 : 0;
+        if (i > 0) fit_update(q, ry, rz, p);
+      }
+    }
+    // ---- iteration 3: inwards over the kept clusters
+    if (good) {
+      int j = n - 1;
+      while (j >= 0 && rej[j]) --j;
+      good = j >= 2;
+      for (int i = n - 2; i >= j && good; --i) good = fit_prop(q, X(i), p);
+      if (good) {
+        const float4 rj = R[j];
+        q.y = j == n - 1 ? 0.0f : rj.x;
+        q.z = j == n - 1 ? 0.0f : rj.y;
+        fit_reset_cov(q, p, f);
+        kept = 1;
+        last = q;
+        for (int i = j - 1; i >= 0 && good; --i) {
+          good = fit_prop(q, X(i), p);
+          if (!good || rej[i]) continue;
+          const float4 ri = R[i];
+          chi2 = chi2 + fit_update(q, ri.x, ri.y, p);
+          ++kept;
+          last = q;
+        }
+        good = good && kept >= 3;
+      }
+    }
+  }
+  if (!good) {
+    // a failed fit rejects nothing
+    for (int i = 0; i < n; ++i) rej[i] = 0;
+    out.ok[t] = 0;
+    out.n_kept[t] = 0;
+    out.chi2[t] = 0.0f;
+    out.x_out[t] = 0.0f;
+    for (int k = 0; k < 5; ++k) out.param[5 * t + k] = 0.0f;
+    for (int k = 0; k < 15; ++k) out.cov[15 * t + k] = 0.0f;
+    return;
+  }
+  out.ok[t] = 1;
+  out.n_kept[t] = kept;
+  out.chi2[t] = chi2;
+  out.x_out[t] = last.x;
+  float* pp = out.param + 5 * t;
+  pp[0] = oy + last.y;
+  pp[1] = oz + last.z;
+  pp[2] = last.s;
+  pp[3] = last.t;
+  pp[4] = last.w;
+  const float cww = last.dw;
+  const float cws = last.usw * last.dw;
+  const float cwy = last.uyw * last.dw;
+  const float css = last.ds + last.usw * cws;
+  const float csy = last.uys * last.ds + last.uyw * cws;
+  const float cyy = (last.dy + last.uys * (last.uys * last.ds)) + last.uyw * cwy;
+  const float ctt = last.dt;
+  const float ctz = last.uzt * last.dt;
+  const float czz = last.dz + last.uzt * ctz;
+  const float cv[15] = {cyy, 0.0f, czz, csy, 0.0f, css, 0.0f, ctz, 0.0f, ctt, cwy, 0.0f, cws, 0.0f, cww};
+  for (int k = 0; k < 15; ++k) out.cov[15 * t + k] = cv[k];
+}
+
+}  // namespace tpcx

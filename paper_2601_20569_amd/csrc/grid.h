@@ -54,9 +54,14 @@ __device__ __forceinline__ float block_reduce_max(float v, float* lds) {
 }
 
 // Dynamic LDS: nz * ny + 1 int32 bin counters of the row.
+// Status bit set when a coordinate is not finite (such a cluster passes no
+// window or chi2 test later, so it links to and joins nothing).
+constexpr unsigned long long kStNonFinite = 8;
+
 __global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float* __restrict__ y,
                              const float* __restrict__ z, Grid g, UnitZ* __restrict__ row_z,
-                             int32_t* __restrict__ bins, float4* __restrict__ pts) {
+                             int32_t* __restrict__ bins, float4* __restrict__ pts,
+                             unsigned long long* __restrict__ status) {
   extern __shared__ int32_t hist[];
   __shared__ float red[1024 / kWave];
   __shared__ int64_t scan_lds[1024 / kWave];
@@ -69,11 +74,14 @@ __global__ void k_grid_build(const int64_t* __restrict__ row_begin, const float*
 
   // z range of the row
   float lo = INFINITY, hi = -INFINITY;
+  bool bad = false;
   for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
     const float v = z[i];
     lo = fminf(lo, v);
     hi = fmaxf(hi, v);
+    bad |= !(isfinite(v) && isfinite(y[i]));
   }
+  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(status, kStNonFinite);
   lo = block_reduce_min(lo, red);
   hi = block_reduce_max(hi, red);
   UnitZ rz;

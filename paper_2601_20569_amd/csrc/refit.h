@@ -215,6 +215,7 @@ struct RefitWs {
   float* ckpt;      // checkpoints, kCkptFloats each
   float* scratch;   // [lanes][kCkpt][kCkptFloats] states of the segment in the backward
   int64_t* acc;     // [kMapNCoef] fixed-point gradient accumulators
+  float* hgrad;     // [n_hits][4] adjoints of the corrected (x, y, z) of every hit (backward)
   int64_t n_lanes;
   unsigned long long* queue;  // [kXcds] track queues of the filter kernel (zeroed before each launch)
 };
@@ -224,7 +225,7 @@ __device__ __forceinline__ int64_t ckpt_base(const RefitIn& in, int64_t t) {
 }
 
 __device__ __forceinline__ int64_t refit_count(const RefitIn& in) {
-  if (in.status_dev && *in.status_dev != 0) return 0;
+  if (in.status_dev && (*in.status_dev & kStOverflow) != 0) return 0;
   if (!in.n_tracks_dev) return in.n_tracks;
   const int64_t n = *in.n_tracks_dev;
   return n < in.n_tracks ? n : in.n_tracks;
@@ -242,23 +243,24 @@ __device__ __forceinline__ void seed_state(KState& q, float xc, float yc, float 
   q.s = sd[2];
   q.t = sd[3];
   q.w = sd[4];
-  q.cyy = p.sy2;
-  q.csy = 0.0f;
-  q.css = 1e-2f;
-  q.cwy = 0.0f;
-  q.cws = 0.0f;
-  q.cww = 1.0f;
-  q.czz = p.sz2;
-  q.ctz = 0.0f;
-  q.ctt = 1e-2f;
+  // diag(sy^2, 1e-2, 1) and diag(sz^2, 1e-2): U = 1
+  q.uys = 0.0f;
+  q.uyw = 0.0f;
+  q.usw = 0.0f;
+  q.dy = p.sy2;
+  q.ds = 1e-2f;
+  q.dw = 1.0f;
+  q.uzt = 0.0f;
+  q.dz = p.sz2;
+  q.dt = 1e-2f;
 }
 
 __device__ __forceinline__ void store_state(float* dst, const KState& q) {
   float4* d = reinterpret_cast<float4*>(dst);
   d[0] = make_float4(q.x, q.y, q.z, q.s);
-  d[1] = make_float4(q.t, q.w, q.cyy, q.csy);
-  d[2] = make_float4(q.css, q.cwy, q.cws, q.cww);
-  d[3] = make_float4(q.czz, q.ctz, q.ctt, 0.0f);
+  d[1] = make_float4(q.t, q.w, q.uys, q.uyw);
+  d[2] = make_float4(q.usw, q.dy, q.ds, q.dw);
+  d[3] = make_float4(q.uzt, q.dz, q.dt, 0.0f);
 }
 
 __device__ __forceinline__ KState load_state(const float* src) {
@@ -266,9 +268,9 @@ __device__ __forceinline__ KState load_state(const float* src) {
   const float4 a = s[0], b = s[1], c = s[2], d = s[3];
   KState q;
   q.x = a.x; q.y = a.y; q.z = a.z; q.s = a.w;
-  q.t = b.x; q.w = b.y; q.cyy = b.z; q.csy = b.w;
-  q.css = c.x; q.cwy = c.y; q.cws = c.z; q.cww = c.w;
-  q.czz = d.x; q.ctz = d.y; q.ctt = d.z;
+  q.t = b.x; q.w = b.y; q.uys = b.z; q.uyw = b.w;
+  q.usw = c.x; q.dy = c.y; q.ds = c.z; q.dw = c.w;
+  q.uzt = d.x; q.dz = d.y; q.dt = d.z;
   return q;
 }
 
@@ -278,9 +280,10 @@ __device__ __forceinline__ bool refit_step(KState& q, float xc, float yc, float 
   float cp = 0.0f, rp = 0.0f;
   bool cached = false;
   if (!kf_propagate<true>(q, xc, p, cp, rp, cached)) return false;
-  const float iSy = k_rcp<true>(q.cyy + p.sy2);
-  const float iSz = k_rcp<true>(q.czz + p.sz2);
-  *chi2 = *chi2 + kf_update(q, yc, zc, iSy, iSz);
+  const KInnov n = kf_innov(q, p);
+  const float iSy = k_rcp<true>(n.sy);
+  const float iSz = k_rcp<true>(n.sz);
+  *chi2 = *chi2 + kf_update<true>(q, yc, zc, n, iSy, iSz, p);
   return true;
 }
 
@@ -316,10 +319,14 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_hits(RefitIn in, const 
 // sector (phi within +-20 degrees of the centre line, the r nodes of the
 // row's radius range); a cluster whose nodes lie outside that copy reads the
 // coefficient array.  Both give the same arithmetic as correct_cluster.
+// z_fixed: the map is evaluated at z = z_map for every cluster (time-frame
+// input, whose drift coordinate is not z); the correction delta z still
+// applies to the measured z.
 __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     int n_rows, const int64_t* __restrict__ row_begin, const float* __restrict__ y,
     const float* __restrict__ z, const float* __restrict__ unit_alpha,
-    const float* __restrict__ row_x, const float* __restrict__ theta, float4* __restrict__ corr) {
+    const float* __restrict__ row_x, const float* __restrict__ theta, int z_fixed, float z_map,
+    float4* __restrict__ corr) {
   __shared__ float4 stage[kStageNodes];
   const int64_t ur = xcd_block();
   const float alpha = unit_alpha[ur / n_rows];
@@ -354,7 +361,7 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     const HitGeom h = hit_geom(x, y[c], z[c], alpha, &r);
     const Weights4 wp = weights_phi(h.phi);
     const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
-    const Weights4 wz = weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
+    const Weights4 wz = weights_lin(z_fixed ? z_map : h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
     float d[3];
     if (ts.covers(wp.first, wr.first))
       map_displacement(ts, wp, wr, wz, d);
@@ -465,14 +472,15 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
 // Adjoint of the filter state (same layout as KState).
 struct KBar {
   float x, y, z, s, t, w;
-  float cyy, csy, css, cwy, cws, cww;
-  float czz, ctz, ctt;
+  float uys, uyw, usw, dy, ds, dw;
+  float uzt, dz, dt;
 };
 
 // Reverse of one refit step.  `q` is the state before the step; `g` holds the
 // adjoint of the state after it and becomes the adjoint of the state before
 // it; gchi2 is the adjoint of the step's chi2; returns the adjoints of the
-// cluster's corrected (x, y, z).  The forward arithmetic is recomputed here.
+// cluster's corrected (x, y, z).  The forward arithmetic (refit_step) is
+// recomputed here, then every assignment is reversed in the opposite order.
 __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz, const DevParams& p,
                                    float gchi2, KBar& g, float* gx1, float* gmy, float* gmz) {
   // ---------------- forward: propagation
@@ -506,175 +514,169 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   const float qb = nb * icc2;
   const float de = dx * e;
   const float b = de * qb;
-  const float Py = (q.cyy + a * q.csy) + b * q.cwy;
-  const float Ps = (q.csy + a * q.css) + b * q.cws;
-  const float Pw = (q.cwy + a * q.cws) + b * q.cww;
-  const float Qy = q.csy + e * q.cwy;
-  const float Qs = q.css + e * q.cws;
-  const float Qw = q.cws + e * q.cww;
-  const float Rz = q.czz + dS * q.ctz;
-  const float Rt = q.ctz + dS * q.ctt;
-  // state after the propagation (input of the update)
-  const float py = q.y + dy, pz = q.z + q.t * dS, ps = s1, pt = q.t, pw = q.w;
-  const float pyy = (Py + a * Ps) + b * Pw, psy = (Qy + a * Qs) + b * Qw, pwy = Pw;
-  const float pss = Qs + e * Qw, pws = Qw, pww = q.cww;
-  const float pzz = Rz + dS * Rt, ptz = Rt, ptt = q.ctt;
+  // state after the propagation (input of the update); D is unchanged
+  const float py = q.y + dy, pz = q.z + q.t * dS;
+  const float puyw = (q.uyw + a * q.usw) + b, puys = q.uys + a, pusw = q.usw + e, puzt = q.uzt + dS;
+  const float pdy = q.dy, pds = q.ds, pdw = q.dw, pdz = q.dz, pdt = q.dt;
   // ---------------- forward: update
+  const float v2 = pds * puys, v3 = pdw * puyw;
+  const float a1 = p.sy2 + pdy;
+  const float a2 = a1 + v2 * puys;
+  const float Sy = a2 + v3 * puyw;
+  const float vz = pdt * puzt;
+  const float z1 = p.sz2 + pdz;
+  const float Sz = z1 + vz * puzt;
   const float ry = my - py, rz = mz - pz;
-  const float iSy = k_rcp<true>(pyy + p.sy2), iSz = k_rcp<true>(pzz + p.sz2);
-  const float k0 = pyy * iSy, k1 = psy * iSy, k2 = pwy * iSy;
-  const float kz0 = pzz * iSz, kz1 = ptz * iSz;
+  const float iSy = k_rcp<true>(Sy), iSz = k_rcp<true>(Sz);
+  const float i1 = k_rcp<true>(a1), i2 = k_rcp<true>(a2), j1 = k_rcp<true>(z1);
+  const float b1 = (pdy + puys * v2) + puyw * v3;
+  const float b2 = v2 + pusw * v3;
+  const float gg = ry * iSy;
+  const float f1 = p.sy2 * i1, f2 = p.sy2 * i2, hh = puyw * i2;
+  const float m2 = a1 * i2, m3 = a2 * iSy;
+  const float bz1 = pdz + puzt * vz;
+  const float gzz = rz * iSz;
+  const float fz = p.sz2 * j1, mz1 = z1 * iSz;
 
-  // ---------------- reverse: update
-  float gy = g.y, gs = g.s, gw = g.w, gz = g.z, gt = g.t, gx = g.x;
-  float gyy = 0.0f, gsy = 0.0f, gwy = 0.0f, gss = g.css, gws = 0.0f, gww = g.cww;
-  float gzz = 0.0f, gtz = 0.0f, gtt = g.ctt;
-  float gk0 = 0.0f, gk1 = 0.0f, gk2 = 0.0f, gkz0 = 0.0f, gkz1 = 0.0f, gry = 0.0f, grz = 0.0f;
-  float giSy = 0.0f, giSz = 0.0f;
-  // ctt' = ctt - kz1*ctz ; ctz' = ctz - kz1*czz ; czz' = czz - kz0*czz
-  gkz1 += -g.ctt * ptz;
-  gtz += -g.ctt * kz1;
-  gtz += g.ctz;
-  gkz1 += -g.ctz * pzz;
-  gzz += -g.ctz * kz1;
-  gzz += g.czz * (1.0f - kz0);
-  gkz0 += -g.czz * pzz;
-  // t' = t + kz1*rz ; z' = z + kz0*rz
-  gkz1 += g.t * rz;
-  grz += g.t * kz1;
-  gkz0 += g.z * rz;
-  grz += g.z * kz0;
-  // kz1 = ctz*iSz ; kz0 = czz*iSz
-  gtz += gkz1 * iSz;
-  giSz += gkz1 * ptz;
-  gzz += gkz0 * iSz;
-  giSz += gkz0 * pzz;
-  // cww' = cww - k2*cwy ; cws' = cws - k2*csy ; css' = css - k1*csy
-  gk2 += -g.cww * pwy;
-  gwy += -g.cww * k2;
-  gws += g.cws;
-  gk2 += -g.cws * psy;
-  gsy += -g.cws * k2;
-  gk1 += -g.css * psy;
-  gsy += -g.css * k1;
-  // cwy' = cwy - k2*cyy ; csy' = csy - k1*cyy ; cyy' = cyy - k0*cyy
-  gwy += g.cwy;
-  gk2 += -g.cwy * pyy;
-  gyy += -g.cwy * k2;
-  gsy += g.csy;
-  gk1 += -g.csy * pyy;
-  gyy += -g.csy * k1;
-  gyy += g.cyy * (1.0f - k0);
-  gk0 += -g.cyy * pyy;
-  // w' = w + k2*ry ; s' = s + k1*ry ; y' = y + k0*ry
-  gk2 += g.w * ry;
-  gry += g.w * k2;
-  gk1 += g.s * ry;
-  gry += g.s * k1;
-  gk0 += g.y * ry;
-  gry += g.y * k0;
-  // k2 = cwy*iSy ; k1 = csy*iSy ; k0 = cyy*iSy
-  gwy += gk2 * iSy;
-  giSy += gk2 * pwy;
-  gsy += gk1 * iSy;
-  giSy += gk1 * psy;
-  gyy += gk0 * iSy;
-  giSy += gk0 * pyy;
+  // ---------------- reverse: update, (z, t) block
+  float Gpdz = 0.0f, Gpdt = 0.0f, Gpuzt = 0.0f, Gpz = 0.0f, Gpt = 0.0f;
+  float Gfz = 0.0f, Gz1 = 0.0f, GiSz = 0.0f, Gvz = 0.0f, Gbz1 = 0.0f, Ggz = 0.0f, Grz = 0.0f;
+  // dz' = pdz*fz ; dt' = pdt*mz1 (mz1 = z1*iSz) ; uzt' = puzt*fz
+  Gpdz += g.dz * fz;
+  Gfz += g.dz * pdz;
+  Gpdt += g.dt * mz1;
+  const float Gmz1 = g.dt * pdt;
+  Gz1 += Gmz1 * iSz;
+  GiSz += Gmz1 * z1;
+  Gpuzt += g.uzt * fz;
+  Gfz += g.uzt * puzt;
+  // t' = pt + vz*gzz ; z' = pz + bz1*gzz
+  Gpt += g.t;
+  Gvz += g.t * gzz;
+  Ggz += g.t * vz;
+  Gpz += g.z;
+  Gbz1 += g.z * gzz;
+  Ggz += g.z * bz1;
+  // fz = sz2*j1 ; j1 = 1/z1
+  const float Gj1 = Gfz * p.sz2;
+  Gz1 += -Gj1 * j1 * j1;
+  // gzz = rz*iSz
+  Grz += Ggz * iSz;
+  GiSz += Ggz * rz;
+  // bz1 = pdz + puzt*vz
+  Gpdz += Gbz1;
+  Gpuzt += Gbz1 * vz;
+  Gvz += Gbz1 * puzt;
+
+  // ---------------- reverse: update, (y, s, w) block
+  float Gpdy = 0.0f, Gpds = 0.0f, Gpdw = 0.0f, Gpuys = 0.0f, Gpuyw = 0.0f, Gpusw = 0.0f;
+  float Gpy = 0.0f, Gps = 0.0f, Gpw = 0.0f;
+  float Gf1 = 0.0f, Gi2 = 0.0f, Ga1 = 0.0f, Ga2 = 0.0f, GiSy = 0.0f, Gv2 = 0.0f, Gv3 = 0.0f;
+  float Gb1 = 0.0f, Gb2 = 0.0f, Ggg = 0.0f, Gry = 0.0f;
+  // dy' = pdy*f1 ; ds' = pds*m2 ; dw' = pdw*m3
+  Gpdy += g.dy * f1;
+  Gf1 += g.dy * pdy;
+  Gpds += g.ds * m2;
+  const float Gm2 = g.ds * pds;
+  Ga1 += Gm2 * i2;
+  Gi2 += Gm2 * a1;
+  Gpdw += g.dw * m3;
+  const float Gm3 = g.dw * pdw;
+  Ga2 += Gm3 * iSy;
+  GiSy += Gm3 * a2;
+  // uys' = puys*f1 ; uyw' = puyw*f2 (f2 = sy2*i2) ; usw' = pusw - v2*hh (hh = puyw*i2)
+  Gpuys += g.uys * f1;
+  Gf1 += g.uys * puys;
+  Gpuyw += g.uyw * f2;
+  Gi2 += g.uyw * puyw * p.sy2;
+  Gpusw += g.usw;
+  Gv2 += -g.usw * hh;
+  const float Ghh = -g.usw * v2;
+  Gpuyw += Ghh * i2;
+  Gi2 += Ghh * puyw;
+  // w' = pw + v3*gg ; s' = ps + b2*gg ; y' = py + b1*gg
+  Gpw += g.w;
+  Gv3 += g.w * gg;
+  Ggg += g.w * v3;
+  Gps += g.s;
+  Gb2 += g.s * gg;
+  Ggg += g.s * b2;
+  Gpy += g.y;
+  Gb1 += g.y * gg;
+  Ggg += g.y * b1;
+  // f1 = sy2*i1 ; i1 = 1/a1 ; i2 = 1/a2
+  const float Gi1 = Gf1 * p.sy2;
+  Ga1 += -Gi1 * i1 * i1;
+  Ga2 += -Gi2 * i2 * i2;
+  // gg = ry*iSy
+  Gry += Ggg * iSy;
+  GiSy += Ggg * ry;
+  // b2 = v2 + pusw*v3 ; b1 = (pdy + puys*v2) + puyw*v3
+  Gv2 += Gb2;
+  Gpusw += Gb2 * v3;
+  Gv3 += Gb2 * pusw;
+  Gpdy += Gb1;
+  Gpuys += Gb1 * v2;
+  Gv2 += Gb1 * puys;
+  Gpuyw += Gb1 * v3;
+  Gv3 += Gb1 * puyw;
   // chi2 = ry^2*iSy + rz^2*iSz
-  gry += gchi2 * 2.0f * ry * iSy;
-  giSy += gchi2 * ry * ry;
-  grz += gchi2 * 2.0f * rz * iSz;
-  giSz += gchi2 * rz * rz;
-  // iS = 1/S ; S = c + sigma^2
-  gzz += -giSz * iSz * iSz;
-  gyy += -giSy * iSy * iSy;
-  // rz = mz - z ; ry = my - y
-  *gmz = grz;
-  gz += -grz;
-  *gmy = gry;
-  gy += -gry;
-  (void)pww;
-  (void)ptt;
-  (void)pss;
-  (void)pws;
-  (void)ps;
-  (void)pt;
-  (void)pw;
-  (void)py;
+  Gry += gchi2 * 2.0f * ry * iSy;
+  GiSy += gchi2 * ry * ry;
+  Grz += gchi2 * 2.0f * rz * iSz;
+  GiSz += gchi2 * rz * rz;
+  // iSy = 1/Sy ; iSz = 1/Sz
+  const float GSy = -GiSy * iSy * iSy;
+  const float GSz = -GiSz * iSz * iSz;
+  // ry = my - py ; rz = mz - pz
+  *gmy = Gry;
+  Gpy += -Gry;
+  *gmz = Grz;
+  Gpz += -Grz;
+  // Sz = z1 + vz*puzt ; z1 = sz2 + pdz ; vz = pdt*puzt
+  Gz1 += GSz;
+  Gvz += GSz * puzt;
+  Gpuzt += GSz * vz;
+  Gpdz += Gz1;
+  Gpdt += Gvz * puzt;
+  Gpuzt += Gvz * pdt;
+  // Sy = a2 + v3*puyw ; a2 = a1 + v2*puys ; a1 = sy2 + pdy
+  Ga2 += GSy;
+  Gv3 += GSy * puyw;
+  Gpuyw += GSy * v3;
+  Ga1 += Ga2;
+  Gv2 += Ga2 * puys;
+  Gpuys += Ga2 * v2;
+  Gpdy += Ga1;
+  // v3 = pdw*puyw ; v2 = pds*puys
+  Gpdw += Gv3 * puyw;
+  Gpuyw += Gv3 * pdw;
+  Gpds += Gv2 * puys;
+  Gpuys += Gv2 * pds;
 
   // ---------------- reverse: propagation
   float gdS = 0.0f, gdy = 0.0f, gdx = 0.0f, ga = 0.0f, gb = 0.0f, ge = 0.0f, gs1 = 0.0f;
-  float gPy = 0.0f, gPs = 0.0f, gPw = 0.0f, gQy = 0.0f, gQs = 0.0f, gQw = 0.0f, gRz = 0.0f, gRt = 0.0f;
-  // outputs after propagation: (py, pz, ps, pt, pw, x1) and covariance
-  float gx1v = gx;  // x' = x1
-  float oy = 0.0f, oz = 0.0f, os = 0.0f, ot = gt, ow = gw;
-  float oyy = 0.0f, osy = 0.0f, owy = 0.0f, oss = gss, ows = gws, oww = gww;
-  float ozz = 0.0f, otz = 0.0f, ott = gtt;
-  gs1 += gs;  // s' = s1
-  // z' = z + t*dS ; y' = y + dy
-  oz += gz;
-  ot += gz * dS;
-  gdS += gz * q.t;
-  oy += gy;
-  gdy += gy;
-  // ctt' = ctt ; ctz' = Rt ; czz' = Rz + dS*Rt
-  ott += 0.0f;
-  gRt += gtz;
-  gRz += gzz;
-  gdS += gzz * Rt;
-  gRt += gzz * dS;
-  // Rt = ctz + dS*ctt ; Rz = czz + dS*ctz
-  otz += gRt;
-  gdS += gRt * q.ctt;
-  ott += gRt * dS;
-  ozz += gRz;
-  gdS += gRz * q.ctz;
-  otz += gRz * dS;
-  // cww' = cww ; cws' = Qw ; css' = Qs + e*Qw ; cwy' = Pw
-  gQw += ows;
-  ows = 0.0f;
-  gQs += oss;
-  ge += oss * Qw;
-  gQw += oss * e;
-  oss = 0.0f;
-  gPw += gwy;
-  // csy' = Qy + a*Qs + b*Qw ; cyy' = Py + a*Ps + b*Pw
-  gQy += gsy;
-  ga += gsy * Qs;
-  gQs += gsy * a;
-  gb += gsy * Qw;
-  gQw += gsy * b;
-  gPy += gyy;
-  ga += gyy * Ps;
-  gPs += gyy * a;
-  gb += gyy * Pw;
-  gPw += gyy * b;
-  // Qw = cws + e*cww ; Qs = css + e*cws ; Qy = csy + e*cwy
-  ows += gQw;
-  ge += gQw * q.cww;
-  oww += gQw * e;
-  oss += gQs;
-  ge += gQs * q.cws;
-  ows += gQs * e;
-  osy += gQy;
-  ge += gQy * q.cwy;
-  owy += gQy * e;
-  // Pw = cwy + a*cws + b*cww ; Ps = csy + a*css + b*cws ; Py = cyy + a*csy + b*cwy
-  owy += gPw;
-  ga += gPw * q.cws;
-  ows += gPw * a;
-  gb += gPw * q.cww;
-  oww += gPw * b;
-  osy += gPs;
-  ga += gPs * q.css;
-  oss += gPs * a;
-  gb += gPs * q.cws;
-  ows += gPs * b;
-  oyy += gPy;
-  ga += gPy * q.csy;
-  osy += gPy * a;
-  gb += gPy * q.cwy;
-  owy += gPy * b;
+  float gx1v = g.x;  // x' = x1
+  float oy = 0.0f, oz = 0.0f, os = 0.0f, ot = Gpt, ow = Gpw;
+  float ouys = 0.0f, ouyw = 0.0f, ousw = 0.0f, ouzt = 0.0f;
+  gs1 += Gps;  // s' = s1
+  // puzt = uzt + dS ; pusw = usw + e ; puys = uys + a ; puyw = (uyw + a*usw) + b
+  ouzt += Gpuzt;
+  gdS += Gpuzt;
+  ousw += Gpusw;
+  ge += Gpusw;
+  ouys += Gpuys;
+  ga += Gpuys;
+  ouyw += Gpuyw;
+  ga += Gpuyw * q.usw;
+  ousw += Gpuyw * a;
+  gb += Gpuyw;
+  // pz = z + t*dS ; py = y + dy
+  oz += Gpz;
+  ot += Gpz * dS;
+  gdS += Gpz * q.t;
+  oy += Gpy;
+  gdy += Gpy;
   // b = de*qb ; de = dx*e ; qb = nb*icc2 ; nb = cc + ss*r1
   float gde = gb * qb, gqb = gb * de;
   gdx += gde * e;
@@ -745,15 +747,15 @@ __device__ void refit_step_reverse(const KState& q, float x1, float my, float mz
   g.s = os;
   g.t = ot;
   g.w = ow;
-  g.cyy = oyy;
-  g.csy = osy;
-  g.css = oss;
-  g.cwy = owy;
-  g.cws = ows;
-  g.cww = oww;
-  g.czz = ozz;
-  g.ctz = otz;
-  g.ctt = ott;
+  g.uys = ouys;
+  g.uyw = ouyw;
+  g.usw = ousw;
+  g.dy = Gpdy;
+  g.ds = Gpds;
+  g.dw = Gpdw;
+  g.uzt = ouzt;
+  g.dz = Gpdz;
+  g.dt = Gpdt;
 }
 
 // Adds the coefficient gradient of one cluster: the adjoints of its corrected
@@ -799,65 +801,91 @@ __device__ __forceinline__ void add_hit_gradient(const HitGeom& h, float r, floa
   }
 }
 
-// Backward: one lane per track.  The block accumulates its coefficient
-// gradients in an LDS window of kWinPhi phi nodes centred on its first track's
-// sector, then adds the window to the global accumulators.
-__global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams p, RefitWs ws,
+// Backward, part 1: the reverse sweep, one lane per track in blocks of one
+// wavefront (a few hundred tracks already spread over every compute unit).
+// Recomputes one kCkpt-cluster segment at a time from its checkpoint into the
+// lane's scratch, runs the reverse of every step and writes the adjoint of
+// each hit's corrected (x, y, z) to hgrad (zero for tracks without gradient).
+__global__ void __launch_bounds__(kWave) k_refit_bwd_sweep(RefitIn in, DevParams p, RefitWs ws,
                                                            const float* __restrict__ dL_dchi2,
                                                            const int32_t* __restrict__ ok_in) {
-  extern __shared__ long long win[];  // [3][kWinPhi][17][20]
-  const int nwin = kMapComp * kWinPhi * kMapNR * kMapNZ;
-  for (int i = threadIdx.x; i < nwin; i += blockDim.x) win[i] = 0;
-  const int64_t t0 = int64_t(blockIdx.x) * blockDim.x;
-  // reference phi node: the sector centre of the block's first track
-  const float a_ref = in.unit_alpha[in.unit[min(t0, in.n_tracks - 1)]];
-  float ph = fmodf(a_ref, 6.28318530717958647692f);
-  if (ph < 0.0f) ph += 6.28318530717958647692f;
-  const int wref = int(floorf(ph / kMapDPhi));
-  __syncthreads();
-
-  const int64_t t = t0 + threadIdx.x;
-  if (t < in.n_tracks && ok_in[t] && dL_dchi2[t] != 0.0f) {
-    const int64_t hb = in.hit_begin[t];
-    const int n = track_size(in, t);
-    const float gchi2 = dL_dchi2[t];
-    const float alpha = in.unit_alpha[in.unit[t]];
-    const int64_t cb = ckpt_base(in, t);
-    float* scr = ws.scratch + t % ws.n_lanes * (kCkpt * kCkptFloats);
-    const float4* xyz = reinterpret_cast<const float4*>(ws.xyz);
-    const float zref = xyz[hb].z;
-    KBar g{};
-    const int nseg = (n - 2) / kCkpt + 1;  // segments covering steps 1..n-1
-    for (int m = nseg - 1; m >= 0; --m) {
-      const int i_lo = m * kCkpt;
-      const int i_hi = min((m + 1) * kCkpt, n - 1);
-      // recompute the segment's states S_{i_lo} .. S_{i_hi - 1}
-      KState q = load_state(ws.ckpt + (cb + m) * kCkptFloats);
-      for (int i = i_lo; i < i_hi; ++i) {
-        store_state(scr + (i - i_lo) * kCkptFloats, q);
-        if (i + 1 < i_hi) {
-          const float4 h = xyz[hb + i + 1];
-          float dummy = 0.0f;
-          refit_step(q, h.x, h.y, rel_z(h, zref), p, &dummy);
-        }
-      }
-      // reverse sweep over the segment's steps i = i_hi .. i_lo + 1
-      for (int i = i_hi; i > i_lo; --i) {
-        const KState prev = load_state(scr + (i - 1 - i_lo) * kCkptFloats);
-        const float4 h = xyz[hb + i];
-        float gx1, gmy, gmz;
-        refit_step_reverse(prev, h.x, h.y, rel_z(h, zref), p, gchi2, g, &gx1, &gmy, &gmz);
-        float r;
-        const HitGeom hg = hit_geom(in.row_x[in.hit_row[hb + i]], in.y[in.hit_id[hb + i]],
-                                    in.z[in.hit_id[hb + i]], alpha, &r);
-        add_hit_gradient(hg, r, gx1, gmy, gmz, wref, win, ws.acc);
+  const int64_t t = int64_t(blockIdx.x) * kWave + threadIdx.x;
+  if (t >= in.n_tracks) return;
+  const int64_t hb = in.hit_begin[t];
+  const int n = track_size(in, t);
+  float4* hg = reinterpret_cast<float4*>(ws.hgrad) + hb;
+  if (!ok_in[t] || dL_dchi2[t] == 0.0f) {
+    for (int i = 0; i < n; ++i) hg[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
+  const float gchi2 = dL_dchi2[t];
+  const int64_t cb = ckpt_base(in, t);
+  float* scr = ws.scratch + t % ws.n_lanes * (kCkpt * kCkptFloats);
+  const float4* xyz = reinterpret_cast<const float4*>(ws.xyz);
+  const float zref = xyz[hb].z;
+  KBar g{};
+  const int nseg = (n - 2) / kCkpt + 1;  // segments covering steps 1..n-1
+  for (int m = nseg - 1; m >= 0; --m) {
+    const int i_lo = m * kCkpt;
+    const int i_hi = min((m + 1) * kCkpt, n - 1);
+    // recompute the segment's states S_{i_lo} .. S_{i_hi - 1}
+    KState q = load_state(ws.ckpt + (cb + m) * kCkptFloats);
+    for (int i = i_lo; i < i_hi; ++i) {
+      store_state(scr + (i - i_lo) * kCkptFloats, q);
+      if (i + 1 < i_hi) {
+        const float4 h = xyz[hb + i + 1];
+        float dummy = 0.0f;
+        refit_step(q, h.x, h.y, rel_z(h, zref), p, &dummy);
       }
     }
-    // the first cluster seeds x, y, z of the state
+    // reverse sweep over the segment's steps i = i_hi .. i_lo + 1
+    for (int i = i_hi; i > i_lo; --i) {
+      const KState prev = load_state(scr + (i - 1 - i_lo) * kCkptFloats);
+      const float4 h = xyz[hb + i];
+      float gx1, gmy, gmz;
+      refit_step_reverse(prev, h.x, h.y, rel_z(h, zref), p, gchi2, g, &gx1, &gmy, &gmz);
+      hg[i] = make_float4(gx1, gmy, gmz, 0.0f);
+    }
+  }
+  // the first cluster seeds x, y, z of the state
+  hg[0] = make_float4(g.x, g.y, g.z, 0.0f);
+}
+
+// Backward, part 2: every hit's adjoints pulled back through the correction
+// and the basis onto the coefficients.  A block takes the hits of
+// kScatterTracks consecutive tracks and sums in 64-bit fixed point, first in
+// an LDS window of kWinPhi phi nodes around its first track's sector, then
+// into the global accumulators; the sums do not depend on the order.
+constexpr int kScatterTracks = 64;
+
+__global__ void __launch_bounds__(kRefitBlock) k_refit_bwd_scatter(RefitIn in, RefitWs ws) {
+  extern __shared__ long long win[];  // [3][kWinPhi][17][20]
+  __shared__ int64_t hb[kScatterTracks + 1];
+  __shared__ float al[kScatterTracks];
+  const int nwin = kMapComp * kWinPhi * kMapNR * kMapNZ;
+  for (int i = threadIdx.x; i < nwin; i += blockDim.x) win[i] = 0;
+  const int64_t t0 = int64_t(blockIdx.x) * kScatterTracks;
+  const int cnt = int(min(int64_t(kScatterTracks), in.n_tracks - t0));
+  const int tid = threadIdx.x;
+  if (tid <= cnt) hb[tid] = in.hit_begin[t0 + tid];
+  if (tid < cnt) al[tid] = in.unit_alpha[in.unit[t0 + tid]];
+  __syncthreads();
+  // reference phi node: the sector centre of the block's first track
+  float ph = fmodf(al[0], 6.28318530717958647692f);
+  if (ph < 0.0f) ph += 6.28318530717958647692f;
+  const int wref = int(floorf(ph / kMapDPhi));
+  const float4* hg = reinterpret_cast<const float4*>(ws.hgrad);
+  for (int64_t q = hb[0] + tid; q < hb[cnt]; q += blockDim.x) {
+    const float4 g = hg[q];
+    if (g.x == 0.0f && g.y == 0.0f && g.z == 0.0f) continue;
+    int lo = 0, hi = cnt - 1;  // last s with hb[s] <= q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hb[mid] <= q) lo = mid; else hi = mid - 1;
+    }
     float r;
-    const HitGeom hg = hit_geom(in.row_x[in.hit_row[hb]], in.y[in.hit_id[hb]], in.z[in.hit_id[hb]],
-                                alpha, &r);
-    add_hit_gradient(hg, r, g.x, g.y, g.z, wref, win, ws.acc);
+    const HitGeom h = hit_geom(in.row_x[in.hit_row[q]], in.y[in.hit_id[q]], in.z[in.hit_id[q]], al[lo], &r);
+    add_hit_gradient(h, r, g.x, g.y, g.z, wref, win, ws.acc);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nwin; i += blockDim.x) {
@@ -866,9 +894,9 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_bwd(RefitIn in, DevParams
     const int k = i % kMapNZ;
     const int j = (i / kMapNZ) % kMapNR;
     const int rel = (i / (kMapNZ * kMapNR)) % kWinPhi;
-    const int q = i / (kMapNZ * kMapNR * kWinPhi);
+    const int qq = i / (kMapNZ * kMapNR * kWinPhi);
     const int ii = ((wref + rel - kWinPhi / 2) % kMapNPhi + kMapNPhi) % kMapNPhi;
-    atomicAdd(reinterpret_cast<unsigned long long*>(&ws.acc[map_index(q, ii, j, k)]),
+    atomicAdd(reinterpret_cast<unsigned long long*>(&ws.acc[map_index(qq, ii, j, k)]),
               static_cast<unsigned long long>(v));
   }
 }

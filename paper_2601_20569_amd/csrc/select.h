@@ -1,0 +1,145 @@
+// Ambiguity solving after the sector tracking (paper, Section 2: tracks are
+// found several times; the best instance of each track keeps the clusters,
+// the clones are removed, and a configurable fraction of a track's clusters
+// may be shared; Section 3, Phase I: among tracks competing for a cluster
+// the smaller global chi2 has priority, the track length weighing less, and
+// shared clusters are counted from the outermost pad row).
+//
+// Rank of a tracklet: smaller q = chi2/ndf (IEEE binary32 quotient), then
+// more clusters, then earlier in its unit (start-hit order), packed into one
+// 64-bit key, larger = better:
+//   bits 63..32  ~bits(q)   (q >= 0: the bit pattern orders like the value)
+//   bits 31..24  n          (at most 255 clusters)
+//   bits 23..0   2^24 - 1 - index in the unit
+// so an atomic maximum over the keys of the tracklets containing a cluster
+// names its owner, whatever the order of the atomics.
+//   claim    every tracklet raises owner[c] to its key for each cluster c;
+//   decide   a tracklet is kept when, walking its clusters from the outermost
+//            row inwards, after every step k the count s(k) of clusters owned
+//            by another tracklet satisfies den s(k) <= num k;
+//   assign   the claim again with the kept tracklets only; each cluster goes
+//            to the kept tracklet whose key won (-1 when none holds it).
+#pragma once
+
+#include "tpcx_common.h"
+
+namespace tpcx {
+
+constexpr int64_t kSelectMaxPerUnit = int64_t(1) << 24;
+
+struct SelectIn {
+  int64_t cap_tracks;
+  const int64_t* counts;  // tpcx_tracks counts: [1] tracklets, [3] status
+  const int32_t* unit;
+  const int32_t* n_hits;
+  const int64_t* hit_begin;
+  const int32_t* hit_id;
+  const float* chi2;
+  const int32_t* ndf;
+};
+
+// Tracklets to consider: none when the tracking overflowed a capacity.
+__device__ __forceinline__ int64_t select_count(const SelectIn& in) {
+  if ((in.counts[3] & kStOverflow) != 0) return 0;
+  return in.counts[1] < in.cap_tracks ? in.counts[1] : in.cap_tracks;
+}
+
+__device__ __forceinline__ uint64_t select_key(const SelectIn& in, const int64_t* first, int64_t t) {
+  const float q = in.chi2[t] / float(in.ndf[t]);
+  const int64_t local = t - first[in.unit[t]];
+  const uint32_t lo = uint32_t(min(in.n_hits[t], 255)) << 24 |
+                      uint32_t(kSelectMaxPerUnit - 1 - min(local, kSelectMaxPerUnit - 1));
+  return uint64_t(~__float_as_uint(q)) << 32 | lo;
+}
+
+// first[u] = index of the first tracklet of unit u (tracklets are in unit
+// order); status bit 1 when a unit holds more tracklets than the key's
+// 24-bit index can order.
+__global__ void k_select_first(SelectIn in, int64_t* __restrict__ first, int64_t* __restrict__ status) {
+  const int64_t n = select_count(in);
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int32_t u = in.unit[t];
+    if (t == 0 || in.unit[t - 1] != u) first[u] = t;
+    if (t + 1 == n || in.unit[t + 1] != u) {
+      // last of its unit: the unit's count must fit the key
+      int64_t lo = 0, hi = t;  // first tracklet of u, by binary search (t is the last)
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (in.unit[mid] < u) lo = mid + 1; else hi = mid;
+      }
+      if (t - lo + 1 > kSelectMaxPerUnit) atomicOr(reinterpret_cast<unsigned long long*>(status), 1ull);
+    }
+  }
+}
+
+// owner[c] = max over (kept, when keep is set) tracklets containing c of
+// their keys.  One lane per tracklet.
+__global__ void k_select_claim(SelectIn in, const int64_t* __restrict__ first,
+                               const uint8_t* __restrict__ keep, unsigned long long* __restrict__ owner) {
+  const int64_t n = select_count(in);
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    if (keep && !keep[t]) continue;
+    const unsigned long long key = select_key(in, first, t);
+    const int64_t b = in.hit_begin[t];
+    const int m = in.n_hits[t];
+    for (int j = 0; j < m; ++j) atomicMax(owner + in.hit_id[b + j], key);
+  }
+}
+
+// keep[t] from the outer-first shared count; n_sel[0] += kept tracklets.
+__global__ void k_select_decide(SelectIn in, const int64_t* __restrict__ first,
+                                const unsigned long long* __restrict__ owner, int32_t num, int32_t den,
+                                uint8_t* __restrict__ keep, int64_t* __restrict__ n_sel) {
+  const int64_t n = select_count(in);
+  int64_t kept = 0;
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const unsigned long long key = select_key(in, first, t);
+    const int64_t b = in.hit_begin[t];
+    const int m = in.n_hits[t];
+    int64_t shared = 0;
+    bool ok = true;
+    for (int k = 1; k <= m; ++k) {
+      if (owner[in.hit_id[b + m - k]] != key) ++shared;
+      if (int64_t(den) * shared > int64_t(num) * k) {
+        ok = false;
+        break;
+      }
+    }
+    keep[t] = ok ? 1 : 0;
+    kept += ok ? 1 : 0;
+  }
+  // one atomic per wavefront
+  for (int d = kWave / 2; d > 0; d >>= 1) kept += __shfl_xor(kept, d, kWave);
+  if (lane_id() == 0 && kept) atomicAdd(reinterpret_cast<unsigned long long*>(n_sel),
+                                        static_cast<unsigned long long>(kept));
+}
+
+// assign[c] = t for every cluster whose owner key is kept tracklet t's.
+__global__ void k_select_assign(SelectIn in, const int64_t* __restrict__ first,
+                                const uint8_t* __restrict__ keep,
+                                const unsigned long long* __restrict__ owner, int32_t* __restrict__ assign) {
+  const int64_t n = select_count(in);
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    if (!keep[t]) continue;
+    const unsigned long long key = select_key(in, first, t);
+    const int64_t b = in.hit_begin[t];
+    const int m = in.n_hits[t];
+    for (int j = 0; j < m; ++j) {
+      const int32_t c = in.hit_id[b + j];
+      if (owner[c] == key) assign[c] = int32_t(t);
+    }
+  }
+}
+
+// keep = 0 for the tracklets beyond the count (whole capacity).
+__global__ void k_select_clear(int64_t cap, uint8_t* __restrict__ keep) {
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < cap;
+       t += int64_t(gridDim.x) * blockDim.x)
+    keep[t] = 0;
+}
+
+}  // namespace tpcx

@@ -13,6 +13,8 @@
 #include "grid.h"
 #include "links.h"
 #include "refit.h"
+#include "select.h"
+#include "fit.h"
 #include "tpcx_common.h"
 #include "tracklet.h"
 
@@ -130,6 +132,7 @@ RefitLayout carve_refit(void* base, int64_t n_tracks, int64_t n_hits) {
   L.ws.n_lanes = std::max<int64_t>(n_tracks, 1);
   L.ws.scratch = cv.take<float>(L.ws.n_lanes * kCkpt * kCkptFloats);
   L.ws.acc = cv.take<int64_t>(kMapNCoef);
+  L.ws.hgrad = cv.take<float>(4 * std::max<int64_t>(n_hits, 1));
   L.ws.queue = cv.take<unsigned long long>(kXcds);
   L.ok = cv.take<int32_t>(n_tracks);
   L.bytes = cv.off;
@@ -165,7 +168,7 @@ int refit_filter_grid(const tpcx_ctx* c, int64_t n_tracks, int32_t refit_grid) {
 }
 
 bool refit_args_ok(const tpcx_ctx* c, const tpcx_refit_in* in) {
-  if (!c || !in || in->n_tracks < 0) return false;
+  if (!c || !in || in->n_tracks < 0 || in->n_hits < 0) return false;
   if (in->n_tracks > 0 && (!in->hit_begin || !in->hit_id || !in->hit_row || !in->unit || !in->seed ||
                            !in->y || !in->z || !in->unit_alpha))
     return false;
@@ -399,7 +402,8 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   const int UR = U * R;
   const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
   hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,
-                     in->z, g, L.row_z, L.bins, L.pts);
+                     in->z, g, L.row_z, L.bins, L.pts,
+                     reinterpret_cast<unsigned long long*>(out->counts + 3));
   if (after_grid) (void)hipEventRecord(after_grid, stream);
   mark(1);
   hipLaunchKernelGGL(k_neighbours, dim3(UR), dim3(kNfBlock), 0, stream, in->row_begin, g,
@@ -460,7 +464,7 @@ void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_
   if (in->n_clusters > 0)
     hipLaunchKernelGGL(k_correct_clusters, dim3(unsigned(n_ur)), dim3(kRefitBlock), 0, c->aux,
                        c->n_rows, in->row_begin, in->y, in->z, refit->unit_alpha, c->d_row_x,
-                       refit->theta, RL.corr);
+                       refit->theta, refit->map_z_fixed ? 1 : 0, refit->map_z, RL.corr);
   (void)hipEventRecord(c->ev_join, c->aux);
 
   RefitIn r;
@@ -575,9 +579,14 @@ hipEvent_t* next_timing_slot(tpcx_ctx* c) {
 
 extern "C" {
 
-tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
-                       int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
-                       hipStream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// tpcx_track on the workspace ws of ws_bytes.
+tpcx_status track_on(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                     int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
+                     hipStream_t stream) {
   const tpcx_status st = check_track_args(c, in, ws, cap_start, out);
   if (st != TPCX_OK) return st;
   const int64_t N = in->n_clusters;
@@ -599,12 +608,24 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
+}  // namespace
+
+extern "C" {
+
+tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws_bytes,
+                       int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
+                       hipStream_t stream) {
+  return track_on(c, in, ws, ws_bytes, cap_start, out, dbg, stream);
+}
+
+
 tpcx_status tpcx_poll(tpcx_ctx* c, const tpcx_tracks* out, hipStream_t stream) {
   if (!c || !out || !out->counts) return TPCX_E_ARG;
   if (hipStreamSynchronize(stream) != hipSuccess) return TPCX_E_HIP;
   int64_t st = 0;
   if (hipMemcpy(&st, out->counts + 3, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) return TPCX_E_HIP;
-  return st ? TPCX_E_CAPACITY : TPCX_OK;
+  if (st & (TPCX_ST_START_OVERFLOW | TPCX_ST_TRACK_OVERFLOW | TPCX_ST_HIT_OVERFLOW)) return TPCX_E_CAPACITY;
+  return (st & TPCX_ST_NONFINITE) ? TPCX_E_INPUT : TPCX_OK;
 }
 
 
@@ -617,14 +638,7 @@ tpcx_status tpcx_refit(tpcx_ctx* c, const tpcx_refit_in* in, const float* theta,
                        int32_t* ok, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!refit_args_ok(c, in) || (in->n_tracks > 0 && (!chi2 || !ok))) return TPCX_E_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
-  // the hit count is the last offset; it lives on the device
-  int64_t n_hits = 0;
-  if (in->n_tracks > 0 &&
-      hipMemcpyAsync(&n_hits, in->hit_begin + in->n_tracks, sizeof n_hits, hipMemcpyDeviceToHost,
-                     stream) != hipSuccess)
-    return TPCX_E_HIP;
-  if (in->n_tracks > 0 && hipStreamSynchronize(stream) != hipSuccess) return TPCX_E_HIP;
-  const RefitLayout L = carve_refit(ws, in->n_tracks, n_hits);
+  const RefitLayout L = carve_refit(ws, in->n_tracks, in->n_hits);
   if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   if (in->n_tracks == 0) return TPCX_OK;
   const RefitIn rv = refit_view(c, in);
@@ -644,20 +658,17 @@ tpcx_status tpcx_refit_backward(tpcx_ctx* c, const tpcx_refit_in* in, const floa
                                 float* grad_theta, void* ws, size_t ws_bytes, hipStream_t stream) {
   if (!refit_args_ok(c, in) || !grad_theta || (in->n_tracks > 0 && !dL_dchi2)) return TPCX_E_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
-  int64_t n_hits = 0;
-  if (in->n_tracks > 0 &&
-      (hipMemcpyAsync(&n_hits, in->hit_begin + in->n_tracks, sizeof n_hits, hipMemcpyDeviceToHost,
-                      stream) != hipSuccess ||
-       hipStreamSynchronize(stream) != hipSuccess))
-    return TPCX_E_HIP;
-  const RefitLayout L = carve_refit(ws, in->n_tracks, n_hits);
+  const RefitLayout L = carve_refit(ws, in->n_tracks, in->n_hits);
   if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   hipLaunchKernelGGL(k_fill_i64, dim3(64), dim3(256), 0, stream, L.ws.acc, int64_t(kMapNCoef),
                      int64_t(0));
   if (in->n_tracks > 0) {
     const size_t win_bytes = sizeof(long long) * kMapComp * kWinPhi * kMapNR * kMapNZ;
-    hipLaunchKernelGGL(k_refit_bwd, dim3(blocks_for(in->n_tracks, kRefitBlock)), dim3(kRefitBlock),
-                       win_bytes, stream, refit_view(c, in), c->dp, L.ws, dL_dchi2, L.ok);
+    const RefitIn rv = refit_view(c, in);
+    hipLaunchKernelGGL(k_refit_bwd_sweep, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream,
+                       rv, c->dp, L.ws, dL_dchi2, L.ok);
+    hipLaunchKernelGGL(k_refit_bwd_scatter, dim3(blocks_for(in->n_tracks, kScatterTracks)),
+                       dim3(kRefitBlock), win_bytes, stream, rv, L.ws);
   }
   hipLaunchKernelGGL(k_grad_finalize, dim3((kMapNCoef + 255) / 256), dim3(256), 0, stream, L.ws.acc,
                      grad_theta);
@@ -680,7 +691,8 @@ tpcx_status tpcx_track_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws, s
                                const tpcx_batch_refit* refit, hipStream_t stream) {
   tpcx_status st = check_track_args(c, in, ws, cap_start, out);
   if (st != TPCX_OK) return st;
-  if (refit && (refit->min_hits < 2 || !refit->unit_alpha || !refit->chi2 || !refit->ok))
+  if (refit && (refit->min_hits < 2 || !refit->unit_alpha || !refit->chi2 || !refit->ok ||
+                (refit->map_z_fixed != 0 && refit->map_z_fixed != 1) || !std::isfinite(refit->map_z)))
     return TPCX_E_ARG;
   if (!stream) return TPCX_E_ARG;  // the legacy default stream cannot be captured
   const int64_t N = in->n_clusters;
@@ -865,6 +877,114 @@ tpcx_status tpcx_timing_read(tpcx_ctx* c, float* ms_host, int32_t* n_calls) {
   return TPCX_OK;
 }
 
+size_t tpcx_fit_workspace_bytes(const tpcx_ctx* c, int64_t n_hits) {
+  if (!c || n_hits < 0) return 0;
+  Carver cv{nullptr};
+  cv.take<float4>(n_hits);
+  return cv.off;
+}
+
+tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* fp, const tpcx_fit_out* out,
+                     void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!c || !in || !fp || !out || in->n_tracks < 0 || in->n_hits < 0) return TPCX_E_ARG;
+  if (in->n_tracks > 0 && (!in->hit_begin || !in->seed || !in->x_ref || !out->param || !out->cov ||
+                           !out->chi2 || !out->x_out || !out->n_kept || !out->ok))
+    return TPCX_E_ARG;
+  if (in->n_hits > 0 && (!in->hit_id || !in->hit_row || !in->y || !in->z || !out->reject)) return TPCX_E_ARG;
+  if (!(fp->chi2_cut >= 0.0f) || !(fp->var_s > 0.0f) || !(fp->var_t > 0.0f) || !(fp->var_w > 0.0f))
+    return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  Carver cv{static_cast<char*>(ws)};
+  auto* rec = cv.take<float4>(in->n_hits);
+  if (!ws || ws_bytes < cv.off) return TPCX_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
+  if (in->n_tracks == 0) return TPCX_OK;
+  FitIn fi;
+  fi.n_tracks = in->n_tracks;
+  fi.hit_begin = in->hit_begin;
+  fi.hit_id = in->hit_id;
+  fi.hit_row = in->hit_row;
+  fi.seed = in->seed;
+  fi.x_ref = in->x_ref;
+  fi.y = in->y;
+  fi.z = in->z;
+  fi.row_x = c->d_row_x;
+  FitOut fo;
+  fo.param = out->param;
+  fo.cov = out->cov;
+  fo.chi2 = out->chi2;
+  fo.x_out = out->x_out;
+  fo.n_kept = out->n_kept;
+  fo.ok = out->ok;
+  fo.reject = out->reject;
+  const FitConsts f{fp->chi2_cut, fp->var_s, fp->var_t, fp->var_w};
+  hipLaunchKernelGGL(k_fit, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream, fi, c->dp, f, rec, fo);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
+size_t tpcx_select_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_clusters) {
+  if (!c || n_units < 1 || n_clusters < 0) return 0;
+  Carver cv{nullptr};
+  cv.take<unsigned long long>(n_clusters);
+  cv.take<int64_t>(n_units);
+  return cv.off;
+}
+
+tpcx_status tpcx_select(tpcx_ctx* c, const tpcx_tracks* tracks, int32_t n_units, int64_t n_clusters,
+                        int32_t shared_num, int32_t shared_den, uint8_t* keep, int32_t* assign,
+                        int64_t* sel_counts, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!c || !tracks || !tracks->counts || n_units < 1 || n_clusters < 0 ||
+      n_clusters >= (int64_t(1) << 31) || shared_num < 0 || shared_den < 1 || !sel_counts ||
+      tracks->cap_tracks < 0 || tracks->cap_hits < 0)
+    return TPCX_E_ARG;
+  if (tracks->cap_tracks > 0 && (!keep || !tracks->unit || !tracks->n_hits || !tracks->hit_begin ||
+                                 !tracks->chi2 || !tracks->ndf))
+    return TPCX_E_ARG;
+  if (tracks->cap_hits > 0 && !tracks->hit_id) return TPCX_E_ARG;
+  if (n_clusters > 0 && !assign) return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  Carver cv{static_cast<char*>(ws)};
+  auto* owner = cv.take<unsigned long long>(n_clusters);
+  auto* first = cv.take<int64_t>(n_units);
+  if (!ws || ws_bytes < cv.off) return TPCX_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
+  SelectIn in;
+  in.cap_tracks = tracks->cap_tracks;
+  in.counts = tracks->counts;
+  in.unit = tracks->unit;
+  in.n_hits = tracks->n_hits;
+  in.hit_begin = tracks->hit_begin;
+  in.hit_id = tracks->hit_id;
+  in.chi2 = tracks->chi2;
+  in.ndf = tracks->ndf;
+  const int grid_t = int(std::max<int64_t>(1, std::min<int64_t>(blocks_for(tracks->cap_tracks, 256),
+                                                                 int64_t(8) * c->n_cu)));
+  const int grid_c = int(std::max<int64_t>(1, std::min<int64_t>(blocks_for(n_clusters, 256),
+                                                                 int64_t(16) * c->n_cu)));
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, sel_counts, int64_t(2), int64_t(0));
+  if (tracks->cap_tracks > 0)
+    hipLaunchKernelGGL(k_select_clear, dim3(grid_t), dim3(256), 0, stream, tracks->cap_tracks, keep);
+  if (n_clusters > 0) {
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_c), dim3(256), 0, stream,
+                       reinterpret_cast<int64_t*>(owner), n_clusters, int64_t(0));
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_c), dim3(256), 0, stream, assign, n_clusters, -1);
+  }
+  if (tracks->cap_tracks == 0 || n_clusters == 0) return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+  hipLaunchKernelGGL(k_select_first, dim3(grid_t), dim3(256), 0, stream, in, first, sel_counts + 1);
+  hipLaunchKernelGGL(k_select_claim, dim3(grid_t), dim3(256), 0, stream, in, first,
+                     static_cast<const uint8_t*>(nullptr), owner);
+  hipLaunchKernelGGL(k_select_decide, dim3(grid_t), dim3(256), 0, stream, in, first, owner, shared_num,
+                     shared_den, keep, sel_counts);
+  hipLaunchKernelGGL(k_fill_i64, dim3(grid_c), dim3(256), 0, stream, reinterpret_cast<int64_t*>(owner),
+                     n_clusters, int64_t(0));
+  hipLaunchKernelGGL(k_select_claim, dim3(grid_t), dim3(256), 0, stream, in, first,
+                     static_cast<const uint8_t*>(keep), owner);
+  hipLaunchKernelGGL(k_select_assign, dim3(grid_t), dim3(256), 0, stream, in, first, keep, owner, assign);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
 const char* tpcx_strerror(tpcx_status s) {
   switch (s) {
     case TPCX_OK: return "ok";
@@ -872,6 +992,7 @@ const char* tpcx_strerror(tpcx_status s) {
     case TPCX_E_CAPACITY: return "a device capacity was exceeded; counts hold the required sizes";
     case TPCX_E_HIP: return "HIP runtime error";
     case TPCX_E_DEVICE: return "device is not gfx950";
+    case TPCX_E_INPUT: return "some cluster coordinates are not finite (those clusters were ignored)";
     default: return "unknown status";
   }
 }

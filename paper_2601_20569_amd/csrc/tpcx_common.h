@@ -8,6 +8,9 @@ namespace tpcx {
 
 constexpr int kWave = 64;
 
+// Capacity-overflow bits of the status word (counts[3]): starts, tracklets, hits.
+constexpr int64_t kStOverflow = 7;
+
 // Method constants in the precision the kernels compute in.
 struct DevParams {
   float kappa;   // d sin(phi) / dx per unit of q/pT

@@ -13,12 +13,20 @@
 
 namespace tpcx {
 
-// State at plane x: (y, z, s = sin(phi), t = dz/ds, w = q/pT), covariance
-// blocks (y, s, w) and (z, t).
+// State at plane x: (y, z, s = sin(phi), t = dz/ds, w = q/pT) and the
+// covariance blocks (y, s, w) and (z, t), each as U D U^T with U unit upper
+// triangular and D diagonal:
+//   (y, s, w): U = [[1, uys, uyw], [0, 1, usw], [0, 0, 1]], D = diag(dy, ds, dw)
+//   (z, t):    U = [[1, uzt], [0, 1]],                      D = diag(dz, dt)
+// The transport multiplies U by the unit upper triangular Jacobian; the
+// measurement update (Bierman's scalar form) forms no difference of nearly
+// equal covariances, which the form C - K H C does in float when the
+// predicted variance of y is far above the cluster error.  In the tracklet
+// constructor y and z are relative to the seed cluster.
 struct KState {
   float x, y, z, s, t, w;
-  float cyy, csy, css, cwy, cws, cww;
-  float czz, ctz, ctt;
+  float uys, uyw, usw, dy, ds, dw;
+  float uzt, dz, dt;
 };
 
 // asin(u)/u to third order in u^2 (u <= 0.1 keeps the dropped term < 5e-8).
@@ -84,21 +92,11 @@ __device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParam
   const float a = dx * ((2.0f * cc + ss * (r0 + r1)) * icc2);
   const float e = -(p.kappa * dx);
   const float b = (dx * e) * ((cc + ss * r1) * icc2);
-  const float Py = (q.cyy + a * q.csy) + b * q.cwy;
-  const float Ps = (q.csy + a * q.css) + b * q.cws;
-  const float Pw = (q.cwy + a * q.cws) + b * q.cww;
-  const float Qy = q.csy + e * q.cwy;
-  const float Qs = q.css + e * q.cws;
-  const float Qw = q.cws + e * q.cww;
-  q.cyy = (Py + a * Ps) + b * Pw;
-  q.csy = (Qy + a * Qs) + b * Qw;
-  q.cwy = Pw;
-  q.css = Qs + e * Qw;
-  q.cws = Qw;
-  const float Rz = q.czz + dS * q.ctz;
-  const float Rt = q.ctz + dS * q.ctt;
-  q.czz = Rz + dS * Rt;
-  q.ctz = Rt;
+  // U' = J U with J = [[1, a, b], [0, 1, e], [0, 0, 1]] and [[1, dS], [0, 1]]
+  q.uyw = (q.uyw + a * q.usw) + b;
+  q.uys = q.uys + a;
+  q.usw = q.usw + e;
+  q.uzt = q.uzt + dS;
   q.y = q.y + dy;
   q.z = q.z + q.t * dS;
   q.s = s1;
@@ -109,53 +107,87 @@ __device__ __forceinline__ bool kf_propagate(KState& q, float x1, const DevParam
   return true;
 }
 
-// Kalman update with the cluster (my, mz), given the inverse residual
-// variances iSy = 1/(cyy + sy^2), iSz = 1/(czz + sz^2); returns the chi2.
-__device__ __forceinline__ float kf_update(KState& q, float my, float mz, float iSy, float iSz) {
+// Residual variances of a measurement, S_y = C_yy + sy^2 and S_z = C_zz +
+// sz^2, as sums of non-negative terms of the factorisation, with the partial
+// sums the update needs (v = D U^T h for h selecting y, resp. z).
+struct KInnov {
+  float v2, v3, a1, a2, sy;
+  float vz, z1, sz;
+};
+
+__device__ __forceinline__ KInnov kf_innov(const KState& q, const DevParams& p) {
+  KInnov n;
+  n.v2 = q.ds * q.uys;
+  n.v3 = q.dw * q.uyw;
+  n.a1 = p.sy2 + q.dy;
+  n.a2 = n.a1 + n.v2 * q.uys;
+  n.sy = n.a2 + n.v3 * q.uyw;
+  n.vz = q.dt * q.uzt;
+  n.z1 = p.sz2 + q.dz;
+  n.sz = n.z1 + n.vz * q.uzt;
+  return n;
+}
+
+// Kalman update with the cluster (my, mz) (in the state's coordinates),
+// given the partial sums of kf_innov and iSy = 1/S_y, iSz = 1/S_z; returns
+// the chi2.  Bierman's scalar update, per block: D' = (dy sy^2/a1, ds a1/a2,
+// dw a2/S_y), uys' = uys sy^2/a1, uyw' = uyw sy^2/a2, usw' = usw - v2 uyw/a2,
+// gain S_y^-1 (C_yy, C_sy, C_wy) from the prior's first column.
+template <bool Fast = false>
+__device__ __forceinline__ float kf_update(KState& q, float my, float mz, const KInnov& n, float iSy,
+                                           float iSz, const DevParams& p) {
   const float ry = my - q.y;
   const float rz = mz - q.z;
   const float chi2 = (ry * ry) * iSy + (rz * rz) * iSz;
-  const float k0 = q.cyy * iSy, k1 = q.csy * iSy, k2 = q.cwy * iSy;
-  q.y = q.y + k0 * ry;
-  q.s = q.s + k1 * ry;
-  q.w = q.w + k2 * ry;
-  const float cyy = q.cyy, csy = q.csy, cwy = q.cwy;
-  q.cyy = cyy - k0 * cyy;
-  q.csy = csy - k1 * cyy;
-  q.cwy = cwy - k2 * cyy;
-  q.css = q.css - k1 * csy;
-  q.cws = q.cws - k2 * csy;
-  q.cww = q.cww - k2 * cwy;
-  const float kz0 = q.czz * iSz, kz1 = q.ctz * iSz;
-  q.z = q.z + kz0 * rz;
-  q.t = q.t + kz1 * rz;
-  const float czz = q.czz, ctz = q.ctz;
-  q.czz = czz - kz0 * czz;
-  q.ctz = ctz - kz1 * czz;
-  q.ctt = q.ctt - kz1 * ctz;
+  const float i1 = k_rcp<Fast>(n.a1);
+  const float i2 = k_rcp<Fast>(n.a2);
+  const float b1 = (q.dy + q.uys * n.v2) + q.uyw * n.v3;
+  const float b2 = n.v2 + q.usw * n.v3;
+  const float g = ry * iSy;
+  q.y = q.y + b1 * g;
+  q.s = q.s + b2 * g;
+  q.w = q.w + n.v3 * g;
+  const float f1 = p.sy2 * i1;
+  q.usw = q.usw - n.v2 * (q.uyw * i2);
+  q.uyw = q.uyw * (p.sy2 * i2);
+  q.uys = q.uys * f1;
+  q.dw = q.dw * (n.a2 * iSy);
+  q.ds = q.ds * (n.a1 * i2);
+  q.dy = q.dy * f1;
+  const float j1 = k_rcp<Fast>(n.z1);
+  const float bz1 = q.dz + q.uzt * n.vz;
+  const float gz = rz * iSz;
+  q.z = q.z + bz1 * gz;
+  q.t = q.t + n.vz * gz;
+  const float fz = p.sz2 * j1;
+  q.uzt = q.uzt * fz;
+  q.dt = q.dt * (n.z1 * iSz);
+  q.dz = q.dz * fz;
   return chi2;
 }
 
 // The search box of one lane: z bins zb0..zb1 (taken in pairs), y bins
 // yb0..yb1, in the row whose first bin is `base` (ny y bins per z bin).  The
-// box |dy| <= 4 sqrt(Sy), |dz| <= 4 sqrt(Sz) is widened so that it holds
-// every cluster the float chi2 cut can accept; the hardware square root
-// (within 1 ulp) is enough, the 1e-3 relative margin covers its error.
+// box |dy| <= 4 sqrt(Sy), |dz| <= 4 sqrt(Sz) around the predicted position
+// (cy, cz) is widened so that it holds every cluster the float chi2 cut can
+// accept; the hardware square root (within 1 ulp) is enough, the 1e-3
+// relative margin covers its error and the rounding of (cy, cz).
 struct SearchBox {
   int64_t base;
   int ny, zb0, zb1, yb0, yb1;
 };
 
-__device__ __forceinline__ SearchBox kf_box(const RowView& rv, const KState& q, const DevParams& p) {
-  const float hy = __builtin_amdgcn_sqrtf(p.chi2max * (q.cyy + p.sy2)) * 1.001f + box_pad(q.y);
-  const float hz = __builtin_amdgcn_sqrtf(p.chi2max * (q.czz + p.sz2)) * 1.001f + box_pad(q.z);
+__device__ __forceinline__ SearchBox kf_box(const RowView& rv, float cy, float cz, const KInnov& n,
+                                            const DevParams& p) {
+  const float hy = __builtin_amdgcn_sqrtf(p.chi2max * n.sy) * 1.001f + box_pad(cy);
+  const float hz = __builtin_amdgcn_sqrtf(p.chi2max * n.sz) * 1.001f + box_pad(cz);
   SearchBox b;
   b.base = rv.base;
   b.ny = rv.ri.ny;
-  b.zb0 = rv.zbin(q.z - hz);
-  b.zb1 = rv.zbin(q.z + hz);
-  b.yb0 = rv.ybin(q.y - hy);
-  b.yb1 = rv.ybin(q.y + hy);
+  b.zb0 = rv.zbin(cz - hz);
+  b.zb1 = rv.zbin(cz + hz);
+  b.yb0 = rv.ybin(cy - hy);
+  b.yb1 = rv.ybin(cy + hy);
   return b;
 }
 
@@ -178,9 +210,9 @@ __device__ __forceinline__ uint32_t chi2_key(float ch) {
 // be called with all 64 lanes active; `sbest` and `scoord` are the
 // wavefront's 64 LDS slots.
 __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox& b, bool searching,
-                                                  float qy, float qz, float iSy, float iSz,
-                                                  float chi2max, uint64_t* sbest, float2* scoord,
-                                                  float* out_my, float* out_mz) {
+                                                  float oy, float oz, float qy, float qz, float iSy,
+                                                  float iSz, float chi2max, uint64_t* sbest,
+                                                  float2* scoord, float* out_my, float* out_mz) {
   const int lane = lane_id();
   sbest[lane] = ~0ull;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -228,9 +260,12 @@ __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox
       float4 ma = make_float4(0.0f, 0.0f, 0.0f, 0.0f), mb = ma;
       if (va) ma = g.pts[pa];
       if (vb) mb = g.pts[pb];
-      const float rya = ma.x - __shfl(qy, oa, kWave), rza = ma.y - __shfl(qz, oa, kWave);
+      // residuals in the owner's coordinates: (cluster - origin) - state
+      const float rya = (ma.x - __shfl(oy, oa, kWave)) - __shfl(qy, oa, kWave);
+      const float rza = (ma.y - __shfl(oz, oa, kWave)) - __shfl(qz, oa, kWave);
       const float cha = (rya * rya) * __shfl(iSy, oa, kWave) + (rza * rza) * __shfl(iSz, oa, kWave);
-      const float ryb = mb.x - __shfl(qy, ob, kWave), rzb = mb.y - __shfl(qz, ob, kWave);
+      const float ryb = (mb.x - __shfl(oy, ob, kWave)) - __shfl(qy, ob, kWave);
+      const float rzb = (mb.y - __shfl(oz, ob, kWave)) - __shfl(qz, ob, kWave);
       const float chb = (ryb * ryb) * __shfl(iSy, ob, kWave) + (rzb * rzb) * __shfl(iSz, ob, kWave);
       const bool oka = va && cha <= chi2max, okb = vb && chb <= chi2max;
       const uint64_t ka = (uint64_t(chi2_key(cha)) << 32) | uint32_t(__float_as_int(ma.z));
@@ -254,7 +289,8 @@ __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox
 }
 
 // Per-start-hit results before compaction.  One 128-byte record per slot:
-//   words 0-15  x_ref, y, z, s, t, w, cyy, csy, css, cwy, cws, cww, czz, ctz, ctt, chi2 (float)
+//   words 0-15  x_ref, y, z, s, t, w, uys, uyw, usw, dy, ds, dw, uzt, dz, dt, chi2 (float;
+//               y, z absolute, the covariance factorised as in KState)
 //   words 16-19 n, n_up, flags, unit (int)
 //   words 20-24 mask of the rows with an attached cluster (rows 0..159)
 // and `stride` hit slots with the cluster ids in attachment order: the
@@ -327,6 +363,7 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     nbuf = 0;
   };
   KState q{}, best{};
+  float oy = 0.0f, oz = 0.0f;  // origin of the state's y and z: the seed cluster
   float c_prev = 0.0f, r_prev = 0.0f, chi2 = 0.0f;
   bool cached = false;
   int kbase = 0, r0 = 0, row = 0, best_row = 0, phase = kIdle, misses = 0, n_up = 0, n_dn = 0,
@@ -395,23 +432,27 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
           const float dx = in.row_x[r0 + 1] - in.row_x[r0];
           const float dy = P1.x - P0.x;
           const float dz = P1.y - P0.y;
-          const float idl = 1.0f / sqrtf(dx * dx + dy * dy);
+          const float dl = sqrtf(dx * dx + dy * dy);
+          const float idl = 1.0f / dl;
           const float idl2 = idl * idl;
+          oy = P1.x;
+          oz = P1.y;
           q.x = in.row_x[r0 + 1];
-          q.y = P1.x;
-          q.z = P1.y;
+          q.y = 0.0f;
+          q.z = 0.0f;
           q.s = dy * idl;
           q.t = dz * idl;
           q.w = 0.0f;
-          q.cyy = p.sy2;
-          q.csy = p.sy2 * idl;
-          q.css = (p.sy2 + p.sy2) * idl2;
-          q.cwy = 0.0f;
-          q.cws = 0.0f;
-          q.cww = p.cww0;
-          q.czz = p.sz2;
-          q.ctz = p.sz2 * idl;
-          q.ctt = (p.sz2 + p.sz2) * idl2;
+          // C_yy = sy^2, C_sy = sy^2/dl, C_ss = 2 sy^2/dl^2 (z, t alike), var(q/pT) = cww0
+          q.uys = dl * 0.5f;
+          q.uyw = 0.0f;
+          q.usw = 0.0f;
+          q.dy = p.sy2 * 0.5f;
+          q.ds = (p.sy2 + p.sy2) * idl2;
+          q.dw = p.cww0;
+          q.uzt = dl * 0.5f;
+          q.dz = p.sz2 * 0.5f;
+          q.dt = (p.sz2 + p.sz2) * idl2;
           cached = false;
           chi2 = 0.0f;
 #pragma unroll
@@ -439,6 +480,7 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     bool finish = false, to_descend = false, attach = false, searching = false;
     int target = 0;
     float iSy = 0.0f, iSz = 0.0f, my = 0.0f, mz = 0.0f;
+    KInnov inn{};
     int32_t c = -1, chain_next = -1;
     SearchBox box{0, 1, 0, -1, 0, -1};
     if (live) {
@@ -468,8 +510,9 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
         else
           to_descend = true;
       } else {
-        iSy = 1.0f / (q.cyy + p.sy2);
-        iSz = 1.0f / (q.czz + p.sz2);
+        inn = kf_innov(q, p);
+        iSy = 1.0f / inn.sy;
+        iSz = 1.0f / inn.sz;
         attach = true;
         if (phase == kChain) {
           const float4 P = in.pts[next_c];
@@ -479,14 +522,14 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
           chain_next = __float_as_int(P.w);
         } else {
           searching = true;
-          box = kf_box(rv, q, p);
+          box = kf_box(rv, oy + q.y, oz + q.z, inn, p);
         }
       }
     }
     if (__ballot(searching) != 0ull) {
       float sy = 0.0f, sz = 0.0f;
-      const int32_t sc = kf_search_wave(g, box, searching, q.y, q.z, iSy, iSz, p.chi2max, sbest[wv],
-                                        scoord[wv], &sy, &sz);
+      const int32_t sc = kf_search_wave(g, box, searching, oy, oz, q.y, q.z, iSy, iSz, p.chi2max,
+                                        sbest[wv], scoord[wv], &sy, &sz);
       if (searching) {
         c = sc;
         my = sy;
@@ -496,7 +539,7 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     if (attach) {
       row = target;
       if (c >= 0) {
-        chi2 = chi2 + kf_update(q, my, mz, iSy, iSz);
+        chi2 = chi2 + kf_update(q, my - oy, mz - oz, inn, iSy, iSz, p);
         cached = false;
         if (phase == kDown)
           ++n_dn;
@@ -528,14 +571,14 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     if (finish) {
       flush();
       uint4* rec = reinterpret_cast<uint4*>(out.rec + slot * kRecWords);
-      rec[0] = make_uint4(__float_as_uint(best.x), __float_as_uint(best.y), __float_as_uint(best.z),
-                          __float_as_uint(best.s));
-      rec[1] = make_uint4(__float_as_uint(best.t), __float_as_uint(best.w), __float_as_uint(best.cyy),
-                          __float_as_uint(best.csy));
-      rec[2] = make_uint4(__float_as_uint(best.css), __float_as_uint(best.cwy),
-                          __float_as_uint(best.cws), __float_as_uint(best.cww));
-      rec[3] = make_uint4(__float_as_uint(best.czz), __float_as_uint(best.ctz),
-                          __float_as_uint(best.ctt), __float_as_uint(chi2));
+      rec[0] = make_uint4(__float_as_uint(best.x), __float_as_uint(oy + best.y),
+                          __float_as_uint(oz + best.z), __float_as_uint(best.s));
+      rec[1] = make_uint4(__float_as_uint(best.t), __float_as_uint(best.w), __float_as_uint(best.uys),
+                          __float_as_uint(best.uyw));
+      rec[2] = make_uint4(__float_as_uint(best.usw), __float_as_uint(best.dy),
+                          __float_as_uint(best.ds), __float_as_uint(best.dw));
+      rec[3] = make_uint4(__float_as_uint(best.uzt), __float_as_uint(best.dz),
+                          __float_as_uint(best.dt), __float_as_uint(chi2));
       rec[4] = make_uint4(uint32_t(n_up + n_dn), uint32_t(n_up), uint32_t(flags), uint32_t(kbase / R));
       rec[5] = make_uint4(rmask[wv][0][lane], rmask[wv][1][lane], rmask[wv][2][lane], rmask[wv][3][lane]);
       rec[6] = make_uint4(rmask[wv][4][lane], 0u, 0u, 0u);
@@ -677,11 +720,21 @@ __global__ void __launch_bounds__(kKeepBlock) k_keep_write(
         pp[2] = __uint_as_float(a0.w);
         pp[3] = __uint_as_float(a1.x);
         pp[4] = __uint_as_float(a1.y);
-        const float cyy = __uint_as_float(a1.z), csy = __uint_as_float(a1.w);
-        const float css = __uint_as_float(a2.x), cwy = __uint_as_float(a2.y);
-        const float cws = __uint_as_float(a2.z), cww = __uint_as_float(a2.w);
-        const float czz = __uint_as_float(a3.x), ctz = __uint_as_float(a3.y);
-        const float ctt = __uint_as_float(a3.z);
+        // covariance blocks multiplied out: C = U D U^T
+        const float uys = __uint_as_float(a1.z), uyw = __uint_as_float(a1.w);
+        const float usw = __uint_as_float(a2.x), dy = __uint_as_float(a2.y);
+        const float ds = __uint_as_float(a2.z), dw = __uint_as_float(a2.w);
+        const float uzt = __uint_as_float(a3.x), dz = __uint_as_float(a3.y);
+        const float dt = __uint_as_float(a3.z);
+        const float cww = dw;
+        const float cws = usw * dw;
+        const float cwy = uyw * dw;
+        const float css = ds + usw * cws;
+        const float csy = uys * ds + uyw * cws;
+        const float cyy = (dy + uys * (uys * ds)) + uyw * cwy;
+        const float ctt = dt;
+        const float ctz = uzt * dt;
+        const float czz = dz + uzt * ctz;
         const float cv[15] = {cyy, 0.0f, czz, csy, 0.0f, css, 0.0f, ctz,
                               0.0f, ctt, cwy, 0.0f, cws, 0.0f, cww};
         for (int j = 0; j < 15; ++j) o.cov[ti * 15 + j] = cv[j];

@@ -3,7 +3,7 @@
 Clusters whose decision lies within eps of a threshold in double
 (oracle.nf_margins: the neighbour finder's window tests, D cut and best-vs-
 second gap; with constructor=True also the tracklet constructor's chi2 cut and
-best-vs-second gap) are re-drawn -- moved by a seeded Gaussian jitter of
+propagation guards, and its best-vs-second chi2 gap within 1e-3) are re-drawn -- moved by a seeded Gaussian jitter of
 0.01 cm, a sub-stream per (seed, round) -- until none is left (at most
 max_rounds rounds).  On such inputs the float and double decisions agree.
 """

@@ -176,3 +176,23 @@ def test_gpu_links_equal_double_oracle_on_margin_clean_input():
     for k in ("link_up", "link_down", "clean_up", "clean_down"):
         np.testing.assert_array_equal(gpu[k], ref[k], err_msg=k)
     np.testing.assert_array_equal(gpu["starts"], ref["starts"].astype(np.int32))
+
+
+def test_non_finite_clusters_are_reported_and_join_nothing():
+    """NaN and infinite coordinates: the status word carries the non-finite
+    bit, and everything else equals the oracle bit for bit."""
+    from types import SimpleNamespace
+    cs = synth.single_sector(seed=1)
+    rng = np.random.default_rng(4)
+    y, z = cs.y.copy(), cs.z.copy()
+    y[rng.choice(cs.n_clusters, 20, replace=False)] = np.nan
+    z[rng.choice(cs.n_clusters, 20, replace=False)] = np.inf
+    z[rng.choice(cs.n_clusters, 20, replace=False)] = np.nan
+    bad = SimpleNamespace(n_units=1, row_begin=cs.row_begin, y=y, z=z, n_clusters=cs.n_clusters)
+    print("case: single sector with 60 non-finite clusters", flush=True)
+    ref = oracle.track(bad)
+    gpu = run_gpu(bad, make_tracker())
+    assert gpu["status"] == 8
+    k, gi = compare_decisions(gpu, ref)
+    np.testing.assert_array_equal(gpu["param"].astype(np.float64), k["param"])
+    np.testing.assert_array_equal(gpu["chi2"].astype(np.float64), k["chi2"])

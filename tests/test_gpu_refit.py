@@ -60,11 +60,10 @@ def test_refit_chi2_matches_fp64(kind):
     chi2 = job.forward(torch.as_tensor(theta, dtype=torch.float32, device="cuda")).cpu().numpy()
     ok = job.ok[:job.n_tracks].cpu().numpy().astype(bool)
     assert len(chi2) > 1000
-    # a guard may trip on one side only right at its threshold
-    assert (ok == ok_ref).mean() > 0.999
-    both = ok & ok_ref
-    rel = np.abs(chi2[both] - want[both]) / np.maximum(want[both], 1.0)
-    assert rel.max() < 1e-3, rel.max()
+    np.testing.assert_array_equal(ok, ok_ref)
+    rel = np.abs(chi2[ok] - want[ok]) / np.maximum(want[ok], 1.0)
+    print(f"refit: {ok.sum()} tracks, max rel {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1e-3, rel.max()
 
 
 def test_refit_without_map_equals_zero_map():
@@ -130,6 +129,35 @@ def test_autograd_function_uses_the_adjoint():
     (g,) = torch.autograd.grad(loss, theta)
     want = job.backward(ok)
     np.testing.assert_array_equal(g.cpu().numpy(), want.cpu().numpy())
+
+
+def test_autograd_backward_after_another_forward_on_the_job():
+    """Two refit_chi2 nodes on one job, the second forward run before the first
+    node's backward: the first node's gradient is its own theta's, not the
+    workspace's last state."""
+    import torch
+
+    import paper_2601_20569_amd as px
+    cs, tk = _case(n_primaries=800)
+    job, _ = _job(cs, tk)
+    rng = np.random.default_rng(4)
+    t1 = torch.as_tensor(rng.normal(0.0, 0.05, oracle.map_ncoef()), dtype=torch.float32, device="cuda")
+    t2 = torch.as_tensor(rng.normal(0.0, 0.05, oracle.map_ncoef()), dtype=torch.float32, device="cuda")
+    job.forward(t1)
+    ok = job.ok[:job.n_tracks].float().clone()
+    want1 = job.backward(ok).cpu().numpy()
+    job.forward(t2)
+    ok2 = job.ok[:job.n_tracks].float().clone()
+    want2 = job.backward(ok2).cpu().numpy()
+    assert not np.array_equal(want1, want2)
+    a = t1.clone().requires_grad_(True)
+    b = t2.clone().requires_grad_(True)
+    c1 = px.refit_chi2(a, job)
+    c2 = px.refit_chi2(b, job)  # replaces the job's workspace
+    (g1,) = torch.autograd.grad((c1 * ok).sum(), a)
+    np.testing.assert_array_equal(g1.cpu().numpy(), want1)
+    (g2,) = torch.autograd.grad((c2 * ok2).sum(), b)
+    np.testing.assert_array_equal(g2.cpu().numpy(), want2)
 
 
 def test_adjoint_matches_central_differences_of_fp64_refit():

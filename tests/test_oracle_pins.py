@@ -513,9 +513,13 @@ def test_fp32_within_tolerance_of_fp64_replay(c1_res, c1, which):
     rp = oracle.replay(cs, k)
     assert rp["ok"].all()
     np.testing.assert_array_equal(rp["xref"], k["xref"])
-    assert not param_bad(k["param"], rp["param"], rp["cov"]).any()
+    assert not param_bad(k["param"], rp["param"], rp["smax"]).any()
     assert not chi2_bad(k["chi2"], rp["chi2"]).any()
-    assert not cov_bad(k["cov"], rp["cov"]).any()
+    assert not cov_bad(k["cov"], rp["cov"], rp["smax"]).any()
+    # outside the near-guard class the plain bounds hold
+    far = rp["smax"] < 0.95
+    assert not param_bad(k["param"][far], rp["param"][far]).any()
+    assert not cov_bad(k["cov"][far], rp["cov"][far]).any()
 
 
 def test_float_replay_reproduces_constructor_bitwise(c1_res, c1):
@@ -558,3 +562,34 @@ def test_brute_and_indexed_scans_agree_on_dense_rows():
     b = oracle.track(cs, brute=True, units=(0, 3))
     for key in ("link_up", "link_down", "starts", "t_hits", "t_n", "t_param"):
         np.testing.assert_array_equal(a[key], b[key])
+
+
+def _with_coordinates(cs, idx, y=None, z=None):
+    from types import SimpleNamespace
+    yy, zz = cs.y.copy(), cs.z.copy()
+    if y is not None:
+        yy[idx] = y
+    if z is not None:
+        zz[idx] = z
+    return SimpleNamespace(n_units=cs.n_units, row_begin=cs.row_begin, y=yy, z=zz,
+                           n_clusters=cs.n_clusters, unit_sector=getattr(cs, "unit_sector", None))
+
+
+@pytest.mark.parametrize("bad", ["nan_y", "nan_z", "inf_z"])
+def test_non_finite_clusters_join_nothing(bad):
+    """A cluster with a non-finite coordinate passes no window or chi2 test:
+    the result equals that of the same input with the cluster moved far
+    outside every window (both the z-sorted index and the brute scan)."""
+    cs = synth.single_sector(seed=1)
+    idx = np.random.default_rng(3).choice(cs.n_clusters, 40, replace=False)
+    val = {"nan_y": dict(y=np.nan), "nan_z": dict(z=np.nan), "inf_z": dict(z=np.inf)}[bad]
+    a = _with_coordinates(cs, idx, **{k: np.float32(v) for k, v in val.items()})
+    spread = (1e5 * (1.0 + np.arange(len(idx)))).astype(np.float32)  # far apart from each other too
+    far = _with_coordinates(cs, idx, y=spread, z=spread)
+    for brute in (False, True):
+        ra = oracle.track(a, brute=brute)
+        rf = oracle.track(far, brute=brute)
+        for key in ("link_up", "link_down", "clean_up", "clean_down", "starts", "t_hits", "t_n"):
+            np.testing.assert_array_equal(ra[key], rf[key], err_msg=key)
+        np.testing.assert_array_equal(ra["t_param"], rf["t_param"])
+        assert (ra["link_up"][idx] == -1).all() and not np.isin(ra["t_hits"], idx).any()

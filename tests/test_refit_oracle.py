@@ -106,6 +106,124 @@ def test_map_is_linear_in_theta_and_matches_basis():
     assert (oracle.map_eval(None, 100.0, 1.0, 0.0) == 0).all()
 
 
+def _constant_map(comp, value):
+    theta = np.zeros(oracle.map_ncoef())
+    for i in range(NPHI):
+        for j in range(NR):
+            for k in range(NZ):
+                theta[coef(comp, i, j, k)] = value
+    return theta
+
+
+@pytest.mark.parametrize("comp", [0, 1, 2])
+def test_constant_map_components_move_clusters_as_stated(comp):
+    """Away from the r and z ends a constant component d moves a cluster by
+    exactly d: delta r along the radius (the angle is kept), delta r*phi along
+    the tangent (-y, x)/r, i.e. a rotation about the beam axis by atan(d/r)
+    with radius hypot(r, d), delta z along z only."""
+    d = 0.37
+    theta = _constant_map(comp, d)
+    rng = np.random.default_rng(comp)
+    for _ in range(200):
+        sector = int(rng.integers(0, 36))
+        alpha = float(G.sector_alpha(np.array([sector]))[0])
+        x = rng.uniform(100.0, 230.0)
+        y = rng.uniform(-0.17, 0.17) * x
+        z = rng.uniform(-200.0, 200.0)
+        xc, yc, zc = oracle.map_correct(theta, x, y, z, alpha)
+        r, rc = math.hypot(x, y), math.hypot(xc, yc)
+        turn = math.atan2(yc, xc) - math.atan2(y, x)
+        if comp == 0:
+            assert abs(rc - (r + d)) < 1e-9 and abs(turn) < 1e-12 and zc == z
+        elif comp == 1:
+            assert abs(turn - math.atan2(d, r)) < 1e-12 and abs(rc - math.hypot(r, d)) < 1e-9
+            assert zc == z
+        else:
+            assert abs(zc - (z + d)) < 1e-12 and xc == x and yc == y
+
+
+def test_map_is_evaluated_at_the_global_azimuth():
+    """A delta r*phi component present only on the phi nodes around one
+    sector's centre moves that sector's clusters and leaves the opposite
+    sector's alone: the node lookup uses the global azimuth alpha + atan2(y, x)."""
+    theta = np.zeros(oracle.map_ncoef())
+    s_on, s_off = 4, 13
+    a_on = float(G.sector_alpha(np.array([s_on]))[0]) % (2 * math.pi)
+    i0 = int(round(a_on / (2 * math.pi / NPHI)))
+    for i in range(i0 - 4, i0 + 5):
+        for j in range(NR):
+            for k in range(NZ):
+                theta[coef(1, i % NPHI, j, k)] = 0.5
+    for s_, moved in ((s_on, True), (s_off, False)):
+        alpha = float(G.sector_alpha(np.array([s_]))[0])
+        xc, yc, zc = oracle.map_correct(theta, 150.0, 3.0, 20.0, alpha)
+        assert (abs(yc - 3.0) > 0.1) == moved, (s_, xc, yc)
+
+
+def test_time_frame_clusters_need_the_fixed_z_map():
+    """In a time frame the drift coordinate of most clusters lies far outside
+    the map's z nodes (collision times shift it by up to thousands of cm), so
+    at the measured z the map is zero for most of them; evaluated at a fixed
+    z (the batched refit's time-frame mode) it acts on every cluster."""
+    cs = synth.timeframe_slice(seed=3005, n_collisions=128, mean_primaries=60.0, truth=False)
+    rng = np.random.default_rng(2)
+    theta = rng.normal(0.0, 0.05, oracle.map_ncoef())
+    rows = cs.row_of()
+    units = cs.unit_of()
+    pick = rng.choice(cs.n_clusters, 400, replace=False)
+    at_z = at_0 = 0
+    for c in pick:
+        x = float(G.row_x()[rows[c]])
+        y = float(cs.y[c])
+        alpha = float(G.sector_alpha(cs.unit_sector[units[c]:units[c] + 1])[0])
+        phi = alpha + math.atan2(y, x)
+        r = math.hypot(x, y)
+        at_z += np.any(oracle.map_eval(theta, r, phi, float(cs.z[c])) != 0.0)
+        at_0 += np.any(oracle.map_eval(theta, r, phi, 0.0) != 0.0)
+    assert at_0 == len(pick)
+    assert at_z < 0.2 * len(pick), at_z
+
+
+def test_tangential_and_z_maps_undo_a_known_displacement():
+    """Exact helices whose clusters were moved by -b(r) along the tangent (a
+    rotation about the beam axis by -b(r)/r) and by -b(r) along z, with b a
+    bump of 0.3 cm times the cubic B-spline of the r node at 205 cm (a shape
+    the track cannot absorb): the refit through the map holding +0.3 cm on that
+    node in the delta r*phi and delta z components recovers chi2 ~ 0, while no
+    map or the opposite sign leaves a large chi2."""
+    from types import SimpleNamespace
+    cs = synth.exact_tracks(71, n_tracks=10, pt_range=(1.0, 10.0), eta_range=(0.05, 0.5))
+    tk = truth_tracklets(cs)
+    j0, amp = 12, 0.3
+    x = G.row_x()[cs.row_of()].astype(np.float64)
+    y = cs.y.astype(np.float64)
+    r = np.hypot(x, y)
+    tt = np.abs((r - R_NODES[j0]) / 10.0)
+    bump = amp * np.where(tt < 1, (4 - 6 * tt ** 2 + 3 * tt ** 3) / 6, np.where(tt < 2, (2 - tt) ** 3 / 6, 0.0))
+    # rotate about the beam axis by -bump/r, then back onto the row plane
+    y_m = x * np.tan(np.arctan2(y, x) - bump / r)
+    moved = SimpleNamespace(**{**cs.__dict__, "y": y_m.astype(np.float32),
+                                "z": (cs.z.astype(np.float64) - bump).astype(np.float32)})
+    fix = np.zeros(oracle.map_ncoef())
+    for i in range(NPHI):
+        for k in range(NZ):
+            fix[coef(1, i, j0, k)] = amp
+            fix[coef(2, i, j0, k)] = amp
+    c_none, ok0 = oracle.refit(moved, tk)
+    c_fix, ok1 = oracle.refit(moved, tk, fix)
+    c_bad, ok2 = oracle.refit(moved, tk, -fix)
+    # tracks that cross the bump (reach past its node)
+    reach = np.array([r[tk["hits"][tk["hit_begin"][t]:tk["hit_begin"][t + 1]]].max() > R_NODES[j0] + 10.0
+                      for t in range(len(tk["n"]))])
+    good = ok0 & ok1 & ok2 & reach
+    assert good.sum() >= 6
+    ndf = 2 * tk["n"][good] - 5
+    print("chi2/ndf without map", c_none[good] / ndf, "with", c_fix[good] / ndf, "opposite", c_bad[good] / ndf)
+    assert (c_none[good] / ndf > 0.1).all(), c_none[good] / ndf
+    assert (c_fix[good] < 1e-2 * c_none[good]).all(), c_fix[good] / ndf
+    assert (c_bad[good] > 3.0 * c_none[good]).all()
+
+
 def truth_tracklets(cs):
     """One tracklet per particle: all its clusters sorted by row, seeded with
     the truth direction and curvature at the innermost cluster."""
