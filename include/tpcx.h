@@ -157,6 +157,26 @@ tpcx_status tpcx_track(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t 
                        int64_t cap_start, const tpcx_tracks* out, const tpcx_debug* dbg,
                        hipStream_t stream);
 
+/* Workspace of tpcx_track_static: 64 MiB per device. */
+#define TPCX_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* tpcx_track for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace is a library-owned array of TPCX_STATIC_SCRATCH_BYTES on each
+ * device (reserved when the library's code is loaded on the device, held
+ * until the process ends; its address is resolved in tpcx_create), so the
+ * call allocates nothing; inputs, outputs and results are those of
+ * tpcx_track.  Returns TPCX_E_ARG, with nothing enqueued, when
+ * tpcx_workspace_bytes(ctx, in->n_units, in->n_clusters, cap_start) exceeds
+ * TPCX_STATIC_SCRATCH_BYTES (a single sector or event of a few 10^5 clusters
+ * with cap_start near its start-hit count fits).  Every call on a device
+ * shares that device's array and the array keeps the last call's contents
+ * (each call clears what it needs itself): calls that overlap in time on one
+ * device -- other streams, contexts or threads -- race and give wrong
+ * results. */
+tpcx_status tpcx_track_static(tpcx_ctx* ctx, const tpcx_clusters* in, int64_t cap_start,
+                              const tpcx_tracks* out, const tpcx_debug* dbg, hipStream_t stream);
+
 /* Waits for the stream and returns TPCX_E_CAPACITY if the last tpcx_track on
  * it overflowed a capacity, else TPCX_E_INPUT if some cluster coordinate was
  * not finite, TPCX_E_HIP on a runtime error, else TPCX_OK. */

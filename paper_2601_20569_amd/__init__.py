@@ -127,6 +127,9 @@ def lib():
         L.tpcx_track.argtypes = [P, ctypes.POINTER(Clusters), P, ctypes.c_size_t, ctypes.c_int64,
                                  ctypes.POINTER(Tracks), ctypes.POINTER(Debug), P]
         L.tpcx_track.restype = ctypes.c_int32
+        L.tpcx_track_static.argtypes = [P, ctypes.POINTER(Clusters), ctypes.c_int64,
+                                        ctypes.POINTER(Tracks), ctypes.POINTER(Debug), P]
+        L.tpcx_track_static.restype = ctypes.c_int32
         L.tpcx_poll.argtypes = [P, ctypes.POINTER(Tracks), P]
         L.tpcx_poll.restype = ctypes.c_int32
         L.tpcx_strerror.argtypes = [ctypes.c_int32]
@@ -261,7 +264,8 @@ class SectorTracker:
     def workspace_bytes(self, n_units, n_clusters, cap_start):
         return int(lib().tpcx_workspace_bytes(self._h, n_units, n_clusters, cap_start))
 
-    def allocate(self, n_units, n_clusters, cap_start=None, cap_tracks=None, cap_hits=None):
+    def allocate(self, n_units, n_clusters, cap_start=None, cap_tracks=None, cap_hits=None,
+                 workspace=True):
         """Device buffers for one call shape (workspace and outputs)."""
         import torch
         dev = torch.device("cuda", self.device)
@@ -269,8 +273,10 @@ class SectorTracker:
         cap_tracks = cap_start if cap_tracks is None else int(cap_tracks)
         cap_hits = int(max(1024, 4 * n_clusters)) if cap_hits is None else int(cap_hits)
         nb = self.workspace_bytes(n_units, n_clusters, cap_start)
-        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
-        off = (-ws.data_ptr()) % 256
+        ws, off = None, 0
+        if workspace:
+            ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+            off = (-ws.data_ptr()) % 256
         i32, i64, f32 = torch.int32, torch.int64, torch.float32
         out = dict(
             counts=torch.zeros(4, dtype=i64, device=dev),
@@ -289,8 +295,10 @@ class SectorTracker:
         return dict(ws=ws, ws_off=off, ws_bytes=nb, cap_start=cap_start, cap_tracks=cap_tracks,
                     cap_hits=cap_hits, out=out)
 
-    def track_into(self, row_begin, y, z, n_units, bufs, debug=None, stream=None):
-        """Enqueue one tpcx_track call into preallocated buffers (no sync)."""
+    def track_into(self, row_begin, y, z, n_units, bufs, debug=None, stream=None, static=False):
+        """Enqueue one tpcx_track call into preallocated buffers (no sync).
+        ``static``: tpcx_track_static, on the library's per-device scratch
+        array instead of bufs' workspace (bufs["ws"] may then be None)."""
         import torch
         n = int(y.numel())
         for t, dt in ((row_begin, torch.int64), (y, torch.float32), (z, torch.float32)):
@@ -309,12 +317,18 @@ class SectorTracker:
             dbg = Debug(*[_ptr(debug.get(k)) for k in ("link_up", "link_down", "clean_up",
                                                         "clean_down", "starts")])
         s = stream if stream is not None else torch.cuda.current_stream()
-        ws = bufs["ws"]
-        st = lib().tpcx_track(self._h, ctypes.byref(cl), ctypes.c_void_p(ws.data_ptr() + bufs["ws_off"]),
-                              bufs["ws_bytes"], bufs["cap_start"], ctypes.byref(tr),
-                              ctypes.byref(dbg) if dbg is not None else None,
-                              ctypes.c_void_p(s.cuda_stream))
-        _check(st, "tpcx_track")
+        if static:
+            st = lib().tpcx_track_static(self._h, ctypes.byref(cl), bufs["cap_start"], ctypes.byref(tr),
+                                         ctypes.byref(dbg) if dbg is not None else None,
+                                         ctypes.c_void_p(s.cuda_stream))
+            _check(st, "tpcx_track_static")
+        else:
+            ws = bufs["ws"]
+            st = lib().tpcx_track(self._h, ctypes.byref(cl), ctypes.c_void_p(ws.data_ptr() + bufs["ws_off"]),
+                                  bufs["ws_bytes"], bufs["cap_start"], ctypes.byref(tr),
+                                  ctypes.byref(dbg) if dbg is not None else None,
+                                  ctypes.c_void_p(s.cuda_stream))
+            _check(st, "tpcx_track")
         self._last = (tr, s)
         return tr
 

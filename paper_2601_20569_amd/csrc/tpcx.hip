@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -19,6 +20,12 @@
 #include "tracklet.h"
 
 using namespace tpcx;
+
+// Workspace of tpcx_track_static, for callers that cannot allocate device
+// memory: one copy per device (reserved when the code object is loaded on
+// the device, held until the process ends).  Host code never uses this name
+// as an address: it resolves the device's copy with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[TPCX_STATIC_SCRATCH_BYTES];
 
 struct tpcx_ctx {
   int device = 0;
@@ -47,6 +54,8 @@ struct tpcx_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<unsigned char> graph_key;
+  // device address of this device's `scratch` array
+  void* scratch = nullptr;
 };
 
 namespace {
@@ -220,6 +229,24 @@ bool valid_tuning(const tpcx_tuning& t) {
          t.refit_refill >= 1 && t.refit_refill <= kWave;
 }
 
+// Device address of the current device's `scratch` array, resolved once per
+// device and kept for the process (each device holds its own copy).
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+tpcx_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return TPCX_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TPCX_E_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return TPCX_OK;
+}
+
 tpcx_status build_rows(tpcx_ctx* c) {
   c->rows_host.resize(c->n_rows);
   int32_t cum = 0;
@@ -326,7 +353,7 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
             hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess &&
             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
-  if (!ok || build_rows(c) != TPCX_OK) {
+  if (!ok || build_rows(c) != TPCX_OK || scratch_address(dev, &c->scratch) != TPCX_OK) {
     tpcx_destroy(c);
     return TPCX_E_HIP;
   }
@@ -618,6 +645,17 @@ tpcx_status tpcx_track(tpcx_ctx* c, const tpcx_clusters* in, void* ws, size_t ws
   return track_on(c, in, ws, ws_bytes, cap_start, out, dbg, stream);
 }
 
+tpcx_status tpcx_track_static(tpcx_ctx* c, const tpcx_clusters* in, int64_t cap_start,
+                              const tpcx_tracks* out, const tpcx_debug* dbg, hipStream_t stream) {
+  if (!c || !c->scratch) return TPCX_E_ARG;
+  // the size check comes first: nothing is enqueued for an input that does not fit
+  if (!in || in->n_units < 1 || in->n_clusters < 0 || cap_start < 0 ||
+      tpcx_workspace_bytes(c, in->n_units, in->n_clusters, cap_start) > size_t(TPCX_STATIC_SCRATCH_BYTES))
+    return TPCX_E_ARG;
+  // every cleared word of the workspace is cleared by a fill kernel of the
+  // sequence itself, so the array's previous contents do not matter
+  return track_on(c, in, c->scratch, size_t(TPCX_STATIC_SCRATCH_BYTES), cap_start, out, dbg, stream);
+}
 
 tpcx_status tpcx_poll(tpcx_ctx* c, const tpcx_tracks* out, hipStream_t stream) {
   if (!c || !out || !out->counts) return TPCX_E_ARG;
