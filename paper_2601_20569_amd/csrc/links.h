@@ -77,6 +77,84 @@ __device__ __forceinline__ int nf_collect(const Grid& g, int64_t kb, int ny, int
   return n;
 }
 
+// Wavefront-cooperative form of nf_collect: the window candidates of all 64
+// lanes' clusters in one row, spread over all lanes.  For each pair of z bins
+// in turn (each lane's box starting at its own zb0), the lanes' candidate
+// ranges are numbered by a prefix sum over the wavefront; lane l evaluates
+// candidates l and l + 64 of every 128, for their owner lane's cluster, and
+// appends those inside the owner's window to the owner's LDS list (an LDS
+// counter per owner).  The order inside a list is free: the pair selection has
+// a total order.  Returns the lane's own count (which may exceed kNfD).  All
+// 64 lanes must call it; `act` marks lanes with a cluster to serve.
+__device__ __forceinline__ int nf_collect_wave(const Grid& g, int64_t kb, int ny, int zb0, int zb1, int yb0,
+                                               int yb1, bool act, float yh, float zh, float wy, float wz,
+                                               int32_t (*pos)[kNfBlock], int32_t* cnt, int t) {
+  const int lane = lane_id();
+  const int wbase = t - lane;
+  cnt[t] = 0;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  for (int zb = zb0;; zb += 2) {
+    const bool a = act && zb <= zb1;
+    if (__ballot(a) == 0ull) break;
+    int32_t a0 = 0, alen = 0, b0 = 0, n = 0;
+    if (a) {
+      const bool z2 = zb + 1 <= zb1;
+      const int64_t ra = kb + int64_t(zb) * ny;
+      const int64_t rb = z2 ? ra + ny : ra;
+      const int32_t j0 = g.bin_start[ra + yb0], j1 = g.bin_start[ra + yb1 + 1];
+      const int32_t k0 = g.bin_start[rb + yb0], k1 = g.bin_start[rb + yb1 + 1];
+      a0 = j0;
+      alen = j1 - j0;
+      b0 = k0;
+      n = alen + (z2 ? k1 - k0 : 0);
+    }
+    int incl = n;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int v = __shfl_up(incl, d, kWave);
+      if (lane >= d) incl += v;
+    }
+    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+    const int excl = incl - n;
+    for (int t0 = 0; t0 < total; t0 += 2 * kWave) {
+      const int ta = t0 + lane, tb = ta + kWave;
+      int oa = 0, ob = 0;
+#pragma unroll
+      for (int st = kWave / 2; st > 0; st >>= 1) {
+        const int va = __shfl(incl, oa + st - 1, kWave);
+        const int vb = __shfl(incl, ob + st - 1, kWave);
+        if (va <= ta) oa += st;
+        if (vb <= tb) ob += st;
+      }
+      const int ua = ta - __shfl(excl, oa, kWave), ub = tb - __shfl(excl, ob, kWave);
+      // every shuffle with all lanes active (a shuffle reads nothing from a
+      // lane its branch has switched off)
+      const int la = __shfl(alen, oa, kWave), lb = __shfl(alen, ob, kWave);
+      const int aa = __shfl(a0, oa, kWave), ab = __shfl(a0, ob, kWave);
+      const int ba = __shfl(b0, oa, kWave), bb = __shfl(b0, ob, kWave);
+      const int pa = ua < la ? aa + ua : ba + (ua - la);
+      const int pb = ub < lb ? ab + ub : bb + (ub - lb);
+      const bool va = ta < total, vb = tb < total;
+      float4 ca = make_float4(0.0f, 0.0f, 0.0f, 0.0f), cb = ca;
+      if (va) ca = g.pts[pa];
+      if (vb) cb = g.pts[pb];
+      const float ya = __shfl(yh, oa, kWave), za = __shfl(zh, oa, kWave);
+      const float yb = __shfl(yh, ob, kWave), zb_ = __shfl(zh, ob, kWave);
+      if (va && fabsf(ca.x - ya) <= wy && fabsf(ca.y - za) <= wz) {
+        const int slot = atomicAdd(&cnt[wbase + oa], 1);
+        if (slot < kNfD) pos[slot][wbase + oa] = pa;
+      }
+      if (vb && fabsf(cb.x - yb) <= wy && fabsf(cb.y - zb_) <= wz) {
+        const int slot = atomicAdd(&cnt[wbase + ob], 1);
+        if (slot < kNfD) pos[slot][wbase + ob] = pb;
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+  }
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  return __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // (D, ju, jd) against the best so far under the order (D, id_u, id_d).
 __device__ __forceinline__ bool nf_better(const Grid& g, float D, int32_t ju, int32_t jd, float bestD,
                                           int32_t best_ju, int32_t best_jd) {
@@ -93,6 +171,8 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
                                                          int32_t* __restrict__ down_s) {
   __shared__ int32_t d_pos[kNfD][kNfBlock];
   __shared__ int32_t u_pos[kNfD][kNfBlock];
+  __shared__ int32_t d_cnt[kNfBlock];
+  __shared__ int32_t u_cnt[kNfBlock];
   const int k = int(xcd_block());
   const int r = k % g.n_rows;
   const int64_t b = row_begin[k], e = row_begin[k + 1];
@@ -109,8 +189,13 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
   const int ku = k + 1, kd = k - 1;
   const int64_t bu = g.row_base(ku), bd = g.row_base(kd);
   const int nyu = g.rows[r + 1].ny, nyd = g.rows[r - 1].ny;
-  for (int64_t i = b + t; i < e; i += blockDim.x) {
-    const float4 ph = g.pts[i];
+  // wavefront-uniform loop: every lane of a wavefront takes part in the
+  // cooperative collections, lanes past the row's end without a cluster
+  const int lane = lane_id();
+  for (int64_t i0 = b + (t - lane); i0 < e; i0 += blockDim.x) {
+    const int64_t i = i0 + lane;
+    const bool act = i < e;
+    const float4 ph = act ? g.pts[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float yh = ph.x, zh = ph.y;
     const float pz = wz + box_pad(zh), py = wy + box_pad(yh);
     const int zu0 = g.zbin(ku, zh - pz), zu1 = g.zbin(ku, zh + pz);
@@ -118,8 +203,10 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
     const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
     const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
 
-    const int nd = nf_collect(g, bd, nyd, zd0, zd1, yd0, yd1, yh, zh, wy, wz, d_pos, t);
-    const int nu = nd > 0 ? nf_collect(g, bu, nyu, zu0, zu1, yu0, yu1, yh, zh, wy, wz, u_pos, t) : 0;
+    const int nd = nf_collect_wave(g, bd, nyd, zd0, zd1, yd0, yd1, act, yh, zh, wy, wz, d_pos, d_cnt, t);
+    const int nu = nf_collect_wave(g, bu, nyu, zu0, zu1, yu0, yu1, act && nd > 0, yh, zh, wy, wz, u_pos,
+                                   u_cnt, t);
+    if (!act) continue;
     float bestD = 0.0f;
     int32_t best_ju = -1, best_jd = -1;
     auto consider = [&](float yu, float zu, int32_t ju, float yd, float zd, int32_t jd) {

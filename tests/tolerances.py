@@ -20,7 +20,9 @@ a step grow as 1/cos^3 phi (>= 33 at cos phi <= 0.31), so the ~3e-8 absolute
 rounding of sin phi in float is amplified into parameter errors up to ~2e-4
 relative (measured on the CPU: 3 of 515 k time-frame tracklets above 1e-4,
 all with smax >= 0.98; outside the class the largest is 2.8e-5).  The class
-is about 7 % of the tracklets; callers count it and assert its fraction.
+holds 7-13 % of the tracklets of a central event (7.4 % with 10k primaries,
+12.5 % with 2k primaries, where loopers weigh more); callers count it and
+assert that it stays below 20 %.
 """
 
 NEAR_GUARD = 0.95
