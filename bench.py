@@ -49,6 +49,9 @@ B_REFIT_PER_HIT = 12           # refitted cluster: id, y, z
 B_SEL_PER_TRACK = 25           # ambiguity solving: unit, n, offset, chi2, ndf read; kept flag written
 B_SEL_PER_HIT = 4              # the cluster id of every attached cluster
 B_SEL_PER_CLUSTER = 20         # owner key written and read (8 + 8), assignment written (4)
+B_RB_PER_TRACK = 160           # rebuild: seed, rank inputs, offsets read; results written
+B_RB_PER_HIT = 5               # id + row of every input cluster
+B_RB_PER_CLUSTER = 32          # grid build (24) and the holder word (8) of every cluster
 B_FIT_PER_TRACK = 128          # fit: seed, x_ref, offsets read; parameters, covariance, chi2, counts written
 B_FIT_PER_HIT = 62             # id, row, y, z read; 16-byte record written once and read twice; flag written
 
@@ -205,14 +208,16 @@ def cpu_model():
     return "unknown"
 
 
-def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, stream):
+def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, stream, row_begin_t):
     """The steps after the sector tracking on its output: ambiguity solving
-    and the three-iteration fit with interpolation rejection, both on every
-    tracklet of the batch, each timed on its own, with its algorithmic bytes
-    against the HBM peak."""
+    (every tracklet of the batch), the rebuild of the kept tracklets of the
+    first slice, and the three-iteration fit with interpolation rejection
+    (every tracklet of the batch), each timed on its own, with its
+    algorithmic bytes against the HBM peak."""
     import torch
     res = {}
     o = bufs["out"]
+    row_begin_h = row_begin_t.cpu().numpy()
     sel = tr.allocate_select(n_units, n_clusters, bufs["cap_tracks"])
     with torch.cuda.stream(stream):
         tr.select_into(bufs, n_units, n_clusters, sel, stream=stream)
@@ -223,7 +228,38 @@ def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, str
     res["select"] = dict(ms=round(ms, 3), tracklets=n_tracks, kept=kept, shared="10%", alg_bytes=int(b),
                          GBs=round(b / (ms * 1e-3) / 1e9, 2), frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
     log(f"ambiguity solving: {ms:.3f} ms, {kept} of {n_tracks} tracklets kept")
+    # the rebuild (Phase II) of the kept tracklets of the first slice (36 units)
+    u1 = min(n_units, 36)
+    keep = sel["keep"][:n_tracks].bool() & (o["unit"][:n_tracks] < u1)
+    idx = keep.nonzero().squeeze(1)
     del sel
+    torch.cuda.empty_cache()
+    cnt = o["n_hits"][:n_tracks][idx].to(torch.int64)
+    hb = torch.zeros(len(idx) + 1, dtype=torch.int64, device=y.device)
+    hb[1:] = torch.cumsum(cnt, 0)
+    src = torch.repeat_interleave(o["hit_begin"][:n_tracks][idx], cnt) + (
+        torch.arange(int(hb[-1]), device=y.device) - torch.repeat_interleave(hb[:-1], cnt))
+    n1 = int(row_begin_h[u1 * 152])
+    rargs = (row_begin_t[:u1 * 152 + 1].contiguous(), y[:n1], z[:n1], u1, o["unit"][:n_tracks][idx].contiguous(), hb,
+             o["hit_id"][src].contiguous(), o["hit_row"][src].contiguous(), o["param"][:n_tracks][idx].contiguous(),
+             o["x_ref"][:n_tracks][idx].contiguous(), o["chi2"][:n_tracks][idx].contiguous(),
+             o["ndf"][:n_tracks][idx].contiguous())
+    del src
+    with torch.cuda.stream(stream):
+        r = tr.rebuild(*rargs, stream=stream)
+        sync()
+        del r
+        ms = timed(lambda: tr.rebuild(*rargs, stream=stream), steps, stream)
+        r = tr.rebuild(*rargs, stream=stream)
+        sync()
+    nt1, nh1 = len(idx), int(hb[-1])
+    b = B_RB_PER_TRACK * nt1 + B_RB_PER_HIT * nh1 + B_RB_PER_CLUSTER * n1
+    res["rebuild"] = dict(ms=round(ms, 3), workload=f"kept tracklets of the first {u1} units", clusters=n1,
+                          tracks=nt1, input_hits=nh1, ok=int(r["ok"].sum()), kept_hits=int(r["n_kept"].sum()),
+                          alg_bytes=int(b), GBs=round(b / (ms * 1e-3) / 1e9, 2),
+                          frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
+    log(f"rebuild: {ms:.3f} ms, {nt1} tracks of the first slice, {res['rebuild']['kept_hits']} clusters kept")
+    del r, rargs
     torch.cuda.empty_cache()
     # every kept tracklet (their hits are contiguous in the output)
     hb = torch.empty(n_tracks + 1, dtype=torch.int64, device=y.device)
@@ -413,7 +449,7 @@ def main():
         forms["batched_tracking_only_ms"] = round(track_ms, 3)
         log(f"batched graph without the refit: {track_ms:.3f} ms/step")
     if not args.no_next:
-        forms.update(next_steps(tr, bufs, U, N, n_tracks, n_hits, y, z, args.steps, stream))
+        forms.update(next_steps(tr, bufs, U, N, n_tracks, n_hits, y, z, args.steps, stream, rb))
     del bufs
     torch.cuda.empty_cache()
 

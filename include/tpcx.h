@@ -378,6 +378,81 @@ tpcx_status tpcx_fit(tpcx_ctx* ctx, const tpcx_fit_in* in, const tpcx_fit_params
                      const tpcx_fit_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Track rebuild (paper, Section 3, Phase II: during the fit the attachment
+ * is redone; iteration 2 queries the sector tracking's cluster search grid
+ * for every cluster compatible with the chi2 cut against the interpolation
+ * and stores the candidates with their residuals; a second ambiguity solving
+ * assigns candidates by rank, a track that does not get its best candidate
+ * staying eligible for the next; iteration 3 applies a plain chi2 cut).
+ *
+ * Per track of one unit (clusters innermost first, rows r_in .. r_out, y and
+ * z relative to the outermost cluster):
+ *   1. from the tracking result at x_ref out to the outermost cluster (its
+ *      y, z; diagonal covariance), then row by row inwards to r_in: store the
+ *      predicted y, z (binary32) and C_yy, C_zz (bfloat16) of every row,
+ *      update with the track's own cluster of the row;
+ *   2. restart at the innermost cluster, row by row outwards: combine the
+ *      outward prediction with the stored one by inverse-variance weighting
+ *      (one alone at r_in and r_out); every cluster of the row with chi2 <=
+ *      chi2_cut against that interpolation is a candidate; the 4 best by
+ *      (chi2, caller id) are kept; update with the best (not at r_in);
+ *   3. rank of a track as in tpcx_select, from the given chi2, ndf and
+ *      length; `rounds` rounds in which every (track, row) proposes its
+ *      current candidate, a cluster is held by its best-ranked proposer so
+ *      far, and a (track, row) whose candidate another holds moves to its
+ *      next; a (track, row) gets its candidate if it holds it; no sharing;
+ *   4. from step 2's final state back to the outermost assigned row (its
+ *      cluster's y, z; diagonal covariance), then inwards over the assigned
+ *      rows: a cluster whose filter chi2 exceeds chi2_final is dropped.
+ *      Result at the innermost kept cluster; ndf = 2 n_kept - 5.
+ * A rebuild fails (ok = 0, nothing assigned) on a propagation guard, with
+ * fewer than 3 kept clusters, or when its input breaks the layout below
+ * (unit outside 0 .. n_units - 1, rows not strictly ascending or outside
+ * the geometry, cluster ids outside the cluster array, offsets outside
+ * 0 .. n_hits): such input is never read out of bounds.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  float chi2_cut;              /* candidate chi2 cut against the interpolation */
+  float chi2_final;            /* chi2 cut of the last iteration */
+  float var_s, var_t, var_w;   /* restart variances of sin(phi), dz/ds, q/pT */
+  int32_t rounds;              /* proposal rounds of the assignment (0 .. 64) */
+} tpcx_rebuild_params;
+
+typedef struct {
+  int64_t n_tracks;            /* tracks in unit order */
+  int64_t n_hits;              /* host copy of hit_begin[n_tracks] */
+  const int32_t* unit;         /* [n_tracks] */
+  const int64_t* hit_begin;    /* [n_tracks + 1] */
+  const int32_t* hit_id;       /* clusters, rows ascending per track */
+  const uint8_t* hit_row;
+  const float* seed;           /* [n_tracks][5] tracking result */
+  const float* x_ref;          /* [n_tracks] */
+  const float* chi2;           /* [n_tracks] tracking chi2 (rank) */
+  const int32_t* ndf;          /* [n_tracks] */
+} tpcx_rebuild_in;
+
+typedef struct {
+  int32_t* assigned;  /* [n_tracks][n_rows] cluster kept at each row, -1 for none */
+  float* param;       /* [n_tracks][5] */
+  float* cov;         /* [n_tracks][15] */
+  float* chi2;        /* [n_tracks] */
+  float* x_out;       /* [n_tracks] */
+  int32_t* n_kept;    /* [n_tracks] */
+  int32_t* ok;        /* [n_tracks] */
+} tpcx_rebuild_out;
+
+/* Workspace of tpcx_rebuild: the search grid of the clusters, ~50 bytes per
+ * track and row, 8 bytes per cluster. */
+size_t tpcx_rebuild_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_clusters,
+                                    int64_t n_tracks);
+
+/* Enqueues the rebuild of the tracks `in` against the clusters `clusters`
+ * (the tracking input: its search grid is built here); ws 256-byte aligned. */
+tpcx_status tpcx_rebuild(tpcx_ctx* ctx, const tpcx_clusters* clusters, const tpcx_rebuild_in* in,
+                         const tpcx_rebuild_params* params, const tpcx_rebuild_out* out, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Tuning and autotuning.  No tuning changes any result (every selection of
  * the method has a total order), only the speed.
  * ------------------------------------------------------------------------ */

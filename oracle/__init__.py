@@ -22,7 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tpc_oracle.cpp")
 SOURCES = [SRC, os.path.join(HERE, "tpc_refit.cpp"), os.path.join(HERE, "tpc_select.cpp"),
-           os.path.join(HERE, "tpc_fit.cpp")]
+           os.path.join(HERE, "tpc_fit.cpp"), os.path.join(HERE, "tpc_rebuild.cpp")]
 HEADERS = [os.path.join(HERE, "kalman.h")]
 LIB = os.path.join(HERE, "libtpc_oracle.so")
 
@@ -109,6 +109,8 @@ def lib():
         L.orc_refit_grad.argtypes = [P, P, ctypes.c_int64] + [P] * 12
         L.orc_fit.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, ctypes.c_int64] + [P] * 14
+        L.orc_rebuild.argtypes = [ctypes.c_int, P, ctypes.c_int, P] + [ctypes.c_float] * 5 + [
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64] + [P] * 17
         L.orc_select.restype = ctypes.c_int64
         L.orc_select.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
                                  ctypes.c_int32, P, P]
@@ -410,4 +412,41 @@ def fit(cs, tk, precision=32, reject=None, params: Params | None = None, row_x=N
                   _p(out["ok"]))
     out["ok"] = out["ok"].astype(bool)
     out["reject"] = rej
+    return out
+
+
+REBUILD_DEFAULTS = dict(chi2_cut=16.0, chi2_final=16.0, vs=1e-2, vt=1e-2, vw=1.0, k_max=4, rounds=6)
+
+
+def rebuild(cs, tk, precision=32, params: Params | None = None, row_x=None, **kw):
+    """Phase II rebuild of the tracks in tk (kept_tracklets layout plus xref,
+    chi2, ndf, unit) against the clusters of their units (cs.row_begin, y,
+    z).  Returns param, cov, chi2, x_out, n_kept, ok and assigned [n, n_rows]
+    (the cluster kept at each row, -1 for none)."""
+    from synth import geometry as G
+    params = params or Params()
+    f = dict(REBUILD_DEFAULTS, **kw)
+    xr = np.ascontiguousarray(row_x if row_x is not None else G.row_x(), dtype=np.float32)
+    R = len(xr)
+    n = len(tk["hit_begin"]) - 1
+    arrs = dict(unit=np.ascontiguousarray(tk["unit"], dtype=np.int32),
+                hb=np.ascontiguousarray(tk["hit_begin"], dtype=np.int64),
+                hits=np.ascontiguousarray(tk["hits"], dtype=np.int32),
+                rows=np.ascontiguousarray(tk["rows"], dtype=np.uint8),
+                seed=np.ascontiguousarray(tk["param"], dtype=np.float32),
+                xref=np.ascontiguousarray(tk["xref"], dtype=np.float32),
+                chi2=np.ascontiguousarray(tk["chi2"], dtype=np.float32),
+                ndf=np.ascontiguousarray(tk["ndf"], dtype=np.int32),
+                rb=np.ascontiguousarray(cs.row_begin, dtype=np.int64),
+                y=np.ascontiguousarray(cs.y, dtype=np.float32), z=np.ascontiguousarray(cs.z, dtype=np.float32))
+    out = dict(assigned=np.zeros((n, R), np.int32), param=np.zeros((n, 5)), cov=np.zeros((n, 15)),
+               chi2=np.zeros(n), x_out=np.zeros(n), n_kept=np.zeros(n, np.int32), ok=np.zeros(n, np.int32))
+    ps = params.c_struct()
+    a = arrs
+    lib().orc_rebuild(precision, _p(xr), R, ctypes.byref(ps), f["chi2_cut"], f["chi2_final"], f["vs"], f["vt"],
+                      f["vw"], int(f["k_max"]), int(f["rounds"]), int(cs.n_units), n, _p(a["unit"]), _p(a["hb"]),
+                      _p(a["hits"]), _p(a["rows"]), _p(a["seed"]), _p(a["xref"]), _p(a["chi2"]), _p(a["ndf"]),
+                      _p(a["rb"]), _p(a["y"]), _p(a["z"]), _p(out["assigned"]), _p(out["param"]), _p(out["cov"]),
+                      _p(out["chi2"]), _p(out["x_out"]), _p(out["n_kept"]), _p(out["ok"]))
+    out["ok"] = out["ok"].astype(bool)
     return out

@@ -90,6 +90,24 @@ class FitOutput(ctypes.Structure):
                 ("reject", ctypes.c_void_p)]
 
 
+class RebuildParams(ctypes.Structure):
+    _fields_ = [("chi2_cut", ctypes.c_float), ("chi2_final", ctypes.c_float), ("var_s", ctypes.c_float),
+                ("var_t", ctypes.c_float), ("var_w", ctypes.c_float), ("rounds", ctypes.c_int32)]
+
+
+class RebuildInput(ctypes.Structure):
+    _fields_ = [("n_tracks", ctypes.c_int64), ("n_hits", ctypes.c_int64), ("unit", ctypes.c_void_p),
+                ("hit_begin", ctypes.c_void_p), ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p),
+                ("seed", ctypes.c_void_p), ("x_ref", ctypes.c_void_p), ("chi2", ctypes.c_void_p),
+                ("ndf", ctypes.c_void_p)]
+
+
+class RebuildOutput(ctypes.Structure):
+    _fields_ = [("assigned", ctypes.c_void_p), ("param", ctypes.c_void_p), ("cov", ctypes.c_void_p),
+                ("chi2", ctypes.c_void_p), ("x_out", ctypes.c_void_p), ("n_kept", ctypes.c_void_p),
+                ("ok", ctypes.c_void_p)]
+
+
 class BatchRefit(ctypes.Structure):
     _fields_ = [("min_hits", ctypes.c_int32), ("map_z_fixed", ctypes.c_int32), ("map_z", ctypes.c_float),
                 ("theta", ctypes.c_void_p),
@@ -152,6 +170,12 @@ def lib():
         L.tpcx_fit.argtypes = [P, ctypes.POINTER(FitInput), ctypes.POINTER(FitParams),
                                ctypes.POINTER(FitOutput), P, ctypes.c_size_t, P]
         L.tpcx_fit.restype = ctypes.c_int32
+        L.tpcx_rebuild_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+        L.tpcx_rebuild_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_rebuild.argtypes = [P, ctypes.POINTER(Clusters), ctypes.POINTER(RebuildInput),
+                                   ctypes.POINTER(RebuildParams), ctypes.POINTER(RebuildOutput), P,
+                                   ctypes.c_size_t, P]
+        L.tpcx_rebuild.restype = ctypes.c_int32
         L.tpcx_select_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
         L.tpcx_select_workspace_bytes.restype = ctypes.c_size_t
         L.tpcx_select.argtypes = [P, ctypes.POINTER(Tracks), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
@@ -369,6 +393,44 @@ class SectorTracker:
         out["_ws"] = ws
         res = {k: v[:n] for k, v in out.items() if k not in ("reject", "_ws")}
         res["reject"] = out["reject"][:nh]
+        res["_ws"] = ws
+        return res
+
+    def rebuild(self, row_begin, y, z, n_units, unit, hit_begin, hit_id, hit_row, seed, x_ref, chi2, ndf,
+                chi2_cut=16.0, chi2_final=16.0, var_s=1e-2, var_t=1e-2, var_w=1.0, rounds=6, stream=None):
+        """Phase II rebuild (tpcx_rebuild) of the tracks given by device tensors
+        against the clusters (row_begin, y, z of the tracking input).  Returns a
+        dict of device tensors: assigned [n, n_rows], param, cov, chi2, x_out,
+        n_kept, ok (no sync)."""
+        import torch
+        n = int(hit_begin.numel()) - 1
+        nh = int(hit_id.numel())
+        for v, dt in ((row_begin, torch.int64), (y, torch.float32), (z, torch.float32), (unit, torch.int32),
+                      (hit_begin, torch.int64), (hit_id, torch.int32), (hit_row, torch.uint8),
+                      (seed, torch.float32), (x_ref, torch.float32), (chi2, torch.float32), (ndf, torch.int32)):
+            if v.dtype != dt or not v.is_cuda or not v.is_contiguous():
+                raise TpcxError("rebuild inputs must be contiguous device tensors of the documented types")
+        dev = hit_begin.device
+        f32, i32 = torch.float32, torch.int32
+        m = max(n, 1)
+        out = dict(assigned=torch.empty((m, self.n_rows), dtype=i32, device=dev),
+                   param=torch.empty((m, 5), dtype=f32, device=dev), cov=torch.empty((m, 15), dtype=f32, device=dev),
+                   chi2=torch.empty(m, dtype=f32, device=dev), x_out=torch.empty(m, dtype=f32, device=dev),
+                   n_kept=torch.empty(m, dtype=i32, device=dev), ok=torch.empty(m, dtype=i32, device=dev))
+        nc = int(y.numel())
+        nb = int(lib().tpcx_rebuild_workspace_bytes(self._h, n_units, nc, n))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        cl = Clusters(n_units, nc, _ptr(row_begin), _ptr(y), _ptr(z))
+        ri = RebuildInput(n, nh, _ptr(unit), _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(seed), _ptr(x_ref),
+                          _ptr(chi2), _ptr(ndf))
+        ro = RebuildOutput(*[_ptr(out[k]) for k in ("assigned", "param", "cov", "chi2", "x_out", "n_kept", "ok")])
+        rp = RebuildParams(chi2_cut, chi2_final, var_s, var_t, var_w, rounds)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().tpcx_rebuild(self._h, ctypes.byref(cl), ctypes.byref(ri), ctypes.byref(rp), ctypes.byref(ro),
+                                  ctypes.c_void_p(ws.data_ptr() + off), nb, ctypes.c_void_p(s.cuda_stream)),
+               "tpcx_rebuild")
+        res = {k: v[:n] for k, v in out.items()}
         res["_ws"] = ws
         return res
 

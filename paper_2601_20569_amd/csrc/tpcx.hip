@@ -16,6 +16,7 @@
 #include "refit.h"
 #include "select.h"
 #include "fit.h"
+#include "rebuild.h"
 #include "tpcx_common.h"
 #include "tracklet.h"
 
@@ -958,6 +959,125 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   fo.reject = out->reject;
   const FitConsts f{fp->chi2_cut, fp->var_s, fp->var_t, fp->var_w};
   hipLaunchKernelGGL(k_fit, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream, fi, c->dp, f, rec, fo);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct RebuildLayout {
+  UnitZ* row_z;
+  int32_t* bins;
+  float4* pts;
+  int64_t* status;
+  RebuildWs ws;
+  size_t bytes;
+};
+
+RebuildLayout carve_rebuild(const tpcx_ctx* c, void* base, int32_t n_units, int64_t n_clusters,
+                            int64_t n_tracks, int nz) {
+  Carver cv{static_cast<char*>(base)};
+  RebuildLayout L{};
+  const int64_t R = c->n_rows;
+  L.row_z = cv.take<UnitZ>(int64_t(n_units) * R);
+  L.bins = cv.take<int32_t>(int64_t(n_units) * bins_per_unit(c, nz));
+  L.pts = cv.take<float4>(n_clusters);
+  L.status = cv.take<int64_t>(1);
+  L.ws.pred = cv.take<float4>(n_tracks * R);
+  L.ws.cand = cv.take<int2>(n_tracks * R * kRebuildK);
+  L.ws.cnt = cv.take<uint8_t>(n_tracks * R);
+  L.ws.ptr = cv.take<uint8_t>(n_tracks * R);
+  L.ws.state = cv.take<float>(16 * n_tracks);
+  L.ws.meta = cv.take<int32_t>(4 * n_tracks);
+  L.ws.key = cv.take<uint64_t>(n_tracks);
+  L.ws.holder = cv.take<unsigned long long>(n_clusters);
+  L.bytes = cv.off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tpcx_rebuild_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_clusters, int64_t n_tracks) {
+  if (!c || n_units < 1 || n_clusters < 0 || n_tracks < 0) return 0;
+  const tpcx_tuning t = effective_tuning(c, n_units, n_clusters);
+  return carve_rebuild(c, nullptr, n_units, n_clusters, n_tracks, t.n_zbins).bytes;
+}
+
+tpcx_status tpcx_rebuild(tpcx_ctx* c, const tpcx_clusters* cl, const tpcx_rebuild_in* in,
+                         const tpcx_rebuild_params* rp, const tpcx_rebuild_out* out, void* ws, size_t ws_bytes,
+                         hipStream_t stream) {
+  if (!c || !cl || !in || !rp || !out || cl->n_units < 1 || cl->n_clusters < 0 ||
+      cl->n_clusters >= (int64_t(1) << 31) || !cl->row_begin || in->n_tracks < 0 || in->n_hits < 0)
+    return TPCX_E_ARG;
+  if (cl->n_clusters > 0 && (!cl->y || !cl->z)) return TPCX_E_ARG;
+  if (in->n_tracks > 0 && (!in->unit || !in->hit_begin || !in->seed || !in->x_ref || !in->chi2 || !in->ndf ||
+                           !out->assigned || !out->param || !out->cov || !out->chi2 || !out->x_out ||
+                           !out->n_kept || !out->ok))
+    return TPCX_E_ARG;
+  if (in->n_hits > 0 && (!in->hit_id || !in->hit_row)) return TPCX_E_ARG;
+  if (!(rp->chi2_cut >= 0.0f) || !(rp->chi2_final >= 0.0f) || !(rp->var_s > 0.0f) || !(rp->var_t > 0.0f) ||
+      !(rp->var_w > 0.0f) || rp->rounds < 0 || rp->rounds > 64)
+    return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  const tpcx_tuning t = effective_tuning(c, cl->n_units, cl->n_clusters);
+  const RebuildLayout L = carve_rebuild(c, ws, cl->n_units, cl->n_clusters, in->n_tracks, t.n_zbins);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
+  if (in->n_tracks == 0) return TPCX_OK;
+  Grid g;
+  g.rows = c->d_rows;
+  g.row_z = L.row_z;
+  g.bin_start = L.bins;
+  g.pts = L.pts;
+  g.n_rows = c->n_rows;
+  g.nz = t.n_zbins;
+  g.btot = bins_per_unit(c, t.n_zbins);
+  const int UR = cl->n_units * c->n_rows;
+  const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, L.status, int64_t(1), int64_t(0));
+  hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(t.block), hist_bytes, stream, cl->row_begin, cl->y, cl->z, g,
+                     L.row_z, L.bins, L.pts, reinterpret_cast<unsigned long long*>(L.status));
+  RebuildIn ri;
+  ri.n_tracks = in->n_tracks;
+  ri.n_hits = in->n_hits;
+  ri.n_clusters = cl->n_clusters;
+  ri.n_rows = c->n_rows;
+  ri.n_units = cl->n_units;
+  ri.unit = in->unit;
+  ri.hit_begin = in->hit_begin;
+  ri.hit_id = in->hit_id;
+  ri.hit_row = in->hit_row;
+  ri.seed = in->seed;
+  ri.x_ref = in->x_ref;
+  ri.chi2 = in->chi2;
+  ri.ndf = in->ndf;
+  ri.y = cl->y;
+  ri.z = cl->z;
+  ri.row_x = c->d_row_x;
+  const RebuildConsts f{rp->chi2_cut, rp->chi2_final, rp->var_s, rp->var_t, rp->var_w, rp->rounds};
+  RebuildOut ro;
+  ro.assigned = out->assigned;
+  ro.param = out->param;
+  ro.cov = out->cov;
+  ro.chi2 = out->chi2;
+  ro.x_out = out->x_out;
+  ro.n_kept = out->n_kept;
+  ro.ok = out->ok;
+  const dim3 gw(blocks_for(in->n_tracks, kWave));
+  hipLaunchKernelGGL(k_rebuild_keys, dim3(blocks_for(in->n_tracks, 256)), dim3(256), 0, stream, ri, L.ws.key);
+  hipLaunchKernelGGL(k_rebuild_pass12, gw, dim3(kWave), 0, stream, ri, g, c->dp, f, L.ws);
+  if (cl->n_clusters > 0)
+    hipLaunchKernelGGL(k_fill_i64, dim3(std::max(1, std::min(blocks_for(cl->n_clusters, 256), 4096))), dim3(256),
+                       0, stream, reinterpret_cast<int64_t*>(L.ws.holder), cl->n_clusters, int64_t(0));
+  for (int round = 0; round < rp->rounds; ++round) {
+    hipLaunchKernelGGL(k_rebuild_propose, gw, dim3(kWave), 0, stream, ri, L.ws);
+    hipLaunchKernelGGL(k_rebuild_advance, gw, dim3(kWave), 0, stream, ri, L.ws);
+  }
+  hipLaunchKernelGGL(k_rebuild_pass3, gw, dim3(kWave), 0, stream, ri, c->dp, f, L.ws, ro);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 

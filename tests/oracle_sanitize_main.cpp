@@ -37,6 +37,17 @@ int64_t orc_select(int64_t n_tracks, const int32_t* unit, const int32_t* n, cons
                    const int32_t* hit_id, const float* chi2, const int32_t* ndf, int64_t n_clusters,
                    int32_t shared_num, int32_t shared_den, uint8_t* keep, int32_t* assign);
 int orc_map_ncoef();
+void orc_fit(int precision, int decide, const float* row_x, const OrcParams* p, float chi2_cut, float vs, float vt,
+             float vw, int64_t n_tracks, const int64_t* hit_begin, const int32_t* hit_id, const uint8_t* hit_row,
+             const float* seed, const float* x_ref, const float* y, const float* z, uint8_t* reject, double* param,
+             double* cov, double* chi2, double* x_out, int32_t* n_kept, int32_t* ok);
+void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams* p, float chi2_cut,
+                 float chi2_final, float vs, float vt, float vw, int32_t k_max, int32_t rounds, int32_t n_units,
+                 int64_t n_tracks, const int32_t* unit, const int64_t* hit_begin, const int32_t* hit_id,
+                 const uint8_t* hit_row, const float* seed, const float* x_ref, const float* t_chi2,
+                 const int32_t* t_ndf, const int64_t* row_begin, const float* y, const float* z,
+                 int32_t* assigned, double* param, double* cov, double* chi2_out, double* x_out,
+                 int32_t* n_kept, int32_t* ok);
 }
 
 template <class T>
@@ -108,6 +119,26 @@ int main(int argc, char** argv) {
   std::vector<int32_t> assign(n);
   const int64_t kept = orc_select(nt, t_unit.data(), t_n.data(), t_hb.data(), t_hits.data(), fchi2.data(),
                                   t_ndf.data(), n, 1, 10, keep.data(), assign.data());
+  auto t_xref = std::vector<float>(nt);
+  {
+    void* h2 = orc_track(32, row_x.data(), n_rows, &p, n_units, rb.data(), y.data(), z.data(), -1, -1, 2);
+    auto xr64 = get<double>(h2, "t_xref");
+    for (int64_t i = 0; i < nt; ++i) t_xref[i] = float(xr64[i]);
+    orc_free(h2);
+  }
+  std::vector<uint8_t> rej(t_hits.size());
+  std::vector<double> fp(5 * nt), fc(15 * nt), fchi(nt), fx(nt);
+  std::vector<int32_t> fk(nt), fok(nt);
+  for (int prec : {32, 64})
+    orc_fit(prec, prec == 32, row_x.data(), &p, 16.0f, 1e-2f, 1e-2f, 1.0f, nt, t_hb.data(), t_hits.data(),
+            t_rows.data(), seed.data(), t_xref.data(), y.data(), z.data(), rej.data(), fp.data(), fc.data(),
+            fchi.data(), fx.data(), fk.data(), fok.data());
+  std::vector<int32_t> assigned(size_t(nt) * n_rows);
+  for (int prec : {32, 64})
+    orc_rebuild(prec, row_x.data(), n_rows, &p, 16.0f, 16.0f, 1e-2f, 1e-2f, 1.0f, 4, 6, n_units, nt, t_unit.data(),
+                t_hb.data(), t_hits.data(), t_rows.data(), seed.data(), t_xref.data(), fchi2.data(), t_ndf.data(),
+                rb.data(), y.data(), z.data(), assigned.data(), fp.data(), fc.data(), fchi.data(), fx.data(),
+                fk.data(), fok.data());
   std::printf("tracklets %lld kept %lld\n", static_cast<long long>(nt), static_cast<long long>(kept));
   return 0;
 }

@@ -1,8 +1,8 @@
 """The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (host
 code, g++): tracking in float and double with both candidate scans, the
 margin check, the FP64 replay, the refit (both map modes) with its gradient,
-and the ambiguity solving, on a single sector that includes non-finite
-clusters.  Any sanitizer report fails the run."""
+the ambiguity solving, the three-iteration fit and the rebuild, on a single
+sector that includes non-finite clusters.  Any sanitizer report fails the run."""
 import os
 import shutil
 import subprocess
