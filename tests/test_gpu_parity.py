@@ -88,6 +88,37 @@ def _doubled(cs):
                             cs.truth_psi[idx], cs.tracks, cs.meta)
 
 
+def _dense_row(cs, row, n_extra, seed):
+    """cs with n_extra uniform noise clusters appended to (unit 0, row)."""
+    rng = np.random.default_rng(seed)
+    x = G.row_x()[row]
+    ye = rng.uniform(-1.0, 1.0, n_extra) * x * G.tan_half_opening()
+    ze = rng.uniform(-240.0, 240.0, n_extra)
+    at = int(cs.row_begin[row + 1])  # after the row's own clusters
+    ins = lambda a, v: np.concatenate([a[:at], v.astype(a.dtype), a[at:]])
+    rb = cs.row_begin.copy()
+    rb[row + 1:] += n_extra
+    m = -np.ones(n_extra)
+    return synth.ClusterSet(cs.n_units, cs.unit_sector, rb, ins(cs.y, ye), ins(cs.z, ze),
+                            ins(cs.truth_track, m), ins(cs.truth_y, ye), ins(cs.truth_z, ze),
+                            ins(cs.truth_psi, 0 * m), cs.tracks, cs.meta)
+
+
+def test_row_longer_than_one_start_bitmap_segment():
+    """A pad row of more than 65,536 clusters: the start-hit ordering takes
+    its id range in several bitmap segments and the neighbour finder's lists
+    overflow into the direct scan; results still equal the oracle's."""
+    print("case: single sector seed 4, 140,000 extra clusters in row 30", flush=True)
+    cs = _dense_row(synth.single_sector(seed=4), 30, 140_000, seed=4)
+    assert np.diff(cs.row_begin)[30] > 2 * 65536
+    gpu, ref = _full_parity(cs)
+    assert len(gpu["n_hits"]) > 100
+    row = cs.row_of()
+    s30 = ref["starts"][row[ref["starts"]] == 30]
+    # start hits in all three segments of the row's id range
+    assert len(np.unique((s30 - cs.row_begin[30]) // 65536)) == 3
+
+
 def test_exact_ties_between_duplicated_clusters():
     """Each cluster has a twin with the same coordinates, so every search of
     the constructor (and every neighbour choice) meets an exact tie, decided

@@ -101,6 +101,37 @@ def test_adjoint_matches_fp64_gradient(kind):
     assert (d <= bound).all()
 
 
+@pytest.mark.timeout(900)
+def test_adjoint_on_the_full_adjoint_workload():
+    """The adjoint workload at full size: a central event of 10^4 primaries
+    and their secondaries with the radial distortion applied, every tracklet
+    of at least 20 clusters refitted through the uncorrected (zero) map.  The
+    refit chi2 and ok flags against the FP64 refit, the gradient against the
+    FP64 gradient of the same weighted sum."""
+    import torch
+    print("case: full adjoint workload (central event seed 5, distorted), theta = 0", flush=True)
+    cs = synth.central_event(seed=5, distortion=synth.RadialDistortion())
+    tk = oracle.select_tracks(oracle.kept_tracklets(oracle.track(cs, n_threads=16)), 20)
+    assert len(tk["n"]) > 50000
+    job, _ = _job(cs, tk)
+    theta = np.zeros(oracle.map_ncoef())
+    chi2 = job.forward(torch.as_tensor(theta, dtype=torch.float32, device="cuda")).cpu().numpy()
+    ok = job.ok[:job.n_tracks].cpu().numpy().astype(bool)
+    want, ok_ref = oracle.refit(cs, tk, theta)
+    np.testing.assert_array_equal(ok, ok_ref)
+    rel = np.abs(chi2[ok] - want[ok]) / np.maximum(want[ok], 1.0)
+    assert rel.max() <= 1e-3, rel.max()
+    w = np.random.default_rng(6).uniform(0.5, 1.5, job.n_tracks) * ok
+    g = job.backward(torch.as_tensor(w, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    want_g = oracle.refit_grad(cs, tk, theta, dL_dchi2=w)
+    err = np.linalg.norm(g - want_g) / np.linalg.norm(want_g)
+    print(f"{ok.sum()} tracks refitted, chi2 max rel {rel.max():.2e}, gradient relative L2 {err:.2e}", flush=True)
+    assert err < 1e-3, err
+    assert (g[want_g == 0.0] == 0.0).all()
+    d = np.abs(g - want_g)
+    assert (d <= 2e-2 * np.abs(want_g) + 2e-3 * np.abs(want_g).max()).all()
+
+
 def test_adjoint_is_deterministic_and_linear_in_weights():
     import torch
     cs, tk = _case(n_primaries=1500)
