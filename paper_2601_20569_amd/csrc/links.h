@@ -19,10 +19,10 @@ namespace tpcx {
 // f_r = (x_r - x_{r-1}) / (x_{r+1} - x_{r-1}) in float.
 //
 // The candidates of each row inside the window are first collected in LDS
-// (their sorted positions; up to kNfD per row), then all pairs are visited in
-// one flat loop, so a wavefront runs max(n_u * n_d) pair steps rather than
-// (scanned up candidates) x max(n_d); the pair loop re-reads the candidates'
-// records, which are in the cache, so the LDS stays small and occupancy high.
+// (their sorted positions; up to kNfD per row), then the down candidates'
+// coordinates are loaded into registers together and every up candidate is
+// evaluated against all of them; the records are re-read from the cache, so
+// the LDS stays small and occupancy high.
 // Caller ids are read only to break an exact tie of D.  A cluster with more
 // than kNfD candidates in a row takes the direct double scan instead.
 constexpr int kNfD = 8;
@@ -31,128 +31,42 @@ constexpr int kNfBlock = 256;
 __device__ __forceinline__ int32_t id_of(const float4& p) { return __float_as_int(p.z); }
 __device__ __forceinline__ int32_t cup_of(const float4& p) { return __float_as_int(p.w); }
 
-// Sorted positions of the window candidates of one row around (yh, zh) into
-// LDS (up to kNfD); returns their number (which may exceed kNfD).  The bin
-// ranges of up to kNfZ z bins are loaded in one round, then the candidates two
-// at a time, so a lane has several loads in flight.
-constexpr int kNfZ = 6;
+// Sorted positions of the window candidates around (yh, zh) of the index
+// range j0 .. j1 appended to the lane's LDS list (up to kNfD; n counts them
+// all): four records in flight at a time.
+__device__ __forceinline__ void nf_take_range(const Grid& g, int32_t j0, int32_t j1, float yh, float zh, float wy,
+                                              float wz, int32_t (*pos)[kNfBlock], int t, int& n) {
+  const float2* yz = reinterpret_cast<const float2*>(g.pts);
+  for (int32_t j = j0; j < j1; j += 4) {
+    float2 v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = yz[2 * int64_t(j + m < j1 ? j + m : j)];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (j + m < j1 && fabsf(v[m].x - yh) <= wy && fabsf(v[m].y - zh) <= wz) {
+        if (n < kNfD) pos[n][t] = j + m;
+        ++n;
+      }
+    }
+  }
+}
 
+// The same over the bin ranges of z bins zb0 .. zb1 (any number), one record
+// at a time: for boxes wider than two z bins.
 __device__ __forceinline__ int nf_collect(const Grid& g, int64_t kb, int ny, int zb0, int zb1, int yb0,
                                           int yb1, float yh, float zh, float wy, float wz,
                                           int32_t (*pos)[kNfBlock], int t) {
   int n = 0;
-  auto take = [&](const float4& pc, int32_t j) {
-    if (!(fabsf(pc.x - yh) <= wy && fabsf(pc.y - zh) <= wz)) return;
-    if (n < kNfD) pos[n][t] = j;
-    ++n;
-  };
-  const int nzb = zb1 - zb0 + 1;
-  if (nzb <= kNfZ) {
-    int32_t s[kNfZ], e[kNfZ];
-#pragma unroll
-    for (int q = 0; q < kNfZ; ++q) {
-      if (q < nzb) {
-        s[q] = g.bin_start[kb + (zb0 + q) * ny + yb0];
-        e[q] = g.bin_start[kb + (zb0 + q) * ny + yb1 + 1];
-      } else {
-        s[q] = e[q] = 0;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kNfZ; ++q) {
-      for (int32_t j = s[q]; j < e[q]; j += 2) {
-        const bool two = j + 1 < e[q];
-        const float4 pa = g.pts[j];
-        const float4 pb = g.pts[two ? j + 1 : j];
-        take(pa, j);
-        if (two) take(pb, j + 1);
-      }
-    }
-    return n;
-  }
   for (int zb = zb0; zb <= zb1; ++zb) {
     const int32_t j0 = g.bin_start[kb + zb * ny + yb0], j1 = g.bin_start[kb + zb * ny + yb1 + 1];
-    for (int32_t j = j0; j < j1; ++j) take(g.pts[j], j);
+    for (int32_t j = j0; j < j1; ++j) {
+      const float4 pc = g.pts[j];
+      if (!(fabsf(pc.x - yh) <= wy && fabsf(pc.y - zh) <= wz)) continue;
+      if (n < kNfD) pos[n][t] = j;
+      ++n;
+    }
   }
   return n;
-}
-
-// Wavefront-cooperative form of nf_collect: the window candidates of all 64
-// lanes' clusters in one row, spread over all lanes.  For each pair of z bins
-// in turn (each lane's box starting at its own zb0), the lanes' candidate
-// ranges are numbered by a prefix sum over the wavefront; lane l evaluates
-// candidates l and l + 64 of every 128, for their owner lane's cluster, and
-// appends those inside the owner's window to the owner's LDS list (an LDS
-// counter per owner).  The order inside a list is free: the pair selection has
-// a total order.  Returns the lane's own count (which may exceed kNfD).  All
-// 64 lanes must call it; `act` marks lanes with a cluster to serve.
-__device__ __forceinline__ int nf_collect_wave(const Grid& g, int64_t kb, int ny, int zb0, int zb1, int yb0,
-                                               int yb1, bool act, float yh, float zh, float wy, float wz,
-                                               int32_t (*pos)[kNfBlock], int32_t* cnt, int t) {
-  const int lane = lane_id();
-  const int wbase = t - lane;
-  cnt[t] = 0;
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  for (int zb = zb0;; zb += 2) {
-    const bool a = act && zb <= zb1;
-    if (__ballot(a) == 0ull) break;
-    int32_t a0 = 0, alen = 0, b0 = 0, n = 0;
-    if (a) {
-      const bool z2 = zb + 1 <= zb1;
-      const int64_t ra = kb + int64_t(zb) * ny;
-      const int64_t rb = z2 ? ra + ny : ra;
-      const int32_t j0 = g.bin_start[ra + yb0], j1 = g.bin_start[ra + yb1 + 1];
-      const int32_t k0 = g.bin_start[rb + yb0], k1 = g.bin_start[rb + yb1 + 1];
-      a0 = j0;
-      alen = j1 - j0;
-      b0 = k0;
-      n = alen + (z2 ? k1 - k0 : 0);
-    }
-    int incl = n;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int v = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += v;
-    }
-    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
-    const int excl = incl - n;
-    for (int t0 = 0; t0 < total; t0 += 2 * kWave) {
-      const int ta = t0 + lane, tb = ta + kWave;
-      int oa = 0, ob = 0;
-#pragma unroll
-      for (int st = kWave / 2; st > 0; st >>= 1) {
-        const int va = __shfl(incl, oa + st - 1, kWave);
-        const int vb = __shfl(incl, ob + st - 1, kWave);
-        if (va <= ta) oa += st;
-        if (vb <= tb) ob += st;
-      }
-      const int ua = ta - __shfl(excl, oa, kWave), ub = tb - __shfl(excl, ob, kWave);
-      // every shuffle with all lanes active (a shuffle reads nothing from a
-      // lane its branch has switched off)
-      const int la = __shfl(alen, oa, kWave), lb = __shfl(alen, ob, kWave);
-      const int aa = __shfl(a0, oa, kWave), ab = __shfl(a0, ob, kWave);
-      const int ba = __shfl(b0, oa, kWave), bb = __shfl(b0, ob, kWave);
-      const int pa = ua < la ? aa + ua : ba + (ua - la);
-      const int pb = ub < lb ? ab + ub : bb + (ub - lb);
-      const bool va = ta < total, vb = tb < total;
-      float4 ca = make_float4(0.0f, 0.0f, 0.0f, 0.0f), cb = ca;
-      if (va) ca = g.pts[pa];
-      if (vb) cb = g.pts[pb];
-      const float ya = __shfl(yh, oa, kWave), za = __shfl(zh, oa, kWave);
-      const float yb = __shfl(yh, ob, kWave), zb_ = __shfl(zh, ob, kWave);
-      if (va && fabsf(ca.x - ya) <= wy && fabsf(ca.y - za) <= wz) {
-        const int slot = atomicAdd(&cnt[wbase + oa], 1);
-        if (slot < kNfD) pos[slot][wbase + oa] = pa;
-      }
-      if (vb && fabsf(cb.x - yb) <= wy && fabsf(cb.y - zb_) <= wz) {
-        const int slot = atomicAdd(&cnt[wbase + ob], 1);
-        if (slot < kNfD) pos[slot][wbase + ob] = pb;
-      }
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    }
-  }
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  return __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // (D, ju, jd) against the best so far under the order (D, id_u, id_d).
@@ -171,8 +85,6 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
                                                          int32_t* __restrict__ down_s) {
   __shared__ int32_t d_pos[kNfD][kNfBlock];
   __shared__ int32_t u_pos[kNfD][kNfBlock];
-  __shared__ int32_t d_cnt[kNfBlock];
-  __shared__ int32_t u_cnt[kNfBlock];
   const int k = int(xcd_block());
   const int r = k % g.n_rows;
   const int64_t b = row_begin[k], e = row_begin[k + 1];
@@ -191,11 +103,8 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
   const int nyu = g.rows[r + 1].ny, nyd = g.rows[r - 1].ny;
   // wavefront-uniform loop: every lane of a wavefront takes part in the
   // cooperative collections, lanes past the row's end without a cluster
-  const int lane = lane_id();
-  for (int64_t i0 = b + (t - lane); i0 < e; i0 += blockDim.x) {
-    const int64_t i = i0 + lane;
-    const bool act = i < e;
-    const float4 ph = act ? g.pts[i] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int64_t i = b + t; i < e; i += blockDim.x) {
+    const float4 ph = g.pts[i];
     const float yh = ph.x, zh = ph.y;
     const float pz = wz + box_pad(zh), py = wy + box_pad(yh);
     const int zu0 = g.zbin(ku, zh - pz), zu1 = g.zbin(ku, zh + pz);
@@ -203,10 +112,26 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
     const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
     const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
 
-    const int nd = nf_collect_wave(g, bd, nyd, zd0, zd1, yd0, yd1, act, yh, zh, wy, wz, d_pos, d_cnt, t);
-    const int nu = nf_collect_wave(g, bu, nyu, zu0, zu1, yu0, yu1, act && nd > 0, yh, zh, wy, wz, u_pos,
-                                   u_cnt, t);
-    if (!act) continue;
+    int nd = 0, nu = 0;
+    if (zd1 - zd0 <= 1 && zu1 - zu0 <= 1) {
+      // the bin ranges of both rows (at most two z bins each) first, then
+      // the candidates
+      const int64_t rd0 = bd + int64_t(zd0) * nyd, rd1 = bd + int64_t(zd1) * nyd;
+      const int64_t ru0 = bu + int64_t(zu0) * nyu, ru1 = bu + int64_t(zu1) * nyu;
+      const int32_t d0s = g.bin_start[rd0 + yd0], d0e = g.bin_start[rd0 + yd1 + 1];
+      const int32_t d1s = g.bin_start[rd1 + yd0], d1e = g.bin_start[rd1 + yd1 + 1];
+      const int32_t u0s = g.bin_start[ru0 + yu0], u0e = g.bin_start[ru0 + yu1 + 1];
+      const int32_t u1s = g.bin_start[ru1 + yu0], u1e = g.bin_start[ru1 + yu1 + 1];
+      nf_take_range(g, d0s, d0e, yh, zh, wy, wz, d_pos, t, nd);
+      if (zd1 > zd0) nf_take_range(g, d1s, d1e, yh, zh, wy, wz, d_pos, t, nd);
+      if (nd > 0) {
+        nf_take_range(g, u0s, u0e, yh, zh, wy, wz, u_pos, t, nu);
+        if (zu1 > zu0) nf_take_range(g, u1s, u1e, yh, zh, wy, wz, u_pos, t, nu);
+      }
+    } else {
+      nd = nf_collect(g, bd, nyd, zd0, zd1, yd0, yd1, yh, zh, wy, wz, d_pos, t);
+      nu = nd > 0 ? nf_collect(g, bu, nyu, zu0, zu1, yu0, yu1, yh, zh, wy, wz, u_pos, t) : 0;
+    }
     float bestD = 0.0f;
     int32_t best_ju = -1, best_jd = -1;
     auto consider = [&](float yu, float zu, int32_t ju, float yd, float zd, int32_t jd) {
@@ -221,17 +146,63 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
       }
     };
     if (nd <= kNfD && nu <= kNfD) {
-      // all (u, d) pairs in one loop: a = up index, c = down index
-      int a = 0, c = 0;
-      for (int q = nu * nd; q > 0; --q) {
-        const int32_t ja = u_pos[a][t], jc = d_pos[c][t];
-        const float4 U = g.pts[ja], Dn = g.pts[jc];
-        consider(U.x, U.y, ja, Dn.x, Dn.y, jc);
-        if (++c == nd) {
-          c = 0;
-          ++a;
-        }
+      // the down candidates' (y, z) into registers first (independent loads,
+      // in flight together), then every up candidate against all of them;
+      // the best down candidate is kept as its LDS slot
+      const float2* yz = reinterpret_cast<const float2*>(g.pts);
+      float ydv[kNfD], zdv[kNfD];
+#pragma unroll
+      for (int c = 0; c < kNfD; ++c) {
+        float2 v = make_float2(0.0f, 0.0f);
+        if (c < nd) v = yz[2 * int64_t(d_pos[c][t])];
+        ydv[c] = v.x;
+        zdv[c] = v.y;
       }
+      int best_c = -1;
+      int32_t ja = 0;
+      float uy = 0.0f, uz = 0.0f;
+      if (nu > 0) {
+        ja = u_pos[0][t];
+        const float2 v = yz[2 * int64_t(ja)];
+        uy = v.x;
+        uz = v.y;
+      }
+      for (int a = 0; a < nu; ++a) {
+        // the next up candidate is loaded while this one is evaluated
+        int32_t jn = ja;
+        float ny = uy, nz = uz;
+        if (a + 1 < nu) {
+          jn = u_pos[a + 1][t];
+          const float2 v = yz[2 * int64_t(jn)];
+          ny = v.x;
+          nz = v.y;
+        }
+#pragma unroll
+        for (int c = 0; c < kNfD; ++c) {
+          if (c < nd) {
+            const float ey = yh - (ydv[c] + (uy - ydv[c]) * f);
+            const float ez = zh - (zdv[c] + (uz - zdv[c]) * f);
+            const float D = ey * ey + ez * ez;
+            if (D <= p.d2max) {
+              bool take = best_ju < 0 || D < bestD;
+              if (!take && D == bestD) {
+                // exact tie: the smaller (id_u, id_d)
+                const int32_t iu = id_of(g.pts[ja]), bu = id_of(g.pts[best_ju]);
+                take = iu != bu ? iu < bu : id_of(g.pts[d_pos[c][t]]) < id_of(g.pts[d_pos[best_c][t]]);
+              }
+              if (take) {
+                bestD = D;
+                best_ju = ja;
+                best_c = c;
+              }
+            }
+          }
+        }
+        ja = jn;
+        uy = ny;
+        uz = nz;
+      }
+      best_jd = best_c >= 0 ? d_pos[best_c][t] : -1;
     } else {
       // more candidates than LDS holds: scan both rows directly
       for (int zb = zu0; zb <= zu1; ++zb) {

@@ -45,6 +45,8 @@ struct tpcx_ctx {
   float* d_frac = nullptr;
   RowInfo* d_rows = nullptr;
   int n_cu = 256;
+  // bin counters of one row that fit the grid build's LDS
+  int max_row_bins = 16384;
   // stage timing: (TPCX_N_STAGES + 1) events per recorded call
   std::vector<hipEvent_t> events;
   int32_t timing_max = 0, timing_used = 0;
@@ -204,9 +206,6 @@ RefitIn refit_view(const tpcx_ctx* c, const tpcx_refit_in* in) {
   return r;
 }
 
-// The bin counters of one row live in LDS during the grid build.
-constexpr int kMaxRowBins = 16384;
-
 int max_row_ny(const tpcx_ctx* c) {
   int m = 1;
   for (const RowInfo& r : c->rows_host) m = std::max(m, r.ny);
@@ -219,7 +218,7 @@ tpcx_tuning effective_tuning(const tpcx_ctx* c, int32_t n_units, int64_t n) {
     tpcx_default_tuning(n_units, n, &t);
     t.bin_y = c->tuning.bin_y;  // the row table is built for this width
   }
-  t.n_zbins = std::max(1, std::min(t.n_zbins, (kMaxRowBins - 1) / max_row_ny(c)));
+  t.n_zbins = std::max(1, std::min(t.n_zbins, (c->max_row_bins - 1) / max_row_ny(c)));
   return t;
 }
 
@@ -314,6 +313,17 @@ tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx
   if (!c) return TPCX_E_HIP;
   c->device = dev;
   c->n_cu = prop.multiProcessorCount;
+  {
+    // the grid build keeps a row's bin counters in LDS: as many as the
+    // device's LDS per workgroup holds (160 KiB on gfx950)
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds > 65536 &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grid_build),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds - 256) == hipSuccess)
+      c->max_row_bins = (lds - 256) / int(sizeof(int32_t)) - 1;
+    (void)hipGetLastError();
+  }
   c->n_rows = g->n_rows;
   c->row_x.assign(g->row_x_host, g->row_x_host + g->n_rows);
   c->tan_half = g->tan_half_opening;
@@ -527,7 +537,7 @@ constexpr int kAutotuneKnobs = 6;
 std::vector<tpcx_tuning> autotune_candidates(const tpcx_ctx* c, const tpcx_tuning& b, int knob) {
   std::vector<tpcx_tuning> v;
   auto add = [&](tpcx_tuning t) {
-    t.n_zbins = std::max(1, std::min(t.n_zbins, (kMaxRowBins - 1) / max_row_ny(c)));
+    t.n_zbins = std::max(1, std::min(t.n_zbins, (c->max_row_bins - 1) / max_row_ny(c)));
     if (!valid_tuning(t) || std::memcmp(&t, &b, sizeof t) == 0) return;
     for (const tpcx_tuning& u : v)
       if (std::memcmp(&t, &u, sizeof t) == 0) return;
