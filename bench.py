@@ -167,10 +167,12 @@ def order_rows_by_z(rb, y, z):
     return y[order].contiguous(), z[order].contiguous()
 
 
-def make_tracker(n_units, n):
+def make_tracker(n_units, n, bin_y=None):
     import paper_2601_20569_amd as px
     from synth import geometry as G
     tuning = px.default_tuning(n_units, n)
+    if bin_y is not None:  # the grid's y-bin width is fixed when the context is made
+        tuning.bin_y = float(bin_y)
     return px.SectorTracker(G.row_x(), G.tan_half_opening(), G.BZ_TESLA, tuning=tuning)
 
 
@@ -412,7 +414,8 @@ def main():
         B = dict(sectors=first.unit_sector, slices=[(0, N, first.row_begin.copy())])
     log(f"input: {N} clusters in {U} sector units ({time.perf_counter() - t0:.1f} s)")
 
-    tr = make_tracker(U, N)
+    fixed = json.loads(args.tuning) if args.tuning else None
+    tr = make_tracker(U, N, fixed.get("bin_y") if fixed else None)
     n_start, n_tracks, n_hits = size_run(tr, rb, y, z, U)
     log(f"tracklets: {n_start} start hits, {n_tracks} kept, {n_hits} attached clusters")
     alpha = torch.as_tensor(G.sector_alpha(B["sectors"]).astype(np.float32), device=dev)

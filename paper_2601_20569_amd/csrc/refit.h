@@ -167,6 +167,43 @@ __device__ __forceinline__ void map_displacement(const Theta& th, const Weights4
   }
 }
 
+// The same with the z sums already formed: for a map evaluated at one fixed
+// z, th(i, j) holds, per component, the sum over the four z nodes of the
+// coefficients times the z weights, accumulated in the order above, so the
+// result equals map_displacement's bit for bit.
+template <class ThetaZ>
+__device__ __forceinline__ void map_displacement_zsum(const ThetaZ& th, const Weights4& wp, const Weights4& wr,
+                                                      float d[3]) {
+  d[0] = d[1] = d[2] = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
+    float e0 = 0.0f, e1 = 0.0f, e2 = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = min(max(wr.first + b, 0), kMapNR - 1);
+      const float4 f = th(i, j);
+      e0 = __builtin_fmaf(f.x, wr.w[b], e0);
+      e1 = __builtin_fmaf(f.y, wr.w[b], e1);
+      e2 = __builtin_fmaf(f.z, wr.w[b], e2);
+    }
+    d[0] = __builtin_fmaf(e0, wp.w[a], d[0]);
+    d[1] = __builtin_fmaf(e1, wp.w[a], d[1]);
+    d[2] = __builtin_fmaf(e2, wp.w[a], d[2]);
+  }
+}
+
+// z sums (see map_displacement_zsum) of the staged kStageNPhi x kStageNR
+// (phi, r) nodes, in LDS.
+struct ThetaZStaged {
+  const float4* lds;
+  int i_lo, j_lo;
+  __device__ __forceinline__ float4 operator()(int i, int j) const {
+    const int si = (i - i_lo + kMapNPhi) % kMapNPhi;
+    return lds[si * kStageNR + (j - j_lo)];
+  }
+};
+
 // Corrected cluster as (x_c, y_c, z_m, delta z): z_c = z_m + delta z is not
 // formed here, because z_m can be large (drift coordinate in a time frame)
 // and the refit works in z relative to its first cluster (rel_z).
@@ -321,7 +358,9 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_hits(RefitIn in, const 
 // coefficient array.  Both give the same arithmetic as correct_cluster.
 // z_fixed: the map is evaluated at z = z_map for every cluster (time-frame
 // input, whose drift coordinate is not z); the correction delta z still
-// applies to the measured z.
+// applies to the measured z.  Then the block forms the z sums of its staged
+// (phi, r) nodes once, and a cluster sums 16 nodes instead of 64 (the same
+// result, bit for bit).
 __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     int n_rows, const int64_t* __restrict__ row_begin, const float* __restrict__ y,
     const float* __restrict__ z, const float* __restrict__ unit_alpha,
@@ -349,6 +388,39 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
     ts.i_lo = (int(floorf(ph / kMapDPhi)) - 1 + kMapNPhi) % kMapNPhi;
     ts.j_lo = min(max(int(floorf((x - kMapR0) / kMapDR)) - 1, 0), kMapNR - kStageNR);
   }
+  if (z_fixed) {
+    // one z for every cluster: the z sums of the staged (phi, r) nodes once
+    const Weights4 wz = weights_lin(z_map, kMapZ0, 1.0f / kMapDZ, kMapNZ);
+    for (int q = threadIdx.x; q < kStageNPhi * kStageNR; q += kRefitBlock) {
+      const int j = ts.j_lo + q % kStageNR;
+      const int i = (ts.i_lo + q / kStageNR) % kMapNPhi;
+      float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+#pragma unroll
+      for (int cz = 0; cz < 4; ++cz) {
+        const int k = min(max(wz.first + cz, 0), kMapNZ - 1);
+        const float4 v = ThetaGlobal{theta}(i, j, k);
+        f0 = __builtin_fmaf(v.x, wz.w[cz], f0);
+        f1 = __builtin_fmaf(v.y, wz.w[cz], f1);
+        f2 = __builtin_fmaf(v.z, wz.w[cz], f2);
+      }
+      stage[q] = make_float4(f0, f1, f2, 0.0f);
+    }
+    __syncthreads();
+    const ThetaZStaged tz{stage, ts.i_lo, ts.j_lo};
+    for (int64_t c = row_begin[ur] + threadIdx.x; c < e; c += kRefitBlock) {
+      float r;
+      const HitGeom h = hit_geom(x, y[c], z[c], alpha, &r);
+      const Weights4 wp = weights_phi(h.phi);
+      const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
+      float d[3];
+      if (ts.covers(wp.first, wr.first))
+        map_displacement_zsum(tz, wp, wr, d);
+      else
+        map_displacement(ThetaGlobal{theta}, wp, wr, wz, d);
+      corr[c] = apply_displacement(h, d);
+    }
+    return;
+  }
   for (int q = threadIdx.x; q < kStageNodes; q += kRefitBlock) {
     const int k = q % kMapNZ;
     const int j = ts.j_lo + (q / kMapNZ) % kStageNR;
@@ -375,9 +447,9 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
 // else xyz[q].  Persistent; every lane runs one track at a time.  Idle lanes
 // take new tracks, `refill` or more at a time, from a wavefront-private
 // chunk of kRefitChunk consecutive tracks refilled from kXcds device queues, so
-// lanes do not wait for the longest track of their wavefront.  The cluster of
-// the next step is loaded one step ahead (and its index two steps ahead), so
-// the loads overlap the arithmetic of the current step.  Which lane runs a
+// lanes do not wait for the longest track of their wavefront.  The clusters of
+// the next two steps are loaded ahead (and the index of the one after), so
+// the loads overlap the arithmetic of the current steps.  Which lane runs a
 // track does not change its result.  Checkpoints (every kCkpt clusters) are
 // written when ckpt is set.
 constexpr int kRefitChunk = 64;
@@ -397,7 +469,8 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
   float chi2 = 0.0f, zref = 0.0f;
   KState q{};
   float4 hn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // corrected cluster of hit i
-  int64_t idn = 0;                                  // xyz index of hit i + 1
+  float4 hn2 = hn;                                  // and of hit i + 1
+  int64_t idn = 0;                                  // xyz index of hit i + 2
   auto xyz_index = [&](int64_t qh) -> int64_t { return by_cluster ? int64_t(in.hit_id[qh]) : qh; };
   while (true) {
     const int nidle = __popcll(__ballot(t < 0));
@@ -447,7 +520,8 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
             i = 1;
             chi2 = 0.0f;
             hn = xyz[xyz_index(hb + 1)];
-            idn = n > 2 ? xyz_index(hb + 2) : 0;
+            if (n > 2) hn2 = xyz[xyz_index(hb + 2)];
+            idn = n > 3 ? xyz_index(hb + 3) : 0;
           }
         }
         chunk += min(int64_t(__popcll(want)), avail);
@@ -455,8 +529,9 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
     }
     if (t >= 0) {
       const float4 h = hn;
-      if (i + 1 < n) hn = xyz[idn];
-      if (i + 2 < n) idn = xyz_index(hb + i + 2);
+      hn = hn2;
+      if (i + 2 < n) hn2 = xyz[idn];
+      if (i + 3 < n) idn = xyz_index(hb + i + 3);
       const bool ok = refit_step(q, h.x, h.y, rel_z(h, zref), p, &chi2);
       if (ok && ckpt && i % kCkpt == 0) store_state(ckpt + (cb + i / kCkpt) * kCkptFloats, q);
       ++i;
