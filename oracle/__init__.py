@@ -22,7 +22,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tpc_oracle.cpp")
 SOURCES = [SRC, os.path.join(HERE, "tpc_refit.cpp"), os.path.join(HERE, "tpc_select.cpp"),
-           os.path.join(HERE, "tpc_fit.cpp"), os.path.join(HERE, "tpc_rebuild.cpp")]
+           os.path.join(HERE, "tpc_fit.cpp"), os.path.join(HERE, "tpc_rebuild.cpp"),
+           os.path.join(HERE, "tpc_merge.cpp")]
 HEADERS = [os.path.join(HERE, "kalman.h")]
 LIB = os.path.join(HERE, "libtpc_oracle.so")
 
@@ -111,6 +112,10 @@ def lib():
                               ctypes.c_float, ctypes.c_float, ctypes.c_int64] + [P] * 14
         L.orc_rebuild.argtypes = [ctypes.c_int, P, ctypes.c_int, P] + [ctypes.c_float] * 5 + [
             ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64] + [P] * 17
+        L.orc_merge_views.restype = ctypes.c_int
+        L.orc_merge_views.argtypes = [P, P, ctypes.c_int, ctypes.c_int64, P, P, P, P]
+        L.orc_merge.restype = ctypes.c_int
+        L.orc_merge.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32] + [P] * 9
         L.orc_select.restype = ctypes.c_int64
         L.orc_select.argtypes = [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
                                  ctypes.c_int32, P, P]
@@ -449,4 +454,73 @@ def rebuild(cs, tk, precision=32, params: Params | None = None, row_x=None, **kw
                       _p(a["rb"]), _p(a["y"]), _p(a["z"]), _p(out["assigned"]), _p(out["param"]), _p(out["cov"]),
                       _p(out["chi2"]), _p(out["x_out"]), _p(out["n_kept"]), _p(out["ok"]))
     out["ok"] = out["ok"].astype(bool)
+    return out
+
+
+class OrcMergeParams(ctypes.Structure):
+    _fields_ = [("x_m", ctypes.c_float), ("cos_h", ctypes.c_float), ("sin_h", ctypes.c_float),
+                ("tol", ctypes.c_float * 5), ("chi2_cut", ctypes.c_float), ("cross_electrode", ctypes.c_int32)]
+
+
+# merging: views at the plane between the pad rows, tolerances of (y, z,
+# sin phi, dz/ds, q/pT) and the chi2 cut (readings; the paper gives none)
+MERGE_DEFAULTS = dict(x_m=165.0, tol=(1.0, 1.0, 0.02, 0.02, 0.1), chi2_cut=25.0, cross_electrode=True)
+
+
+def merge_params(**kw):
+    """The merging parameters as the C struct; cos/sin of half the sector
+    opening are rounded once from double."""
+    import math
+    from synth import geometry as G
+    f = dict(MERGE_DEFAULTS, **kw)
+    return OrcMergeParams(float(f["x_m"]), math.cos(G.HALF_OPENING_RAD), math.sin(G.HALF_OPENING_RAD),
+                          (ctypes.c_float * 5)(*f["tol"]), float(f["chi2_cut"]), int(bool(f["cross_electrode"])))
+
+
+def unit_neighbours(unit_sector, unit_group=None):
+    """[n_units, 3]: the unit of the next sector of the same half, of the
+    previous one, and of the same azimuth across the central electrode, in the
+    same group (time-frame slice), -1 where there is none."""
+    from synth import geometry as G
+    sec = np.asarray(unit_sector, dtype=np.int64)
+    grp = np.zeros(len(sec), np.int64) if unit_group is None else np.asarray(unit_group, dtype=np.int64)
+    S = G.SECTORS_PER_SIDE
+    where = {(int(g), int(s)): u for u, (g, s) in enumerate(zip(grp, sec))}
+    nbr = -np.ones((len(sec), 3), np.int32)
+    for u, (g, s) in enumerate(zip(grp, sec)):
+        side, loc = divmod(int(s), S)
+        for k, other in enumerate((side * S + (loc + 1) % S, side * S + (loc - 1) % S, (1 - side) * S + loc)):
+            nbr[u, k] = where.get((int(g), other), -1)
+    return nbr
+
+
+def merge_views(tk, precision=64, params: Params | None = None, **kw):
+    """Views [n, 3, 5] and their flags [n, 3] of the tracks in tk (param at
+    xref, in their sector frames)."""
+    params = params or Params()
+    n = len(tk["param"])
+    prm = np.ascontiguousarray(tk["param"], dtype=np.float32)
+    xr = np.ascontiguousarray(tk["xref"], dtype=np.float32)
+    views = np.zeros((n, 3, 5))
+    ok = np.zeros((n, 3), np.uint8)
+    ps, mp = params.c_struct(), merge_params(**kw)
+    lib().orc_merge_views(ctypes.byref(ps), ctypes.byref(mp), precision, n, _p(prm), _p(xr), _p(views), _p(ok))
+    return views, ok.astype(bool)
+
+
+def merge(tk, unit_nbr, n_units, params: Params | None = None, **kw):
+    """Track merging (FP32 decisions) of the tracks in tk (unit order; param
+    at xref; r_in, r_out).  Returns prev, next, root."""
+    params = params or Params()
+    n = len(tk["param"])
+    a = dict(unit=np.ascontiguousarray(tk["unit"], dtype=np.int32),
+             prm=np.ascontiguousarray(tk["param"], dtype=np.float32),
+             xr=np.ascontiguousarray(tk["xref"], dtype=np.float32),
+             r_in=np.ascontiguousarray(tk["r_in"], dtype=np.int32),
+             r_out=np.ascontiguousarray(tk["r_out"], dtype=np.int32),
+             nbr=np.ascontiguousarray(unit_nbr, dtype=np.int32))
+    out = {k: np.zeros(n, np.int32) for k in ("prev", "next", "root")}
+    ps, mp = params.c_struct(), merge_params(**kw)
+    lib().orc_merge(ctypes.byref(ps), ctypes.byref(mp), n, int(n_units), _p(a["unit"]), _p(a["prm"]), _p(a["xr"]),
+                    _p(a["r_in"]), _p(a["r_out"]), _p(a["nbr"]), _p(out["prev"]), _p(out["next"]), _p(out["root"]))
     return out
