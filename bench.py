@@ -52,6 +52,7 @@ B_SEL_PER_CLUSTER = 20         # owner key written and read (8 + 8), assignment 
 B_RB_PER_TRACK = 160           # rebuild: seed, rank inputs, offsets read; results written
 B_RB_PER_HIT = 5               # id + row of every input cluster
 B_RB_PER_CLUSTER = 32          # grid build (24) and the holder word (8) of every cluster
+B_MERGE_PER_TRACK = 48        # merging: unit, param, x_ref, first and last row read; prev, next, root written
 B_FIT_PER_TRACK = 128          # fit: seed, x_ref, offsets read; parameters, covariance, chi2, counts written
 B_FIT_PER_HIT = 62             # id, row, y, z read; 16-byte record written once and read twice; flag written
 
@@ -238,7 +239,8 @@ def cpu_model():
     return "unknown"
 
 
-def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, stream, row_begin_t):
+def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, stream, row_begin_t, unit_sector,
+               unit_group, cross_electrode):
     """The steps after the sector tracking on its output: ambiguity solving
     (every tracklet of the batch), the rebuild of the kept tracklets of the
     first slice, and the three-iteration fit with interpolation rejection
@@ -258,6 +260,29 @@ def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, str
     res["select"] = dict(ms=round(ms, 3), tracklets=n_tracks, kept=kept, shared="10%", alg_bytes=int(b),
                          GBs=round(b / (ms * 1e-3) / 1e9, 2), frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
     log(f"ambiguity solving: {ms:.3f} ms, {kept} of {n_tracks} tracklets kept")
+    # merging of the kept tracklets of the whole batch (units of one slice)
+    import paper_2601_20569_amd as px
+    kidx = sel["keep"][:n_tracks].bool().nonzero().squeeze(1)
+    hb0 = o["hit_begin"][:n_tracks][kidx]
+    margs = (o["unit"][:n_tracks][kidx].contiguous(), o["param"][:n_tracks][kidx].contiguous(),
+             o["x_ref"][:n_tracks][kidx].contiguous(), o["hit_row"][hb0].to(torch.int32).contiguous(),
+             o["hit_row"][hb0 + o["n_hits"][:n_tracks][kidx].to(torch.int64) - 1].to(torch.int32).contiguous(),
+             torch.as_tensor(px.unit_neighbours(unit_sector, unit_group), device=y.device), n_units)
+    del hb0
+    with torch.cuda.stream(stream):
+        r = tr.merge(*margs, cross_electrode=cross_electrode, stream=stream)
+        sync()
+        del r
+        ms = timed(lambda: tr.merge(*margs, cross_electrode=cross_electrode, stream=stream), steps, stream)
+        r = tr.merge(*margs, cross_electrode=cross_electrode, stream=stream)
+        sync()
+    nk = len(kidx)
+    b = B_MERGE_PER_TRACK * nk
+    links = int((r["next"] >= 0).sum())
+    res["merge"] = dict(ms=round(ms, 3), tracks=nk, links=links, cross_electrode=cross_electrode, alg_bytes=int(b),
+                        GBs=round(b / (ms * 1e-3) / 1e9, 2), frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
+    log(f"merging: {ms:.3f} ms, {nk} tracks, {links} links")
+    del r, margs, kidx
     # the rebuild (Phase II) of the kept tracklets of the first slice (36 units)
     u1 = min(n_units, 36)
     keep = sel["keep"][:n_tracks].bool() & (o["unit"][:n_tracks] < u1)
@@ -482,7 +507,13 @@ def main():
         forms["batched_tracking_only_ms"] = round(track_ms, 3)
         log(f"batched graph without the refit: {track_ms:.3f} ms/step")
     if not args.no_next:
-        forms.update(next_steps(tr, bufs, U, N, n_tracks, n_hits, y, z, args.steps, stream, rb))
+        groups = None
+        if len(B["slices"]) > 1:
+            per = [len(sl[2]) - 1 for sl in B["slices"]]  # rows of each slice
+            groups = np.repeat(np.arange(len(per)), np.array(per) // G.N_ROWS)
+        # a time frame's drift coordinate is not z: no merging across the electrode
+        forms.update(next_steps(tr, bufs, U, N, n_tracks, n_hits, y, z, args.steps, stream, rb, B["sectors"],
+                                groups, not cfg["workload"].startswith("timeframe")))
     del bufs
     torch.cuda.empty_cache()
 

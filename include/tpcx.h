@@ -370,8 +370,10 @@ typedef struct {
   uint8_t* reject;  /* [n_hits] 1: cluster rejected */
 } tpcx_fit_out;
 
-/* Workspace of tpcx_fit: 16 bytes per hit (the stored iteration-1 record). */
-size_t tpcx_fit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_hits);
+/* Workspace of tpcx_fit: 16 bytes per hit (the stored iteration-1 record)
+ * and 4 bytes per track (the processing order: longest tracks first within
+ * chunks of consecutive tracks).  n_tracks < 2^31. */
+size_t tpcx_fit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_tracks, int64_t n_hits);
 
 /* Enqueues the fit of every track of `in`; ws 256-byte aligned. */
 tpcx_status tpcx_fit(tpcx_ctx* ctx, const tpcx_fit_in* in, const tpcx_fit_params* params,
@@ -451,6 +453,67 @@ size_t tpcx_rebuild_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_
 tpcx_status tpcx_rebuild(tpcx_ctx* ctx, const tpcx_clusters* clusters, const tpcx_rebuild_in* in,
                          const tpcx_rebuild_params* params, const tpcx_rebuild_out* out, void* ws,
                          size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Track merging (paper, Section 2: the track segments of the sector tracking
+ * are merged inside a sector, between adjacent sectors of one TPC half and
+ * across the central electrode).  The paper gives no matching criterion;
+ * this one:
+ *   views  each track's state (param at x_ref, in its sector frame) is
+ *          carried to the plane x = x_m in its own frame (view 0) and in the
+ *          frames of the boundaries with the next (view 1: rotated by -h
+ *          about the beam axis, h = half the sector opening) and the
+ *          previous sector of its half (view 2: +h), with the tracking's
+ *          circle step in equal steps of at most 10 cm; a view is missing
+ *          when |sin(phi)| (before or after the rotation) or a step meets the
+ *          tracking's propagation guards;
+ *   pairs  a (inner) and b (outer), r_out[a] < r_in[b], in the same unit
+ *          (views 0, 0), in the units of one azimuth across the electrode
+ *          (0, 0; when cross_electrode), or in adjacent sectors (a's view
+ *          towards b's sector against b's view towards a's: 1 against 2 when
+ *          b's unit is a's next, 2 against 1 when it is the previous);
+ *   chi2   sum over (y, z, sin(phi), dz/ds, q/pT) of (difference)^2 /
+ *          tol^2, in this order, IEEE binary32; candidates at chi2 <= cut;
+ *   links  a's best outer candidate and b's best inner candidate by (chi2,
+ *          track index); a and b are linked when each is the other's.
+ * Outputs per track: next (its outer partner), prev (its inner partner), -1
+ * for none, and root (the first track of its chain).  A track whose unit is
+ * outside 0 .. n_units - 1 or whose rows are not 0 <= r_in <= r_out < 256
+ * links to nothing.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  float x_m;              /* plane of the views [cm] */
+  float cos_h, sin_h;     /* cos and sin of half the sector opening */
+  float tol[5];           /* tolerances of y, z [cm], sin(phi), dz/ds, q/pT [(GeV/c)^-1] */
+  float chi2_cut;
+  int32_t cross_electrode;
+} tpcx_merge_params;
+
+typedef struct {
+  int64_t n_tracks;          /* < 2^31 */
+  int32_t n_units;
+  const int32_t* unit;       /* [n_tracks], ascending */
+  const float* param;        /* [n_tracks][5] at x_ref, sector frame */
+  const float* x_ref;        /* [n_tracks] */
+  const int32_t* r_in;       /* [n_tracks] first row */
+  const int32_t* r_out;      /* [n_tracks] last row */
+  const int32_t* unit_nbr;   /* [n_units][3]: unit of the next sector of the same half,
+                                of the previous one, across the electrode; -1: none */
+} tpcx_merge_in;
+
+typedef struct {
+  int32_t* prev;  /* [n_tracks] */
+  int32_t* next;  /* [n_tracks] */
+  int32_t* root;  /* [n_tracks] */
+} tpcx_merge_out;
+
+/* Workspace of tpcx_merge: 128 bytes per track and 12 KiB per unit. */
+size_t tpcx_merge_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64_t n_tracks);
+
+/* Enqueues the merging of the tracks `in` (device arrays); ws 256-byte
+ * aligned. */
+tpcx_status tpcx_merge(tpcx_ctx* ctx, const tpcx_merge_in* in, const tpcx_merge_params* params,
+                       const tpcx_merge_out* out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Tuning and autotuning.  No tuning changes any result (every selection of

@@ -108,6 +108,21 @@ class RebuildOutput(ctypes.Structure):
                 ("ok", ctypes.c_void_p)]
 
 
+class MergeParams(ctypes.Structure):
+    _fields_ = [("x_m", ctypes.c_float), ("cos_h", ctypes.c_float), ("sin_h", ctypes.c_float),
+                ("tol", ctypes.c_float * 5), ("chi2_cut", ctypes.c_float), ("cross_electrode", ctypes.c_int32)]
+
+
+class MergeInput(ctypes.Structure):
+    _fields_ = [("n_tracks", ctypes.c_int64), ("n_units", ctypes.c_int32), ("unit", ctypes.c_void_p),
+                ("param", ctypes.c_void_p), ("x_ref", ctypes.c_void_p), ("r_in", ctypes.c_void_p),
+                ("r_out", ctypes.c_void_p), ("unit_nbr", ctypes.c_void_p)]
+
+
+class MergeOutput(ctypes.Structure):
+    _fields_ = [("prev", ctypes.c_void_p), ("next", ctypes.c_void_p), ("root", ctypes.c_void_p)]
+
+
 class BatchRefit(ctypes.Structure):
     _fields_ = [("min_hits", ctypes.c_int32), ("map_z_fixed", ctypes.c_int32), ("map_z", ctypes.c_float),
                 ("theta", ctypes.c_void_p),
@@ -165,7 +180,7 @@ def lib():
                                          ctypes.c_int64, ctypes.POINTER(Tracks),
                                          ctypes.POINTER(BatchRefit), P]
         L.tpcx_track_batched.restype = ctypes.c_int32
-        L.tpcx_fit_workspace_bytes.argtypes = [P, ctypes.c_int64]
+        L.tpcx_fit_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.c_int64]
         L.tpcx_fit_workspace_bytes.restype = ctypes.c_size_t
         L.tpcx_fit.argtypes = [P, ctypes.POINTER(FitInput), ctypes.POINTER(FitParams),
                                ctypes.POINTER(FitOutput), P, ctypes.c_size_t, P]
@@ -176,6 +191,11 @@ def lib():
                                    ctypes.POINTER(RebuildParams), ctypes.POINTER(RebuildOutput), P,
                                    ctypes.c_size_t, P]
         L.tpcx_rebuild.restype = ctypes.c_int32
+        L.tpcx_merge_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
+        L.tpcx_merge_workspace_bytes.restype = ctypes.c_size_t
+        L.tpcx_merge.argtypes = [P, ctypes.POINTER(MergeInput), ctypes.POINTER(MergeParams),
+                                 ctypes.POINTER(MergeOutput), P, ctypes.c_size_t, P]
+        L.tpcx_merge.restype = ctypes.c_int32
         L.tpcx_select_workspace_bytes.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
         L.tpcx_select_workspace_bytes.restype = ctypes.c_size_t
         L.tpcx_select.argtypes = [P, ctypes.POINTER(Tracks), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
@@ -201,6 +221,25 @@ def lib():
 def _check(st, what):
     if st != TPCX_OK:
         raise TpcxError(f"{what}: {lib().tpcx_strerror(st).decode()} ({st})")
+
+
+def unit_neighbours(unit_sector, unit_group=None, sectors_per_side=18):
+    """[n_units, 3] int32 (numpy): for every unit, the unit of the next
+    sector of the same half, of the previous one, and of the same azimuth
+    across the central electrode, within the same group (time-frame slice);
+    -1 where there is none.  Sectors 0 .. S-1 are one half, S .. 2S-1 the
+    other, in the same azimuthal order."""
+    import numpy as np
+    sec = [int(s) for s in unit_sector]
+    grp = [0] * len(sec) if unit_group is None else [int(g) for g in unit_group]
+    S = int(sectors_per_side)
+    index = {(g, s): u for u, (g, s) in enumerate(zip(grp, sec))}
+    nbr = np.full((len(sec), 3), -1, np.int32)
+    for u, (g, s) in enumerate(zip(grp, sec)):
+        half, k = divmod(s, S)
+        nbr[u] = [index.get((g, half * S + (k + 1) % S), -1), index.get((g, half * S + (k - 1) % S), -1),
+                  index.get((g, (1 - half) * S + k), -1)]
+    return nbr
 
 
 def default_tuning(n_units, n_clusters):
@@ -252,6 +291,7 @@ class SectorTracker:
         self.params = params or MethodParams()
         self.row_x = np.ascontiguousarray(row_x, dtype=np.float32)
         self.n_rows = len(self.row_x)
+        self.tan_half = float(tan_half_opening)
         g = Geometry(self.n_rows, self.row_x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
                      float(tan_half_opening), float(bz))
         p = self.params.c_struct()
@@ -379,7 +419,7 @@ class SectorTracker:
                    n_kept=torch.zeros(max(n, 1), dtype=i32, device=dev),
                    ok=torch.zeros(max(n, 1), dtype=i32, device=dev),
                    reject=torch.zeros(max(nh, 1), dtype=torch.uint8, device=dev))
-        nb = int(lib().tpcx_fit_workspace_bytes(self._h, nh))
+        nb = int(lib().tpcx_fit_workspace_bytes(self._h, n, nh))
         ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         off = (-ws.data_ptr()) % 256
         fi = FitInput(n, nh, _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(seed), _ptr(x_ref), _ptr(y),
@@ -430,6 +470,40 @@ class SectorTracker:
         _check(lib().tpcx_rebuild(self._h, ctypes.byref(cl), ctypes.byref(ri), ctypes.byref(rp), ctypes.byref(ro),
                                   ctypes.c_void_p(ws.data_ptr() + off), nb, ctypes.c_void_p(s.cuda_stream)),
                "tpcx_rebuild")
+        res = {k: v[:n] for k, v in out.items()}
+        res["_ws"] = ws
+        return res
+
+    def merge(self, unit, param, x_ref, r_in, r_out, unit_nbr, n_units, x_m=165.0,
+              tol=(1.0, 1.0, 0.02, 0.02, 0.1), chi2_cut=25.0, cross_electrode=True, half_opening=None,
+              stream=None):
+        """Track merging (tpcx_merge) of the tracks given by device tensors
+        (unit ascending; param at x_ref in the sector frame; first and last
+        row); unit_nbr [n_units, 3] int32 on the device; half_opening: half
+        the sector opening in radians (default: from the geometry's tangent).
+        Returns a dict of device tensors prev, next, root (no sync)."""
+        import math
+
+        import torch
+        n = int(unit.numel())
+        for v, dt in ((unit, torch.int32), (param, torch.float32), (x_ref, torch.float32), (r_in, torch.int32),
+                      (r_out, torch.int32), (unit_nbr, torch.int32)):
+            if v.dtype != dt or not v.is_cuda or not v.is_contiguous():
+                raise TpcxError("merge inputs must be contiguous device tensors of the documented types")
+        dev = unit.device
+        m = max(n, 1)
+        out = {k: torch.empty(m, dtype=torch.int32, device=dev) for k in ("prev", "next", "root")}
+        nb = int(lib().tpcx_merge_workspace_bytes(self._h, int(n_units), n))
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        h = math.atan(self.tan_half) if half_opening is None else float(half_opening)
+        mp = MergeParams(x_m, math.cos(h), math.sin(h), (ctypes.c_float * 5)(*tol), chi2_cut, int(bool(cross_electrode)))
+        mi = MergeInput(n, int(n_units), _ptr(unit), _ptr(param), _ptr(x_ref), _ptr(r_in), _ptr(r_out), _ptr(unit_nbr))
+        mo = MergeOutput(*[_ptr(out[k]) for k in ("prev", "next", "root")])
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(lib().tpcx_merge(self._h, ctypes.byref(mi), ctypes.byref(mp), ctypes.byref(mo),
+                                ctypes.c_void_p(ws.data_ptr() + off), nb, ctypes.c_void_p(s.cuda_stream)),
+               "tpcx_merge")
         res = {k: v[:n] for k, v in out.items()}
         res["_ws"] = ws
         return res

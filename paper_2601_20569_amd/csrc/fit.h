@@ -5,7 +5,8 @@
 // the first, inward iteration stores, the second, outward one interpolates
 // and cuts, the third applies the rejection).
 //
-// One lane per track.  Iteration 1 walks from the tracking result at x_ref
+// One lane per track, tracks taken longest first within chunks of
+// consecutive tracks (so the lanes of a wavefront have equal work).  Iteration 1 walks from the tracking result at x_ref
 // out to the outermost cluster, restarts there (y, z of the cluster, diagonal
 // covariance) and goes inwards; at every cluster it stores, per hit, the
 // cluster relative to the track's origin (its outermost cluster) and the
@@ -19,6 +20,7 @@
 // reproducible bit for bit.
 #pragma once
 
+#include "order.h"
 #include "tpcx_common.h"
 #include "tracklet.h"
 
@@ -95,10 +97,11 @@ __device__ __forceinline__ float fit_czz(const KState& q) {
 }
 
 // rec[q] = (cluster y, z relative to the origin, bf16 (d_y | d_z), bf16 (C_yy | C_zz)).
-__global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts f, float4* __restrict__ rec,
-                                               FitOut out) {
-  const int64_t t = int64_t(blockIdx.x) * kWave + threadIdx.x;
-  if (t >= in.n_tracks) return;
+__global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts f, const int32_t* __restrict__ order,
+                                               float4* __restrict__ rec, FitOut out) {
+  const int64_t gid = int64_t(blockIdx.x) * kWave + threadIdx.x;
+  if (gid >= in.n_tracks) return;
+  const int64_t t = order[gid];
   const int64_t b = in.hit_begin[t];
   const int n = int(in.hit_begin[t + 1] - b);
   float4* R = rec + b;
@@ -131,11 +134,18 @@ __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts 
       q.z = 0.0f;
       fit_reset_cov(q, p, f);
       R[n - 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      // the cluster of the next step is loaded one step ahead
+      int32_t cn = in.hit_id[b + n - 2];
+      float yn = in.y[cn], zn = in.z[cn];
       for (int i = n - 2; i >= 0 && good; --i) {
+        const float ry = yn - oy, rz = zn - oz;
+        if (i > 0) {
+          cn = in.hit_id[b + i - 1];
+          yn = in.y[cn];
+          zn = in.z[cn];
+        }
         good = fit_prop(q, X(i), p);
         if (!good) break;
-        const int32_t c = in.hit_id[b + i];
-        const float ry = in.y[c] - oy, rz = in.z[c] - oz;
         const uint32_t dd = bf16_bits(q.y - ry) | (bf16_bits(q.z - rz) << 16);
         const uint32_t cc = bf16_bits(fit_cyy(q)) | (bf16_bits(fit_czz(q)) << 16);
         R[i] = make_float4(ry, rz, __uint_as_float(dd), __uint_as_float(cc));

@@ -17,6 +17,7 @@
 #include "select.h"
 #include "fit.h"
 #include "rebuild.h"
+#include "merge.h"
 #include "tpcx_common.h"
 #include "tracklet.h"
 
@@ -926,10 +927,11 @@ tpcx_status tpcx_timing_read(tpcx_ctx* c, float* ms_host, int32_t* n_calls) {
   return TPCX_OK;
 }
 
-size_t tpcx_fit_workspace_bytes(const tpcx_ctx* c, int64_t n_hits) {
-  if (!c || n_hits < 0) return 0;
+size_t tpcx_fit_workspace_bytes(const tpcx_ctx* c, int64_t n_tracks, int64_t n_hits) {
+  if (!c || n_tracks < 0 || n_hits < 0) return 0;
   Carver cv{nullptr};
   cv.take<float4>(n_hits);
+  cv.take<int32_t>(n_tracks);
   return cv.off;
 }
 
@@ -943,8 +945,10 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   if (!(fp->chi2_cut >= 0.0f) || !(fp->var_s > 0.0f) || !(fp->var_t > 0.0f) || !(fp->var_w > 0.0f))
     return TPCX_E_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  if (in->n_tracks >= (int64_t(1) << 31)) return TPCX_E_ARG;
   Carver cv{static_cast<char*>(ws)};
   auto* rec = cv.take<float4>(in->n_hits);
+  auto* order = cv.take<int32_t>(in->n_tracks);
   if (!ws || ws_bytes < cv.off) return TPCX_E_ARG;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
@@ -968,7 +972,9 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   fo.ok = out->ok;
   fo.reject = out->reject;
   const FitConsts f{fp->chi2_cut, fp->var_s, fp->var_t, fp->var_w};
-  hipLaunchKernelGGL(k_fit, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream, fi, c->dp, f, rec, fo);
+  enqueue_length_order(in->n_tracks, in->hit_begin, order, stream);
+  hipLaunchKernelGGL(k_fit, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream, fi, c->dp, f, order,
+                     rec, fo);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
@@ -1009,6 +1015,85 @@ RebuildLayout carve_rebuild(const tpcx_ctx* c, void* base, int32_t n_units, int6
 }  // namespace
 
 extern "C" {
+
+namespace {
+
+struct MergeLayout {
+  MergeWs ws;
+  size_t bytes;
+};
+
+MergeLayout carve_merge(void* base, int32_t n_units, int64_t n) {
+  Carver cv{static_cast<char*>(base)};
+  MergeLayout L{};
+  L.ws.view = cv.take<float>(15 * n);
+  L.ws.ok = cv.take<uint8_t>(3 * n);
+  L.ws.ub = cv.take<int64_t>(int64_t(n_units) + 1);
+  L.ws.rec = cv.take<float4>(3 * n);
+  L.ws.cell = cv.take<int32_t>(int64_t(n_units) * 3 * (kMergeCells + 1));
+  L.ws.zcell = cv.take<float2>(int64_t(n_units) * 3);
+  L.ws.best_out = cv.take<int32_t>(n);
+  L.ws.best_in = cv.take<int32_t>(n);
+  L.bytes = cv.off;
+  return L;
+}
+
+}  // namespace
+
+size_t tpcx_merge_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_tracks) {
+  if (!c || n_units < 1 || n_tracks < 0) return 0;
+  return carve_merge(nullptr, n_units, n_tracks).bytes;
+}
+
+tpcx_status tpcx_merge(tpcx_ctx* c, const tpcx_merge_in* in, const tpcx_merge_params* mp, const tpcx_merge_out* out,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!c || !in || !mp || !out || in->n_tracks < 0 || in->n_tracks >= (int64_t(1) << 31) || in->n_units < 1)
+    return TPCX_E_ARG;
+  if (in->n_tracks > 0 && (!in->unit || !in->param || !in->x_ref || !in->r_in || !in->r_out || !in->unit_nbr ||
+                           !out->prev || !out->next || !out->root))
+    return TPCX_E_ARG;
+  if (!std::isfinite(mp->x_m) || !(mp->chi2_cut >= 0.0f) || !std::isfinite(mp->chi2_cut) ||
+      !(std::fabs(mp->cos_h) <= 1.0f) || !(std::fabs(mp->sin_h) <= 1.0f))
+    return TPCX_E_ARG;
+  for (int i = 0; i < 5; ++i)
+    if (!(mp->tol[i] > 0.0f) || !std::isfinite(mp->tol[i])) return TPCX_E_ARG;
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
+  const MergeLayout L = carve_merge(ws, in->n_units, in->n_tracks);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
+  if (in->n_tracks == 0) return TPCX_OK;
+  MergeIn mi;
+  mi.n = in->n_tracks;
+  mi.n_units = in->n_units;
+  mi.unit = in->unit;
+  mi.param = in->param;
+  mi.x_ref = in->x_ref;
+  mi.r_in = in->r_in;
+  mi.r_out = in->r_out;
+  mi.unit_nbr = in->unit_nbr;
+  MergeConsts m;
+  m.x_m = mp->x_m;
+  m.cos_h = mp->cos_h;
+  m.sin_h = mp->sin_h;
+  m.chi2_cut = mp->chi2_cut;
+  for (int i = 0; i < 5; ++i) m.itol2[i] = 1.0f / (mp->tol[i] * mp->tol[i]);
+  // the window holds every pair the chi2 cut can accept (with a margin for
+  // the rounding of the float chi2)
+  const float rc = std::sqrt(mp->chi2_cut);
+  m.wy = mp->tol[0] * rc * 1.001f;
+  m.wz = std::max(mp->tol[1] * rc * 1.001f, 1e-6f);
+  m.cross_electrode = mp->cross_electrode ? 1 : 0;
+  const int64_t n = in->n_tracks;
+  hipLaunchKernelGGL(k_merge_views, dim3(blocks_for(n, kMergeBlock)), dim3(kMergeBlock), 0, stream, mi, c->dp, m,
+                     L.ws);
+  hipLaunchKernelGGL(k_merge_units, dim3(blocks_for(int64_t(in->n_units) + 1, 256)), dim3(256), 0, stream, mi, L.ws);
+  hipLaunchKernelGGL(k_merge_grid, dim3(in->n_units * 3), dim3(kMergeBlock), 0, stream, mi, m, L.ws);
+  hipLaunchKernelGGL(k_merge_match, dim3(blocks_for(n, kMergeBlock)), dim3(kMergeBlock), 0, stream, mi, m, L.ws);
+  hipLaunchKernelGGL(k_merge_link, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, L.ws, out->prev, out->next);
+  hipLaunchKernelGGL(k_merge_root, dim3(blocks_for(n, 256)), dim3(256), 0, stream, n, out->prev, out->root);
+  return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+}
 
 size_t tpcx_rebuild_workspace_bytes(const tpcx_ctx* c, int32_t n_units, int64_t n_clusters, int64_t n_tracks) {
   if (!c || n_units < 1 || n_clusters < 0 || n_tracks < 0) return 0;

@@ -48,6 +48,17 @@ void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams*
                  const int32_t* t_ndf, const int64_t* row_begin, const float* y, const float* z,
                  int32_t* assigned, double* param, double* cov, double* chi2_out, double* x_out,
                  int32_t* n_kept, int32_t* ok);
+struct OrcMergeParams {
+  float x_m, cos_h, sin_h;
+  float tol[5];
+  float chi2_cut;
+  int32_t cross_electrode;
+};
+int orc_merge_views(const OrcParams* p, const OrcMergeParams* mp, int precision, int64_t n_tracks,
+                    const float* param, const float* x_ref, double* views, uint8_t* ok);
+int orc_merge(const OrcParams* p, const OrcMergeParams* mp, int64_t n_tracks, int32_t n_units,
+              const int32_t* unit, const float* param, const float* x_ref, const int32_t* r_in,
+              const int32_t* r_out, const int32_t* unit_nbr, int32_t* prev, int32_t* next, int32_t* root);
 }
 
 template <class T>
@@ -139,6 +150,26 @@ int main(int argc, char** argv) {
                 t_hb.data(), t_hits.data(), t_rows.data(), seed.data(), t_xref.data(), fchi2.data(), t_ndf.data(),
                 rb.data(), y.data(), z.data(), assigned.data(), fp.data(), fc.data(), fchi.data(), fx.data(),
                 fk.data(), fok.data());
+  {
+    // merging of the tracklets (units = sectors 0 .. n_units - 1 of one half)
+    const OrcMergeParams mp{165.0f, 0.98480775f, 0.17364818f, {1.0f, 1.0f, 0.02f, 0.02f, 0.1f}, 25.0f, 1};
+    std::vector<int32_t> r_in(nt), r_out(nt), nbr(size_t(3) * n_units), prv(nt), nxt(nt), root(nt);
+    for (int64_t i = 0; i < nt; ++i) {
+      r_in[i] = t_rows[size_t(t_hb[i])];
+      r_out[i] = t_rows[size_t(t_hb[i + 1] - 1)];
+    }
+    for (int u = 0; u < n_units; ++u) {
+      nbr[3 * u + 0] = u + 1 < n_units ? u + 1 : -1;
+      nbr[3 * u + 1] = u > 0 ? u - 1 : -1;
+      nbr[3 * u + 2] = -1;
+    }
+    std::vector<double> views(size_t(15) * nt);
+    std::vector<uint8_t> vok(size_t(3) * nt);
+    for (int prec : {32, 64})
+      orc_merge_views(&p, &mp, prec, nt, seed.data(), t_xref.data(), views.data(), vok.data());
+    orc_merge(&p, &mp, nt, n_units, t_unit.data(), seed.data(), t_xref.data(), r_in.data(), r_out.data(),
+              nbr.data(), prv.data(), nxt.data(), root.data());
+  }
   std::printf("tracklets %lld kept %lld\n", static_cast<long long>(nt), static_cast<long long>(kept));
   return 0;
 }

@@ -265,3 +265,22 @@ def test_random_tiny_inputs_against_brute_force():
             while out["prev"][r] >= 0:
                 r = out["prev"][r]
             assert out["root"][a] == r
+
+
+def test_links_join_segments_of_one_particle_on_the_central_event():
+    """On the selected tracklets of a central event, the links join segments
+    of one particle (the majority particle of each tracklet's clusters)."""
+    cs = synth.central_event(seed=2)
+    k = oracle.kept_tracklets(oracle.track(cs, n_threads=16))
+    keep, _ = oracle.select(k, cs.n_clusters)
+    idx = np.nonzero(keep)[0]
+    hb = k["hit_begin"]
+    tk = dict(unit=k["unit"][idx].astype(np.int32), param=k["param"][idx], xref=k["xref"][idx],
+              r_in=np.array([k["rows"][hb[i]] for i in idx], np.int32),
+              r_out=np.array([k["rows"][hb[i + 1] - 1] for i in idx], np.int32))
+    out = oracle.merge(tk, oracle.unit_neighbours(cs.unit_sector), cs.n_units)
+    truth = np.array([np.bincount(np.maximum(cs.truth_track[k["hits"][hb[i]:hb[i + 1]]], 0)).argmax()
+                      for i in idx])
+    a = np.nonzero(out["next"] >= 0)[0]
+    assert len(a) > 3000
+    assert (truth[a] == truth[out["next"][a]]).mean() > 0.99
