@@ -314,6 +314,19 @@ def next_steps(tr, bufs, n_units, n_clusters, n_tracks, n_hits, y, z, steps, str
                           alg_bytes=int(b), GBs=round(b / (ms * 1e-3) / 1e9, 2),
                           frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
     log(f"rebuild: {ms:.3f} ms, {nt1} tracks of the first slice, {res['rebuild']['kept_hits']} clusters kept")
+    del r
+    # the same with Phase III's extrapolation beyond the tracks' ends
+    with torch.cuda.stream(stream):
+        r = tr.rebuild(*rargs, extrapolate=True, stream=stream)
+        sync()
+        del r
+        ms = timed(lambda: tr.rebuild(*rargs, extrapolate=True, stream=stream), steps, stream)
+        r = tr.rebuild(*rargs, extrapolate=True, stream=stream)
+        sync()
+    res["rebuild_phase3"] = dict(ms=round(ms, 3), ok=int(r["ok"].sum()), kept_hits=int(r["n_kept"].sum()),
+                                 alg_bytes=int(b), GBs=round(b / (ms * 1e-3) / 1e9, 2),
+                                 frac=round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5))
+    log(f"rebuild with extrapolation: {ms:.3f} ms, {res['rebuild_phase3']['kept_hits']} clusters kept")
     del r, rargs
     torch.cuda.empty_cache()
     # every kept tracklet (their hits are contiguous in the output)

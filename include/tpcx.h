@@ -407,6 +407,15 @@ tpcx_status tpcx_fit(tpcx_ctx* ctx, const tpcx_fit_in* in, const tpcx_fit_params
  *      cluster's y, z; diagonal covariance), then inwards over the assigned
  *      rows: a cluster whose filter chi2 exceeds chi2_final is dropped.
  *      Result at the innermost kept cluster; ndf = 2 n_kept - 5.
+ * Phase III (paper, Section 3: the rebuild extended by extrapolating the
+ * tracks inwards and outwards; candidates found so go through the same
+ * ambiguity solving, optionally with a stricter cut), when extrapolate is
+ * set: after step 1 the state of r_in is carried further in row by row
+ * (no updates) until row 0 or a propagation guard, and after step 2 its
+ * final state further out until the last row or a guard; those rows' clusters
+ * with chi2 <= chi2_extrap against the extrapolation alone are candidates,
+ * and steps 3 and 4 run over the extended rows.  Not across sector
+ * boundaries.
  * A rebuild fails (ok = 0, nothing assigned) on a propagation guard, with
  * fewer than 3 kept clusters, or when its input breaks the layout below
  * (unit outside 0 .. n_units - 1, rows not strictly ascending or outside
@@ -418,6 +427,8 @@ typedef struct {
   float chi2_final;            /* chi2 cut of the last iteration */
   float var_s, var_t, var_w;   /* restart variances of sin(phi), dz/ds, q/pT */
   int32_t rounds;              /* proposal rounds of the assignment (0 .. 64) */
+  int32_t extrapolate;         /* 1: Phase III, candidates also beyond the track's ends */
+  float chi2_extrap;           /* chi2 cut of those candidates */
 } tpcx_rebuild_params;
 
 typedef struct {

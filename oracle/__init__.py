@@ -111,7 +111,7 @@ def lib():
         L.orc_fit.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, ctypes.c_float, ctypes.c_int64] + [P] * 14
         L.orc_rebuild.argtypes = [ctypes.c_int, P, ctypes.c_int, P] + [ctypes.c_float] * 5 + [
-            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64] + [P] * 17
+            ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_int32, ctypes.c_int64] + [P] * 17
         L.orc_merge_views.restype = ctypes.c_int
         L.orc_merge_views.argtypes = [P, P, ctypes.c_int, ctypes.c_int64, P, P, P, P]
         L.orc_merge.restype = ctypes.c_int
@@ -420,13 +420,15 @@ def fit(cs, tk, precision=32, reject=None, params: Params | None = None, row_x=N
     return out
 
 
-REBUILD_DEFAULTS = dict(chi2_cut=16.0, chi2_final=16.0, vs=1e-2, vt=1e-2, vw=1.0, k_max=4, rounds=6)
+REBUILD_DEFAULTS = dict(chi2_cut=16.0, chi2_final=16.0, vs=1e-2, vt=1e-2, vw=1.0, k_max=4, rounds=6,
+                        extrapolate=False, chi2_extrap=9.0)
 
 
 def rebuild(cs, tk, precision=32, params: Params | None = None, row_x=None, **kw):
     """Phase II rebuild of the tracks in tk (kept_tracklets layout plus xref,
     chi2, ndf, unit) against the clusters of their units (cs.row_begin, y,
-    z).  Returns param, cov, chi2, x_out, n_kept, ok and assigned [n, n_rows]
+    z); with extrapolate=True also Phase III's candidates beyond the tracks'
+    ends (chi2 cut chi2_extrap).  Returns param, cov, chi2, x_out, n_kept, ok and assigned [n, n_rows]
     (the cluster kept at each row, -1 for none)."""
     from synth import geometry as G
     params = params or Params()
@@ -449,7 +451,8 @@ def rebuild(cs, tk, precision=32, params: Params | None = None, row_x=None, **kw
     ps = params.c_struct()
     a = arrs
     lib().orc_rebuild(precision, _p(xr), R, ctypes.byref(ps), f["chi2_cut"], f["chi2_final"], f["vs"], f["vt"],
-                      f["vw"], int(f["k_max"]), int(f["rounds"]), int(cs.n_units), n, _p(a["unit"]), _p(a["hb"]),
+                      f["vw"], int(f["k_max"]), int(f["rounds"]), int(bool(f["extrapolate"])), f["chi2_extrap"],
+                      int(cs.n_units), n, _p(a["unit"]), _p(a["hb"]),
                       _p(a["hits"]), _p(a["rows"]), _p(a["seed"]), _p(a["xref"]), _p(a["chi2"]), _p(a["ndf"]),
                       _p(a["rb"]), _p(a["y"]), _p(a["z"]), _p(out["assigned"]), _p(out["param"]), _p(out["cov"]),
                       _p(out["chi2"]), _p(out["x_out"]), _p(out["n_kept"]), _p(out["ok"]))

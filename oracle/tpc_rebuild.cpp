@@ -67,6 +67,8 @@ double bf16(double v) { return double(bf16(float(v))); }
 struct RebuildParams {
   float chi2_cut, chi2_final, vs, vt, vw;
   int k_max, rounds;
+  int extrapolate;    // Phase III: candidates also beyond the track's ends
+  float chi2_extrap;  // their chi2 cut
 };
 
 template <class T>
@@ -79,27 +81,44 @@ struct Cand {
   float chi2;
 };
 
-// Per track: candidates of every row r_in .. r_out after iteration 2 and the
-// final state of iteration 2.
+// Per track: candidates of every row r_lo .. r_hi (r_in .. r_out, extended
+// beyond the track's ends by the extrapolation) after iteration 2, and the
+// final state of iteration 2 (at r_hi).
 template <class T>
 struct Pass2 {
   bool ok = false;
-  int r_in = 0, r_out = 0;
+  int r_lo = 0, r_hi = 0;
   T oy{}, oz{};
   State<T> st{};
   std::vector<std::vector<Cand>> cand;  // [r_out - r_in + 1]
 };
 
+// The candidates of one row against the prediction (iy, iz) with variances
+// (vy, vz): chi2 <= cut, the k_max best by (chi2, id).
+template <class T>
+void row_candidates(std::vector<Cand>& L, int64_t j0, int64_t j1, const float* y, const float* z, T oy, T oz, T iy,
+                    T iz, T vy, T vz, const Consts<T>& c, float cut, int k_max) {
+  const T sy = vy + c.sy2, sz = vz + c.sz2;
+  for (int64_t j = j0; j < j1; ++j) {
+    const T dy = (T(y[j]) - oy) - iy, dz = (T(z[j]) - oz) - iz;
+    const T ch = (dy * dy) / sy + (dz * dz) / sz;
+    if (ch <= T(cut)) L.push_back({int32_t(j), float(ch)});
+  }
+  std::sort(L.begin(), L.end(), [](const Cand& a, const Cand& b) {
+    return a.chi2 < b.chi2 || (a.chi2 == b.chi2 && a.id < b.id);
+  });
+  if (int(L.size()) > k_max) L.resize(k_max);
+}
+
 template <class T>
 Pass2<T> pass12(int n, const int32_t* hits, const uint8_t* rows, const float* seed, T x_ref, const T* xr,
-                const int64_t* rb, const float* y, const float* z, const Consts<T>& c, const RebuildParams& f) {
+                int n_rows, const int64_t* rb, const float* y, const float* z, const Consts<T>& c,
+                const RebuildParams& f) {
   Pass2<T> P;
   if (n < 3) return P;
-  P.r_in = rows[0];
-  P.r_out = rows[n - 1];
-  const int nr = P.r_out - P.r_in + 1;
-  std::vector<int32_t> own(nr, -1);
-  for (int i = 0; i < n; ++i) own[rows[i] - P.r_in] = hits[i];
+  const int r_in = rows[0], r_out = rows[n - 1];
+  std::vector<int32_t> own(n_rows, -1);
+  for (int i = 0; i < n; ++i) own[rows[i]] = hits[i];
   P.oy = T(y[hits[n - 1]]);
   P.oz = T(z[hits[n - 1]]);
   const T oy = P.oy, oz = P.oz;
@@ -116,70 +135,95 @@ Pass2<T> pass12(int n, const int32_t* hits, const uint8_t* rows, const float* se
     const T xi = xr[rows[i]];
     if (xi > x_ref && !(st.x == xi) && !propagate(st, xi, c)) return P;
   }
-  if (!(st.x == xr[P.r_out]) && !propagate(st, xr[P.r_out], c)) return P;
+  if (!(st.x == xr[r_out]) && !propagate(st, xr[r_out], c)) return P;
   st.y = T(0);
   st.z = T(0);
   diag(st, c, f);
-  std::vector<T> py(nr), pz(nr), cy(nr), cz(nr);
-  for (int r = P.r_out - 1; r >= P.r_in; --r) {
+  std::vector<T> py(n_rows), pz(n_rows), cy(n_rows), cz(n_rows);
+  for (int r = r_out - 1; r >= r_in; --r) {
     if (!propagate(st, xr[r], c)) return P;
     const Cov9<T> cv = covariance(st);
-    py[r - P.r_in] = st.y;
-    pz[r - P.r_in] = st.z;
-    cy[r - P.r_in] = bf16(cv.cyy);
-    cz[r - P.r_in] = bf16(cv.czz);
-    const int32_t h = own[r - P.r_in];
+    py[r] = st.y;
+    pz[r] = st.z;
+    cy[r] = bf16(cv.cyy);
+    cz[r] = bf16(cv.czz);
+    const int32_t h = own[r];
     if (h >= 0) update(st, T(y[h]) - oy, T(z[h]) - oz, c);
   }
-  // iteration 2
   const T s1 = st.s, t1 = st.t, w1 = st.w;
+  // Phase III inwards: the state of r_in carried further in, row by row,
+  // without updates, until the first row or a propagation guard
+  int r_lo = r_in;
+  if (f.extrapolate) {
+    State<T> ex = st;
+    for (int r = r_in - 1; r >= 0; --r) {
+      if (!propagate(ex, xr[r], c)) break;
+      const Cov9<T> cv = covariance(ex);
+      py[r] = ex.y;
+      pz[r] = ex.z;
+      cy[r] = bf16(cv.cyy);
+      cz[r] = bf16(cv.czz);
+      r_lo = r;
+    }
+  }
+  // iteration 2
   st = State<T>{};
-  st.x = xr[P.r_in];
+  st.x = xr[r_in];
   st.y = T(y[hits[0]]) - oy;
   st.z = T(z[hits[0]]) - oz;
   st.s = s1;
   st.t = t1;
   st.w = w1;
   diag(st, c, f);
-  P.cand.assign(nr, {});
-  for (int r = P.r_in; r <= P.r_out; ++r) {
-    const int q = r - P.r_in;
-    if (r > P.r_in && !propagate(st, xr[r], c)) return P;
+  std::vector<std::vector<Cand>> cand(n_rows);
+  // rows below the track: the inward extrapolation alone
+  for (int r = r_lo; r < r_in; ++r)
+    row_candidates(cand[r], rb[r], rb[r + 1], y, z, oy, oz, py[r], pz[r], cy[r], cz[r], c, f.chi2_extrap, f.k_max);
+  for (int r = r_in; r <= r_out; ++r) {
+    if (r > r_in && !propagate(st, xr[r], c)) return P;
     T iy, iz, vy, vz;
-    if (r == P.r_in) {
-      iy = py[q];
-      iz = pz[q];
-      vy = cy[q];
-      vz = cz[q];
+    if (r == r_in) {
+      iy = py[r];
+      iz = pz[r];
+      vy = cy[r];
+      vz = cz[r];
     } else {
       const Cov9<T> cv = covariance(st);
-      if (r == P.r_out) {
+      if (r == r_out) {
         iy = st.y;
         iz = st.z;
         vy = cv.cyy;
         vz = cv.czz;
       } else {
-        const T wy = T(1) / (cy[q] + cv.cyy);
-        const T wz = T(1) / (cz[q] + cv.czz);
-        iy = (py[q] * cv.cyy + st.y * cy[q]) * wy;
-        iz = (pz[q] * cv.czz + st.z * cz[q]) * wz;
-        vy = (cy[q] * cv.cyy) * wy;
-        vz = (cz[q] * cv.czz) * wz;
+        const T wy = T(1) / (cy[r] + cv.cyy);
+        const T wz = T(1) / (cz[r] + cv.czz);
+        iy = (py[r] * cv.cyy + st.y * cy[r]) * wy;
+        iz = (pz[r] * cv.czz + st.z * cz[r]) * wz;
+        vy = (cy[r] * cv.cyy) * wy;
+        vz = (cz[r] * cv.czz) * wz;
       }
     }
-    const T sy = vy + c.sy2, sz = vz + c.sz2;
-    std::vector<Cand>& L = P.cand[q];
-    for (int64_t j = rb[r]; j < rb[r + 1]; ++j) {
-      const T dy = (T(y[j]) - oy) - iy, dz = (T(z[j]) - oz) - iz;
-      const T ch = (dy * dy) / sy + (dz * dz) / sz;
-      if (ch <= T(f.chi2_cut)) L.push_back({int32_t(j), float(ch)});
-    }
-    std::sort(L.begin(), L.end(), [](const Cand& a, const Cand& b) {
-      return a.chi2 < b.chi2 || (a.chi2 == b.chi2 && a.id < b.id);
-    });
-    if (int(L.size()) > f.k_max) L.resize(f.k_max);
-    if (r > P.r_in && !L.empty()) update(st, T(y[L[0].id]) - oy, T(z[L[0].id]) - oz, c);
+    std::vector<Cand>& L = cand[r];
+    row_candidates(L, rb[r], rb[r + 1], y, z, oy, oz, iy, iz, vy, vz, c, f.chi2_cut, f.k_max);
+    if (r > r_in && !L.empty()) update(st, T(y[L[0].id]) - oy, T(z[L[0].id]) - oz, c);
   }
+  // Phase III outwards: the final state carried further out, without
+  // updates, until the last row or a propagation guard
+  int r_hi = r_out;
+  if (f.extrapolate) {
+    for (int r = r_out + 1; r < n_rows; ++r) {
+      State<T> nx = st;
+      if (!propagate(nx, xr[r], c)) break;
+      st = nx;
+      const Cov9<T> cv = covariance(st);
+      row_candidates(cand[r], rb[r], rb[r + 1], y, z, oy, oz, st.y, st.z, cv.cyy, cv.czz, c, f.chi2_extrap,
+                     f.k_max);
+      r_hi = r;
+    }
+  }
+  P.r_lo = r_lo;
+  P.r_hi = r_hi;
+  P.cand.assign(cand.begin() + r_lo, cand.begin() + r_hi + 1);
   P.st = st;
   P.ok = true;
   return P;
@@ -206,13 +250,13 @@ extern "C" {
 // [n], n_kept [n], ok [n].
 void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams* p, float chi2_cut,
                  float chi2_final, float vs, float vt, float vw, int32_t k_max, int32_t rounds,
-                 int32_t n_units, int64_t n_tracks, const int32_t* unit, const int64_t* hit_begin,
+                 int32_t extrapolate, float chi2_extrap, int32_t n_units, int64_t n_tracks, const int32_t* unit, const int64_t* hit_begin,
                  const int32_t* hit_id,
                  const uint8_t* hit_row, const float* seed, const float* x_ref, const float* t_chi2,
                  const int32_t* t_ndf, const int64_t* row_begin, const float* y, const float* z,
                  int32_t* assigned, double* param, double* cov, double* chi2_out, double* x_out,
                  int32_t* n_kept, int32_t* ok) {
-  const RebuildParams f{chi2_cut, chi2_final, vs, vt, vw, k_max, rounds};
+  const RebuildParams f{chi2_cut, chi2_final, vs, vt, vw, k_max, rounds, extrapolate, chi2_extrap};
   auto go = [&](auto tag) {
     using T = decltype(tag);
     const Consts<T> c = make_consts<T>(*p);
@@ -225,7 +269,7 @@ void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams*
     for (int64_t t = 0; t < n_tracks; ++t) {
       const int64_t b = hit_begin[t];
       const int n = int(hit_begin[t + 1] - b);
-      P[t] = pass12<T>(n, hit_id + b, hit_row + b, seed + 5 * t, T(x_ref[t]), xr.data(),
+      P[t] = pass12<T>(n, hit_id + b, hit_row + b, seed + 5 * t, T(x_ref[t]), xr.data(), n_rows,
                        row_begin + int64_t(unit[t]) * n_rows, y, z, c, f);
     }
     // ranks and proposal rounds (a cluster belongs to one unit)
@@ -271,7 +315,7 @@ void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams*
       for (int k = 0; k < 15; ++k) cov[15 * t + k] = 0.0;
       const Pass2<T>& Q = P[t];
       if (!Q.ok) continue;
-      const int nr = Q.r_out - Q.r_in + 1;
+      const int nr = Q.r_hi - Q.r_lo + 1;
       std::vector<int32_t> got(nr, -1);
       for (int q = 0; q < nr; ++q) {
         const int k = ptr[t][q];
@@ -282,7 +326,7 @@ void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams*
       if (j < 2) continue;
       State<T> st = Q.st;
       bool good = true;
-      for (int q = nr - 2; q >= j && good; --q) good = propagate(st, xr[Q.r_in + q], c);
+      for (int q = nr - 2; q >= j && good; --q) good = propagate(st, xr[Q.r_lo + q], c);
       if (!good) continue;
       st.y = T(y[got[j]]) - Q.oy;
       st.z = T(z[got[j]]) - Q.oz;
@@ -294,7 +338,7 @@ void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams*
       State<T> last = st;
       for (int q = j - 1; q >= 0 && good; --q) {
         if (got[q] < 0) continue;
-        if (!propagate(st, xr[Q.r_in + q], c)) {
+        if (!propagate(st, xr[Q.r_lo + q], c)) {
           good = false;
           break;
         }
@@ -307,7 +351,7 @@ void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams*
         last = st;
       }
       if (!good || kept < 3) continue;
-      for (int q = 0; q < nr; ++q) as[Q.r_in + q] = keep[q];
+      for (int q = 0; q < nr; ++q) as[Q.r_lo + q] = keep[q];
       ok[t] = 1;
       n_kept[t] = kept;
       chi2_out[t] = double(chi2);

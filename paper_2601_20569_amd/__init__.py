@@ -92,7 +92,8 @@ class FitOutput(ctypes.Structure):
 
 class RebuildParams(ctypes.Structure):
     _fields_ = [("chi2_cut", ctypes.c_float), ("chi2_final", ctypes.c_float), ("var_s", ctypes.c_float),
-                ("var_t", ctypes.c_float), ("var_w", ctypes.c_float), ("rounds", ctypes.c_int32)]
+                ("var_t", ctypes.c_float), ("var_w", ctypes.c_float), ("rounds", ctypes.c_int32),
+                ("extrapolate", ctypes.c_int32), ("chi2_extrap", ctypes.c_float)]
 
 
 class RebuildInput(ctypes.Structure):
@@ -437,9 +438,11 @@ class SectorTracker:
         return res
 
     def rebuild(self, row_begin, y, z, n_units, unit, hit_begin, hit_id, hit_row, seed, x_ref, chi2, ndf,
-                chi2_cut=16.0, chi2_final=16.0, var_s=1e-2, var_t=1e-2, var_w=1.0, rounds=6, stream=None):
+                chi2_cut=16.0, chi2_final=16.0, var_s=1e-2, var_t=1e-2, var_w=1.0, rounds=6, extrapolate=False,
+                chi2_extrap=9.0, stream=None):
         """Phase II rebuild (tpcx_rebuild) of the tracks given by device tensors
-        against the clusters (row_begin, y, z of the tracking input).  Returns a
+        against the clusters (row_begin, y, z of the tracking input); with
+        extrapolate, Phase III's candidates beyond the tracks' ends too.  Returns a
         dict of device tensors: assigned [n, n_rows], param, cov, chi2, x_out,
         n_kept, ok (no sync)."""
         import torch
@@ -465,7 +468,7 @@ class SectorTracker:
         ri = RebuildInput(n, nh, _ptr(unit), _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(seed), _ptr(x_ref),
                           _ptr(chi2), _ptr(ndf))
         ro = RebuildOutput(*[_ptr(out[k]) for k in ("assigned", "param", "cov", "chi2", "x_out", "n_kept", "ok")])
-        rp = RebuildParams(chi2_cut, chi2_final, var_s, var_t, var_w, rounds)
+        rp = RebuildParams(chi2_cut, chi2_final, var_s, var_t, var_w, rounds, int(bool(extrapolate)), chi2_extrap)
         s = stream if stream is not None else torch.cuda.current_stream()
         _check(lib().tpcx_rebuild(self._h, ctypes.byref(cl), ctypes.byref(ri), ctypes.byref(rp), ctypes.byref(ro),
                                   ctypes.c_void_p(ws.data_ptr() + off), nb, ctypes.c_void_p(s.cuda_stream)),

@@ -71,6 +71,8 @@ struct RebuildOut {
 struct RebuildConsts {
   float chi2_cut, chi2_final, vs, vt, vw;
   int rounds;
+  int extrapolate;    // Phase III: candidates also beyond the track's ends
+  float chi2_extrap;  // their chi2 cut
 };
 
 __device__ __forceinline__ void rb_reset(KState& q, const DevParams& p, const RebuildConsts& f) {
@@ -103,6 +105,53 @@ __global__ void k_rebuild_keys(RebuildIn in, uint64_t* __restrict__ key) {
                                                           uint32_t(kSelectMaxPerUnit - 1 - min(local, kSelectMaxPerUnit - 1)));
 }
 
+// The candidates of row r of unit row base kb against the prediction (iy,
+// iz) (relative to (oy, oz)) with variances (vy, vz): chi2 <= cut, the
+// kRebuildK best by (chi2, caller id) into cand; returns their number and the
+// best one's id in *best (-1 if none).
+__device__ __forceinline__ int rb_row_candidates(const Grid& g, const DevParams& p, int kb, int r, float oy,
+                                                 float oz, float iy, float iz, float vy, float vz, float cut,
+                                                 int2* cand, int32_t* best) {
+  const float sy = vy + p.sy2, sz = vz + p.sz2;
+  // the grid box around the interpolation, widened to hold every cluster
+  // the float chi2 cut can accept
+  const float cy_abs = oy + iy, cz_abs = oz + iz;
+  const float hy = __builtin_amdgcn_sqrtf(cut * sy) * 1.001f + box_pad(cy_abs);
+  const float hz = __builtin_amdgcn_sqrtf(cut * sz) * 1.001f + box_pad(cz_abs);
+  const RowView rv(g, kb + r, r);
+  const int zb0 = rv.zbin(cz_abs - hz), zb1 = rv.zbin(cz_abs + hz);
+  const int yb0 = rv.ybin(cy_abs - hy), yb1 = rv.ybin(cy_abs + hy);
+  // K best (chi2, id), ascending
+  float bc[kRebuildK];
+  int32_t bi[kRebuildK];
+  int nb = 0;
+  for (int zb = zb0; zb <= zb1; ++zb) {
+    const int64_t ra = rv.base + int64_t(zb) * rv.ri.ny;
+    const int32_t j0 = g.bin_start[ra + yb0], j1 = g.bin_start[ra + yb1 + 1];
+    for (int32_t j = j0; j < j1; ++j) {
+      const float4 pc = g.pts[j];
+      const float dy = (pc.x - oy) - iy, dz = (pc.y - oz) - iz;
+      const float ch = (dy * dy) / sy + (dz * dz) / sz;
+      if (!(ch <= cut)) continue;
+      const int32_t id = __float_as_int(pc.z);
+      // insertion into the sorted top-K
+      int pos = nb;
+      while (pos > 0 && (ch < bc[pos - 1] || (ch == bc[pos - 1] && id < bi[pos - 1]))) --pos;
+      if (pos >= kRebuildK) continue;
+      for (int m = min(nb, kRebuildK - 1); m > pos; --m) {
+        bc[m] = bc[m - 1];
+        bi[m] = bi[m - 1];
+      }
+      bc[pos] = ch;
+      bi[pos] = id;
+      nb = min(nb + 1, kRebuildK);
+    }
+  }
+  for (int m = 0; m < nb; ++m) cand[m] = make_int2(bi[m], __float_as_int(bc[m]));
+  *best = nb > 0 ? bi[0] : -1;
+  return nb;
+}
+
 __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, DevParams p, RebuildConsts f,
                                                           RebuildWs ws) {
   const int64_t t = int64_t(blockIdx.x) * kWave + threadIdx.x;
@@ -121,8 +170,6 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
     if (r >= R || (i > 0 && r <= in.hit_row[b + i - 1]) || h < 0 || h >= in.n_clusters) return;
   }
   const int r_in = in.hit_row[b], r_out = in.hit_row[b + n - 1];
-  meta[1] = r_in;
-  meta[2] = r_out;
   float4* pred = ws.pred + t * R;
   uint8_t* cnt = ws.cnt + t * R;
   uint8_t* ptr = ws.ptr + t * R;
@@ -160,8 +207,29 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
       --hi;
     }
   }
-  // ---- iteration 2
   const float s1 = q.s, t1 = q.t, w1 = q.w;
+  // Phase III inwards: the state of r_in carried further in, row by row,
+  // without updates, until the first row or a propagation guard
+  int r_lo = r_in;
+  if (f.extrapolate) {
+    KState ex = q;
+    for (int r = r_in - 1; r >= 0; --r) {
+      if (!fit_prop(ex, X(r), p)) break;
+      const uint32_t cc = bf16_bits(fit_cyy(ex)) | (bf16_bits(fit_czz(ex)) << 16);
+      pred[r] = make_float4(ex.y, ex.z, __uint_as_float(cc), 0.0f);
+      r_lo = r;
+    }
+  }
+  // ---- iteration 2
+  // rows below the track: the inward extrapolation alone
+  for (int r = r_lo; r < r_in; ++r) {
+    const float4 pr = pred[r];
+    const uint32_t cc = __float_as_uint(pr.z);
+    int32_t best = -1;
+    cnt[r] = uint8_t(rb_row_candidates(g, p, kb, r, oy, oz, pr.x, pr.y, bf16_lo(cc), bf16_hi(cc), f.chi2_extrap,
+                                       cand + r * kRebuildK, &best));
+    ptr[r] = 0;
+  }
   q = KState{};
   q.x = X(r_in);
   q.y = in.y[in.hit_id[b]] - oy;
@@ -199,46 +267,29 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
         vz = (pcz * cz) * wz;
       }
     }
-    const float sy = vy + p.sy2, sz = vz + p.sz2;
-    // the grid box around the interpolation, widened to hold every cluster
-    // the float chi2 cut can accept
-    const float cy_abs = oy + iy, cz_abs = oz + iz;
-    const float hy = __builtin_amdgcn_sqrtf(f.chi2_cut * sy) * 1.001f + box_pad(cy_abs);
-    const float hz = __builtin_amdgcn_sqrtf(f.chi2_cut * sz) * 1.001f + box_pad(cz_abs);
-    const RowView rv(g, kb + r, r);
-    const int zb0 = rv.zbin(cz_abs - hz), zb1 = rv.zbin(cz_abs + hz);
-    const int yb0 = rv.ybin(cy_abs - hy), yb1 = rv.ybin(cy_abs + hy);
-    // K best (chi2, id), ascending
-    float bc[kRebuildK];
-    int32_t bi[kRebuildK];
-    int nb = 0;
-    for (int zb = zb0; zb <= zb1; ++zb) {
-      const int64_t ra = rv.base + int64_t(zb) * rv.ri.ny;
-      const int32_t j0 = g.bin_start[ra + yb0], j1 = g.bin_start[ra + yb1 + 1];
-      for (int32_t j = j0; j < j1; ++j) {
-        const float4 pc = g.pts[j];
-        const float dy = (pc.x - oy) - iy, dz = (pc.y - oz) - iz;
-        const float ch = (dy * dy) / sy + (dz * dz) / sz;
-        if (!(ch <= f.chi2_cut)) continue;
-        const int32_t id = __float_as_int(pc.z);
-        // insertion into the sorted top-K
-        int pos = nb;
-        while (pos > 0 && (ch < bc[pos - 1] || (ch == bc[pos - 1] && id < bi[pos - 1]))) --pos;
-        if (pos >= kRebuildK) continue;
-        for (int m = min(nb, kRebuildK - 1); m > pos; --m) {
-          bc[m] = bc[m - 1];
-          bi[m] = bi[m - 1];
-        }
-        bc[pos] = ch;
-        bi[pos] = id;
-        nb = min(nb + 1, kRebuildK);
-      }
-    }
-    for (int m = 0; m < nb; ++m) cand[r * kRebuildK + m] = make_int2(bi[m], __float_as_int(bc[m]));
+    int32_t best = -1;
+    const int nb = rb_row_candidates(g, p, kb, r, oy, oz, iy, iz, vy, vz, f.chi2_cut, cand + r * kRebuildK, &best);
     cnt[r] = uint8_t(nb);
     ptr[r] = 0;
-    if (r > r_in && nb > 0) fit_update(q, in.y[bi[0]] - oy, in.z[bi[0]] - oz, p);
+    if (r > r_in && nb > 0) fit_update(q, in.y[best] - oy, in.z[best] - oz, p);
   }
+  // Phase III outwards: the final state carried further out, without
+  // updates, until the last row or a propagation guard
+  int r_hi = r_out;
+  if (f.extrapolate) {
+    for (int r = r_out + 1; r < R; ++r) {
+      KState nx = q;
+      if (!fit_prop(nx, X(r), p)) break;
+      q = nx;
+      int32_t best = -1;
+      cnt[r] = uint8_t(rb_row_candidates(g, p, kb, r, oy, oz, q.y, q.z, fit_cyy(q), fit_czz(q), f.chi2_extrap,
+                                         cand + r * kRebuildK, &best));
+      ptr[r] = 0;
+      r_hi = r;
+    }
+  }
+  meta[1] = r_lo;
+  meta[2] = r_hi;
   float* st = ws.state + 16 * t;
   st[0] = q.x; st[1] = q.y; st[2] = q.z; st[3] = q.s; st[4] = q.t; st[5] = q.w;
   st[6] = q.uys; st[7] = q.uyw; st[8] = q.usw; st[9] = q.dy; st[10] = q.ds; st[11] = q.dw;

@@ -1114,7 +1114,7 @@ tpcx_status tpcx_rebuild(tpcx_ctx* c, const tpcx_clusters* cl, const tpcx_rebuil
     return TPCX_E_ARG;
   if (in->n_hits > 0 && (!in->hit_id || !in->hit_row)) return TPCX_E_ARG;
   if (!(rp->chi2_cut >= 0.0f) || !(rp->chi2_final >= 0.0f) || !(rp->var_s > 0.0f) || !(rp->var_t > 0.0f) ||
-      !(rp->var_w > 0.0f) || rp->rounds < 0 || rp->rounds > 64)
+      !(rp->var_w > 0.0f) || rp->rounds < 0 || rp->rounds > 64 || !(rp->chi2_extrap >= 0.0f))
     return TPCX_E_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
   const tpcx_tuning t = effective_tuning(c, cl->n_units, cl->n_clusters);
@@ -1153,7 +1153,8 @@ tpcx_status tpcx_rebuild(tpcx_ctx* c, const tpcx_clusters* cl, const tpcx_rebuil
   ri.y = cl->y;
   ri.z = cl->z;
   ri.row_x = c->d_row_x;
-  const RebuildConsts f{rp->chi2_cut, rp->chi2_final, rp->var_s, rp->var_t, rp->var_w, rp->rounds};
+  const RebuildConsts f{rp->chi2_cut,    rp->chi2_final, rp->var_s,      rp->var_t,
+                       rp->var_w,       rp->rounds,     rp->extrapolate ? 1 : 0, rp->chi2_extrap};
   RebuildOut ro;
   ro.assigned = out->assigned;
   ro.param = out->param;

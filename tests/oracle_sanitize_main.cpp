@@ -42,8 +42,8 @@ void orc_fit(int precision, int decide, const float* row_x, const OrcParams* p, 
              const float* seed, const float* x_ref, const float* y, const float* z, uint8_t* reject, double* param,
              double* cov, double* chi2, double* x_out, int32_t* n_kept, int32_t* ok);
 void orc_rebuild(int precision, const float* row_x, int n_rows, const OrcParams* p, float chi2_cut,
-                 float chi2_final, float vs, float vt, float vw, int32_t k_max, int32_t rounds, int32_t n_units,
-                 int64_t n_tracks, const int32_t* unit, const int64_t* hit_begin, const int32_t* hit_id,
+                 float chi2_final, float vs, float vt, float vw, int32_t k_max, int32_t rounds,
+                 int32_t extrapolate, float chi2_extrap, int32_t n_units, int64_t n_tracks, const int32_t* unit, const int64_t* hit_begin, const int32_t* hit_id,
                  const uint8_t* hit_row, const float* seed, const float* x_ref, const float* t_chi2,
                  const int32_t* t_ndf, const int64_t* row_begin, const float* y, const float* z,
                  int32_t* assigned, double* param, double* cov, double* chi2_out, double* x_out,
@@ -146,7 +146,9 @@ int main(int argc, char** argv) {
             fchi.data(), fx.data(), fk.data(), fok.data());
   std::vector<int32_t> assigned(size_t(nt) * n_rows);
   for (int prec : {32, 64})
-    orc_rebuild(prec, row_x.data(), n_rows, &p, 16.0f, 16.0f, 1e-2f, 1e-2f, 1.0f, 4, 6, n_units, nt, t_unit.data(),
+    for (int ex : {0, 1})
+    orc_rebuild(prec, row_x.data(), n_rows, &p, 16.0f, 16.0f, 1e-2f, 1e-2f, 1.0f, 4, 6, ex, 9.0f, n_units, nt,
+                t_unit.data(),
                 t_hb.data(), t_hits.data(), t_rows.data(), seed.data(), t_xref.data(), fchi2.data(), t_ndf.data(),
                 rb.data(), y.data(), z.data(), assigned.data(), fp.data(), fc.data(), fchi.data(), fx.data(),
                 fk.data(), fok.data());

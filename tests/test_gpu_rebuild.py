@@ -3,7 +3,9 @@
 counts, parameters, covariances and chi2.  Inputs are the oracle's own
 selected tracklets (no value of the HIP path feeds the oracle): the single
 sector, the central event, tracks with clusters left out of their input
-lists, and time-frame units."""
+lists, and time-frame units; with Phase III's extrapolation beyond the
+tracks' ends: the central event, tracks cut to their middle rows and
+time-frame units."""
 import numpy as np
 import pytest
 
@@ -27,9 +29,9 @@ def _selected(cs):
     return tk
 
 
-def _check(cs, tk, name):
+def _check(cs, tk, name, **kw):
     import torch
-    print(f"case: {name}, {len(tk['n'])} tracks", flush=True)
+    print(f"case: {name}, {len(tk['n'])} tracks {kw}", flush=True)
     dev = torch.device("cuda")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     tr = make_tracker()
@@ -37,10 +39,10 @@ def _check(cs, tk, name):
                    T(tk["unit"], torch.int32), T(tk["hit_begin"], torch.int64), T(tk["hits"], torch.int32),
                    T(tk["rows"], torch.uint8), T(np.asarray(tk["param"], np.float32), torch.float32),
                    T(np.asarray(tk["xref"], np.float32), torch.float32),
-                   T(np.asarray(tk["chi2"], np.float32), torch.float32), T(tk["ndf"], torch.int32))
+                   T(np.asarray(tk["chi2"], np.float32), torch.float32), T(tk["ndf"], torch.int32), **kw)
     torch.cuda.synchronize()
     g = {k: v.cpu().numpy() for k, v in g.items() if k != "_ws"}
-    r = oracle.rebuild(cs, tk)
+    r = oracle.rebuild(cs, tk, **kw)
     np.testing.assert_array_equal(g["ok"].astype(bool), r["ok"])
     np.testing.assert_array_equal(g["assigned"], r["assigned"])
     np.testing.assert_array_equal(g["n_kept"], r["n_kept"])
@@ -81,3 +83,25 @@ def test_rebuild_timeframe_units():
     cu = SimpleNamespace(n_units=u1 - u0, row_begin=cs.row_begin[u0 * R:u1 * R + 1] - lo,
                          y=np.asarray(cs.y[lo:hi]), z=np.asarray(cs.z[lo:hi]), n_clusters=hi - lo)
     _check(cu, _selected(cu), "time-frame slice seed 3003, units 20..22")
+
+
+def test_rebuild_with_phase3_extrapolation():
+    from test_rebuild_oracle import _case, _cut
+    cs, tk = _case(95)
+    mid = _cut(tk, lambda r: (r >= 50) & (r <= 110))
+    _check(cs, mid, "exact tracks cut to rows 50..110", extrapolate=True)
+    cs = synth.central_event(seed=2)
+    tk = _selected(cs)
+    _check(cs, tk, "central event", extrapolate=True)
+    _check(cs, _cut(tk, lambda r: r >= 20), "central event, inner 20 rows cut", extrapolate=True, chi2_extrap=16.0)
+
+
+def test_rebuild_phase3_timeframe_units():
+    from types import SimpleNamespace
+    cs = synth.timeframe_slice(seed=3005, n_collisions=24, device="cuda", truth=False)
+    R = 152
+    u0, u1 = 7, 10
+    lo, hi = int(cs.row_begin[u0 * R]), int(cs.row_begin[u1 * R])
+    cu = SimpleNamespace(n_units=u1 - u0, row_begin=cs.row_begin[u0 * R:u1 * R + 1] - lo,
+                         y=np.asarray(cs.y[lo:hi]), z=np.asarray(cs.z[lo:hi]), n_clusters=hi - lo)
+    _check(cu, _selected(cu), "time-frame slice seed 3005, units 7..9", extrapolate=True)

@@ -147,3 +147,65 @@ def test_fp32_against_fp64_on_a_central_event():
     unit = np.array([10.0, 10.0, 1.0, 1.0, 1.0])
     rel = np.abs(a["param"][same] - b["param"][same]) / np.maximum(np.abs(b["param"][same]), unit)
     assert rel.max() < 1e-4, rel.max()
+
+
+def _cut(tk, keep_row):
+    """tk with every track's clusters reduced to the rows keep_row accepts."""
+    hb = tk["hit_begin"]
+    hits, rows, n = [], [], []
+    for u in range(len(tk["n"])):
+        h, r = tk["hits"][hb[u]:hb[u + 1]], tk["rows"][hb[u]:hb[u + 1]]
+        m = keep_row(r)
+        hits.append(h[m])
+        rows.append(r[m])
+        n.append(int(m.sum()))
+    out = dict(tk)
+    out["hits"], out["rows"] = np.concatenate(hits), np.concatenate(rows)
+    out["n"] = np.array(n)
+    out["hit_begin"] = np.concatenate([[0], np.cumsum(n)]).astype(np.int64)
+    return out
+
+
+def test_phase3_extrapolation_recovers_the_cut_off_ends():
+    """Phase III (Section 3): exact helices given only their middle rows get
+    their inner and outer clusters back from the extrapolation beyond the
+    track's ends; without it the rebuild keeps to the given rows."""
+    cs, tk = _case(95)
+    full = {t: set(_hits(tk, t)) for t in range(len(tk["n"]))}
+    rows_of = {t: tk["rows"][tk["hit_begin"][t]:tk["hit_begin"][t + 1]] for t in range(len(tk["n"]))}
+    mid = _cut(tk, lambda r: (r >= 50) & (r <= 110))
+    on = oracle.rebuild(cs, mid, precision=64, extrapolate=True)
+    off = oracle.rebuild(cs, mid, precision=64, extrapolate=False)
+    assert on["ok"].all() and off["ok"].all()
+    recovered = 0
+    for t in range(len(tk["n"])):
+        got_on = set(on["assigned"][t][on["assigned"][t] >= 0])
+        got_off = set(off["assigned"][t][off["assigned"][t] >= 0])
+        assert got_on == full[t], t
+        r = rows_of[t]
+        assert got_off == set(_hits(tk, t)[(r >= 50) & (r <= 110)])
+        assert (np.nonzero(off["assigned"][t] >= 0)[0] >= 50).all() and (np.nonzero(off["assigned"][t] >= 0)[0] <= 110).all()
+        recovered += len(got_on) - len(got_off)
+    assert recovered > 100
+    truth = truth_tracklets(cs)["param"]
+    np.testing.assert_allclose(on["param"], truth, rtol=1e-6, atol=1e-6)
+
+
+def test_phase3_extrapolated_candidates_go_to_the_better_ranked_track():
+    cs, tk = _case(96, smear=0.1, n_tracks=3)
+    mid = _cut(tk, lambda r: r >= 40)
+    hb = mid["hit_begin"]
+    dup = {k: v for k, v in mid.items()}
+    n0 = mid["n"][0]
+    dup["hits"] = np.concatenate([mid["hits"][:hb[1]], mid["hits"]])
+    dup["rows"] = np.concatenate([mid["rows"][:hb[1]], mid["rows"]])
+    dup["n"] = np.concatenate([[n0], mid["n"]])
+    dup["hit_begin"] = np.concatenate([[0], np.cumsum(dup["n"])]).astype(np.int64)
+    for k in ("param", "xref", "unit", "ndf"):
+        dup[k] = np.concatenate([mid[k][:1], mid[k]])
+    dup["chi2"] = np.concatenate([[2.0], mid["chi2"]])  # the copy ranks lower
+    r = oracle.rebuild(cs, dup, extrapolate=True)
+    assert r["ok"][1] and not r["ok"][0]
+    inner = set(_hits(tk, 0)[tk["rows"][tk["hit_begin"][0]:tk["hit_begin"][1]] < 40])
+    got = set(r["assigned"][1][r["assigned"][1] >= 0])
+    assert len(inner) > 10 and len(inner & got) > 0.9 * len(inner)
