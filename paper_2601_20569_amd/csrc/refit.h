@@ -443,19 +443,20 @@ __global__ void __launch_bounds__(kRefitBlock) k_correct_clusters(
   }
 }
 
-// Forward filter over the corrected clusters: xyz[hit_id[q]] when by_cluster,
+// Forward filter over the corrected clusters: xyz[hit_id[q]] when ByCluster,
 // else xyz[q].  Persistent; every lane runs one track at a time.  Idle lanes
-// take new tracks, `refill` or more at a time, from a wavefront-private
-// chunk of kRefitChunk consecutive tracks refilled from kXcds device queues, so
-// lanes do not wait for the longest track of their wavefront.  The clusters of
-// the next two steps are loaded ahead (and the index of the one after), so
-// the loads overlap the arithmetic of the current steps.  Which lane runs a
-// track does not change its result.  Checkpoints (every kCkpt clusters) are
-// written when ckpt is set.
+// take new tracks, `refill` or more at a time (all 64: the lanes step through
+// rows together), from a wavefront-private chunk of kRefitChunk consecutive
+// tracks refilled from kXcds device queues.  Three steps per iteration, each
+// reloading, after its arithmetic, the register it used with the cluster
+// three steps ahead: the loads overlap two steps of arithmetic.  Which lane
+// runs a track does not change its result.  Checkpoints (every kCkpt
+// clusters) are written when ckpt is set.
 constexpr int kRefitChunk = 64;
 
+template <bool ByCluster>
 __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
-    RefitIn in, DevParams p, const float4* __restrict__ xyz, int by_cluster, float* __restrict__ ckpt,
+    RefitIn in, DevParams p, const float4* __restrict__ xyz, float* __restrict__ ckpt,
     unsigned long long* __restrict__ queue, int refill, float* __restrict__ chi2_out,
     int32_t* __restrict__ ok_out) {
   const int64_t n_tr = refit_count(in);
@@ -468,10 +469,15 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
   int i = 0, n = 0;
   float chi2 = 0.0f, zref = 0.0f;
   KState q{};
-  float4 hn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);  // corrected cluster of hit i
-  float4 hn2 = hn;                                  // and of hit i + 1
-  int64_t idn = 0;                                  // xyz index of hit i + 2
-  auto xyz_index = [&](int64_t qh) -> int64_t { return by_cluster ? int64_t(in.hit_id[qh]) : qh; };
+  // Three steps per iteration, A, B and C: hA / hB / hC hold the corrected
+  // clusters of the steps' hits, each reloaded at the end of its step (for
+  // the hit three steps later) into the register the step has just used, so
+  // no register is copied and a step waits only for loads two steps old;
+  // idA / idB / idC are the cluster ids for those reloads, loaded three steps
+  // before.
+  float4 hA = make_float4(0.0f, 0.0f, 0.0f, 0.0f), hB = hA, hC = hA;
+  int32_t idA = 0, idB = 0, idC = 0;
+  auto xyz_index = [&](int64_t qh) -> int64_t { return ByCluster ? int64_t(in.hit_id[qh]) : qh; };
   while (true) {
     const int nidle = __popcll(__ballot(t < 0));
     if (nidle == kWave && exhausted) break;
@@ -519,28 +525,46 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_filter(
             if (ckpt) store_state(ckpt + cb * kCkptFloats, q);
             i = 1;
             chi2 = 0.0f;
-            hn = xyz[xyz_index(hb + 1)];
-            if (n > 2) hn2 = xyz[xyz_index(hb + 2)];
-            idn = n > 3 ? xyz_index(hb + 3) : 0;
+            // the lane's next step is of hit 1 and runs as A, B or C
+            // depending on where the iteration stands: give all three
+            hA = xyz[xyz_index(hb + 1)];
+            hB = xyz[xyz_index(hb + min(2, n - 1))];
+            hC = xyz[xyz_index(hb + min(3, n - 1))];
+            if (ByCluster) {
+              idA = in.hit_id[hb + min(4, n - 1)];
+              idB = in.hit_id[hb + min(5, n - 1)];
+              idC = in.hit_id[hb + min(6, n - 1)];
+            }
           }
         }
         chunk += min(int64_t(__popcll(want)), avail);
       }
     }
-    if (t >= 0) {
-      const float4 h = hn;
-      hn = hn2;
-      if (i + 2 < n) hn2 = xyz[idn];
-      if (i + 3 < n) idn = xyz_index(hb + i + 3);
-      const bool ok = refit_step(q, h.x, h.y, rel_z(h, zref), p, &chi2);
-      if (ok && ckpt && i % kCkpt == 0) store_state(ckpt + (cb + i / kCkpt) * kCkptFloats, q);
-      ++i;
-      if (!ok || i == n) {
-        chi2_out[t] = ok ? chi2 : 0.0f;
-        ok_out[t] = ok ? 1 : 0;
-        t = -1;
+    // every lane runs the steps (idle lanes on indices 0, without effect),
+    // so the loads of each iteration are the same
+    auto step = [&](float4& hc, int32_t& idc) {
+      const bool act = t >= 0;
+      const bool ok = refit_step(q, hc.x, hc.y, rel_z(hc, zref), p, &chi2);
+      // reload for the hit three steps later (clamped into the track)
+      if (ByCluster) {
+        hc = xyz[int64_t(act ? idc : 0)];
+        idc = in.hit_id[act ? hb + min(i + 6, n - 1) : 0];
+      } else {
+        hc = xyz[act ? hb + min(i + 3, n - 1) : 0];
       }
-    }
+      if (act) {
+        if (ok && ckpt && i % kCkpt == 0) store_state(ckpt + (cb + i / kCkpt) * kCkptFloats, q);
+        ++i;
+        if (!ok || i == n) {
+          chi2_out[t] = ok ? chi2 : 0.0f;
+          ok_out[t] = ok ? 1 : 0;
+          t = -1;
+        }
+      }
+    };
+    step(hA, idA);
+    step(hB, idB);
+    step(hC, idC);
   }
 }
 

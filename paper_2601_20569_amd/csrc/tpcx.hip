@@ -285,7 +285,9 @@ void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t) {
   t->construct_grid = 1024;  // 4 blocks of 4 wavefronts per CU, persistent
   t->construct_refill = 16;
   t->refit_grid = 0;
-  t->refit_refill = 16;
+  // lanes refilled only when all of a wavefront's are idle: its lanes then
+  // step through rows together (the filter waits on the cluster loads)
+  t->refit_refill = 64;
 }
 
 tpcx_status tpcx_create(const tpcx_geometry* g, const tpcx_params* p, const tpcx_tuning* tuning,
@@ -524,8 +526,8 @@ void enqueue_batch_refit(const tpcx_ctx* c, const tpcx_clusters* in, const tpcx_
   hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, stream, reinterpret_cast<int64_t*>(RL.queue),
                      int64_t(kXcds), int64_t(0));
   (void)hipStreamWaitEvent(stream, c->ev_join, 0);
-  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, out->cap_tracks, t.refit_grid)),
-                     dim3(kRefitBlock), 0, stream, r, c->dp, RL.corr, 1, static_cast<float*>(nullptr),
+  hipLaunchKernelGGL(k_refit_filter<true>, dim3(refit_filter_grid(c, out->cap_tracks, t.refit_grid)),
+                     dim3(kRefitBlock), 0, stream, r, c->dp, RL.corr, static_cast<float*>(nullptr),
                      RL.queue, t.refit_refill, refit->chi2, refit->ok);
 }
 
@@ -583,7 +585,7 @@ std::vector<tpcx_tuning> autotune_candidates(const tpcx_ctx* c, const tpcx_tunin
       }
       break;
     case 5:
-      for (int r : {4, 8, 16, 32}) {
+      for (int r : {4, 16, 32, 64}) {
         t = b;
         t.refit_refill = r;
         add(t);
@@ -696,8 +698,8 @@ tpcx_status tpcx_refit(tpcx_ctx* c, const tpcx_refit_in* in, const float* theta,
                      int64_t(kXcds), int64_t(0));
   hipLaunchKernelGGL(k_correct_hits, dim3(blocks_for(in->n_tracks, kRefitBlock)), dim3(kRefitBlock), 0,
                      stream, rv, theta, reinterpret_cast<float4*>(L.ws.xyz));
-  hipLaunchKernelGGL(k_refit_filter, dim3(refit_filter_grid(c, in->n_tracks, c->tuning.refit_grid)),
-                     dim3(kRefitBlock), 0, stream, rv, c->dp, reinterpret_cast<const float4*>(L.ws.xyz), 0,
+  hipLaunchKernelGGL(k_refit_filter<false>, dim3(refit_filter_grid(c, in->n_tracks, c->tuning.refit_grid)),
+                     dim3(kRefitBlock), 0, stream, rv, c->dp, reinterpret_cast<const float4*>(L.ws.xyz),
                      L.ws.ckpt, L.ws.queue, c->tuning.refit_refill, chi2, L.ok);
   (void)hipMemcpyAsync(ok, L.ok, sizeof(int32_t) * size_t(in->n_tracks), hipMemcpyDeviceToDevice,
                        stream);
