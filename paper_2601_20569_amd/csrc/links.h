@@ -24,7 +24,9 @@ namespace tpcx {
 // evaluated against all of them; the records are re-read from the cache, so
 // the LDS stays small and occupancy high.
 // Caller ids are read only to break an exact tie of D.  A cluster with more
-// than kNfD candidates in a row takes the direct double scan instead.
+// than kNfD candidates in a row takes the direct double scan instead.  A
+// lane's clusters are software-pipelined: while one is processed, the record
+// of the one after next and the bin ranges of the next are in flight.
 constexpr int kNfD = 8;
 constexpr int kNfBlock = 256;
 
@@ -101,36 +103,71 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
   const int ku = k + 1, kd = k - 1;
   const int64_t bu = g.row_base(ku), bd = g.row_base(kd);
   const int nyu = g.rows[r + 1].ny, nyd = g.rows[r - 1].ny;
-  // wavefront-uniform loop: every lane of a wavefront takes part in the
-  // cooperative collections, lanes past the row's end without a cluster
-  for (int64_t i = b + t; i < e; i += blockDim.x) {
-    const float4 ph = g.pts[i];
-    const float yh = ph.x, zh = ph.y;
+  // Software pipeline over the lane's clusters i, i + B, i + 2B (B the block
+  // size): while cluster i is processed, the record of i + 2B and the bin
+  // ranges of i + B are in flight, so a cluster waits only for its candidates.
+  const float2* yz = reinterpret_cast<const float2*>(g.pts);
+  const int64_t B = blockDim.x;
+  struct Box {
+    int32_t r[8];  // bin ranges: d0s, d0e, d1s, d1e, u0s, u0e, u1s, u1e
+    int mode;      // bit 0: boxes of at most two z bins; bit 1: two down z bins; bit 2: two up z bins
+  };
+  struct Bins {
+    int zu0, zu1, zd0, zd1, yu0, yu1, yd0, yd1;
+  };
+  auto bins_of = [&](float yh, float zh) {
     const float pz = wz + box_pad(zh), py = wy + box_pad(yh);
-    const int zu0 = g.zbin(ku, zh - pz), zu1 = g.zbin(ku, zh + pz);
-    const int zd0 = g.zbin(kd, zh - pz), zd1 = g.zbin(kd, zh + pz);
-    const int yu0 = g.ybin(r + 1, yh - py), yu1 = g.ybin(r + 1, yh + py);
-    const int yd0 = g.ybin(r - 1, yh - py), yd1 = g.ybin(r - 1, yh + py);
-
+    Bins q;
+    q.zu0 = g.zbin(ku, zh - pz);
+    q.zu1 = g.zbin(ku, zh + pz);
+    q.zd0 = g.zbin(kd, zh - pz);
+    q.zd1 = g.zbin(kd, zh + pz);
+    q.yu0 = g.ybin(r + 1, yh - py);
+    q.yu1 = g.ybin(r + 1, yh + py);
+    q.yd0 = g.ybin(r - 1, yh - py);
+    q.yd1 = g.ybin(r - 1, yh + py);
+    return q;
+  };
+  auto box_of = [&](float yh, float zh, Box& x) {
+    const Bins q = bins_of(yh, zh);
+    const bool fast = q.zd1 - q.zd0 <= 1 && q.zu1 - q.zu0 <= 1;
+    x.mode = (fast ? 1 : 0) | (q.zd1 > q.zd0 ? 2 : 0) | (q.zu1 > q.zu0 ? 4 : 0);
+    if (fast) {
+      // the bin ranges of both rows (at most two z bins each)
+      const int64_t rd0 = bd + int64_t(q.zd0) * nyd, rd1 = bd + int64_t(q.zd1) * nyd;
+      const int64_t ru0 = bu + int64_t(q.zu0) * nyu, ru1 = bu + int64_t(q.zu1) * nyu;
+      x.r[0] = g.bin_start[rd0 + q.yd0];
+      x.r[1] = g.bin_start[rd0 + q.yd1 + 1];
+      x.r[2] = g.bin_start[rd1 + q.yd0];
+      x.r[3] = g.bin_start[rd1 + q.yd1 + 1];
+      x.r[4] = g.bin_start[ru0 + q.yu0];
+      x.r[5] = g.bin_start[ru0 + q.yu1 + 1];
+      x.r[6] = g.bin_start[ru1 + q.yu0];
+      x.r[7] = g.bin_start[ru1 + q.yu1 + 1];
+    }
+  };
+  int64_t i = b + t;
+  float2 cur = i < e ? yz[2 * i] : make_float2(0.0f, 0.0f);
+  float2 nxt = i + B < e ? yz[2 * (i + B)] : make_float2(0.0f, 0.0f);
+  Box bx{};
+  if (i < e) box_of(cur.x, cur.y, bx);
+  for (; i < e; i += B) {
+    const float yh = cur.x, zh = cur.y;
+    const float2 nn = i + 2 * B < e ? yz[2 * (i + 2 * B)] : make_float2(0.0f, 0.0f);
+    Box bn{};
+    if (i + B < e) box_of(nxt.x, nxt.y, bn);
     int nd = 0, nu = 0;
-    if (zd1 - zd0 <= 1 && zu1 - zu0 <= 1) {
-      // the bin ranges of both rows (at most two z bins each) first, then
-      // the candidates
-      const int64_t rd0 = bd + int64_t(zd0) * nyd, rd1 = bd + int64_t(zd1) * nyd;
-      const int64_t ru0 = bu + int64_t(zu0) * nyu, ru1 = bu + int64_t(zu1) * nyu;
-      const int32_t d0s = g.bin_start[rd0 + yd0], d0e = g.bin_start[rd0 + yd1 + 1];
-      const int32_t d1s = g.bin_start[rd1 + yd0], d1e = g.bin_start[rd1 + yd1 + 1];
-      const int32_t u0s = g.bin_start[ru0 + yu0], u0e = g.bin_start[ru0 + yu1 + 1];
-      const int32_t u1s = g.bin_start[ru1 + yu0], u1e = g.bin_start[ru1 + yu1 + 1];
-      nf_take_range(g, d0s, d0e, yh, zh, wy, wz, d_pos, t, nd);
-      if (zd1 > zd0) nf_take_range(g, d1s, d1e, yh, zh, wy, wz, d_pos, t, nd);
+    if (bx.mode & 1) {
+      nf_take_range(g, bx.r[0], bx.r[1], yh, zh, wy, wz, d_pos, t, nd);
+      if (bx.mode & 2) nf_take_range(g, bx.r[2], bx.r[3], yh, zh, wy, wz, d_pos, t, nd);
       if (nd > 0) {
-        nf_take_range(g, u0s, u0e, yh, zh, wy, wz, u_pos, t, nu);
-        if (zu1 > zu0) nf_take_range(g, u1s, u1e, yh, zh, wy, wz, u_pos, t, nu);
+        nf_take_range(g, bx.r[4], bx.r[5], yh, zh, wy, wz, u_pos, t, nu);
+        if (bx.mode & 4) nf_take_range(g, bx.r[6], bx.r[7], yh, zh, wy, wz, u_pos, t, nu);
       }
     } else {
-      nd = nf_collect(g, bd, nyd, zd0, zd1, yd0, yd1, yh, zh, wy, wz, d_pos, t);
-      nu = nd > 0 ? nf_collect(g, bu, nyu, zu0, zu1, yu0, yu1, yh, zh, wy, wz, u_pos, t) : 0;
+      const Bins q = bins_of(yh, zh);
+      nd = nf_collect(g, bd, nyd, q.zd0, q.zd1, q.yd0, q.yd1, yh, zh, wy, wz, d_pos, t);
+      nu = nd > 0 ? nf_collect(g, bu, nyu, q.zu0, q.zu1, q.yu0, q.yu1, yh, zh, wy, wz, u_pos, t) : 0;
     }
     float bestD = 0.0f;
     int32_t best_ju = -1, best_jd = -1;
@@ -205,6 +242,9 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
       best_jd = best_c >= 0 ? d_pos[best_c][t] : -1;
     } else {
       // more candidates than LDS holds: scan both rows directly
+      const Bins q = bins_of(yh, zh);
+      const int zu0 = q.zu0, zu1 = q.zu1, zd0 = q.zd0, zd1 = q.zd1;
+      const int yu0 = q.yu0, yu1 = q.yu1, yd0 = q.yd0, yd1 = q.yd1;
       for (int zb = zu0; zb <= zu1; ++zb) {
         const int32_t j0 = g.bin_start[bu + zb * nyu + yu0], j1 = g.bin_start[bu + zb * nyu + yu1 + 1];
         for (int32_t ju = j0; ju < j1; ++ju) {
@@ -223,6 +263,9 @@ __global__ void __launch_bounds__(kNfBlock) k_neighbours(const int64_t* __restri
     }
     up_s[i] = best_ju;
     down_s[i] = best_jd;
+    cur = nxt;
+    nxt = nn;
+    bx = bn;
   }
 }
 
