@@ -60,7 +60,7 @@ B_FIT_PER_HIT = 62             # id, row, y, z read; 16-byte record written once
 # kernels of each stage, for the recorded HBM traffic (profiles/)
 STAGE_KERNELS = {"grid": ["k_grid_build"], "neighbours": ["k_neighbours"],
                  "starts": ["k_clean_starts", "k_write_starts"], "construct": ["k_construct"],
-                 "compact": ["k_keep_count", "k_keep_write"], "refit": ["k_correct_clusters", "k_refit_filter"]}
+                 "compact": ["k_keep_count", "k_keep_write"], "refit": ["k_correct_clusters", "k_refit_filter<true>"]}
 
 
 def recorded_traffic(stage, workload):
