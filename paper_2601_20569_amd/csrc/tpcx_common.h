@@ -122,6 +122,32 @@ __device__ __forceinline__ int64_t xcd_block() {
   return (i / kXcdChunk) * (kXcds * kXcdChunk) + x * kXcdChunk + (i % kXcdChunk);
 }
 
+// Inclusive scans over the 64 lanes of a wavefront on the DPP lane network:
+// inside each row of 16 lanes by shifts of 1, 2, 4 and 8 lanes, then across
+// rows by broadcasting lane 15 into rows 1 and 3 and lane 31 into rows 2 and
+// 3.  A lane whose source lies outside its row (or whose row is masked off)
+// keeps `old`, the operation's identity.  All 64 lanes must be active.
+__device__ __forceinline__ int wave_scan_add(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
+}
+
+// Inclusive maximum scan of values >= -1 (identity -1).
+__device__ __forceinline__ int wave_scan_max(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
+  return x;
+}
+
 __device__ __forceinline__ uint64_t lanes_below() {
   int l = lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));

@@ -203,18 +203,33 @@ __device__ __forceinline__ uint32_t chi2_key(float ch) {
 // holds 5 candidates on average, the largest box of a wavefront ~17): the
 // candidate ranges of one z-bin pair are numbered by a prefix sum over the
 // lanes, and lane l evaluates candidates l, l + 64, l + 128, ... of that
-// numbering (two per round), for their owner lane's state.  The minimum per
-// owner is an LDS atomic on the 64-bit key (chi2, caller id); after each
-// round the lane holding an owner's current minimum stores its coordinates.
-// The result does not depend on which lane evaluates which candidate.  Must
-// be called with all 64 lanes active; `sbest` and `scoord` are the
-// wavefront's 64 LDS slots.
+// numbering (kSearchSub per round), for their owner lane's state.  A
+// candidate's owner is the last lane whose range starts at or before it:
+// each lane marks its start in an LDS window of the round's positions and a
+// maximum scan over the window carries the marks forward.  The owners' states
+// and ranges are read from LDS.  The minimum per owner is an LDS atomic on
+// the 64-bit key (chi2, caller id); after each round the lane holding an
+// owner's current minimum stores its coordinates.  The result does not
+// depend on which lane evaluates which candidate.  Must be called with all
+// 64 lanes active.
+constexpr int kSearchSub = 2;
+
+struct SearchLds {
+  uint64_t best[kWave];
+  float2 coord[kWave];
+  float4 state[kWave];  // origin and state: oy, qy, oz, qz
+  float4 inv[kWave];    // 1/Sy, 1/Sz, second range start (bits)
+  int4 range[kWave];    // first candidate number, count, length and start of the first range
+  int32_t mark[kSearchSub * kWave];
+};
+
 __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox& b, bool searching,
                                                   float oy, float oz, float qy, float qz, float iSy,
-                                                  float iSz, float chi2max, uint64_t* sbest,
-                                                  float2* scoord, float* out_my, float* out_mz) {
+                                                  float iSz, float chi2max, SearchLds& L,
+                                                  float* out_my, float* out_mz) {
   const int lane = lane_id();
-  sbest[lane] = ~0ull;
+  L.best[lane] = ~0ull;
+  L.state[lane] = make_float4(oy, qy, oz, qz);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   for (int zb = b.zb0;; zb += 2) {
     const bool act = searching && zb <= b.zb1;
@@ -231,58 +246,62 @@ __device__ __forceinline__ int32_t kf_search_wave(const Grid& g, const SearchBox
       b0 = k0;
       n = alen + (z2 ? k1 - k0 : 0);
     }
-    int incl = n;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int v = __shfl_up(incl, d, kWave);
-      if (lane >= d) incl += v;
-    }
-    const int total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+    const int incl = wave_scan_add(n);
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+    if (total == 0) continue;
     const int excl = incl - n;
-    for (int t0 = 0; t0 < total; t0 += 2 * kWave) {
-      // two candidates per lane: t0 + lane and t0 + 64 + lane
-      const int ta = t0 + lane, tb = ta + kWave;
-      int oa = 0, ob = 0;
+    L.range[lane] = make_int4(excl, n, alen, a0);
+    L.inv[lane] = make_float4(iSy, iSz, __int_as_float(b0), 0.0f);
+    int carry = -1;  // owner of the position before the round
+    for (int t0 = 0; t0 < total; t0 += kSearchSub * kWave) {
 #pragma unroll
-      for (int st = kWave / 2; st > 0; st >>= 1) {
-        const int va = __shfl(incl, oa + st - 1, kWave);
-        const int vb = __shfl(incl, ob + st - 1, kWave);
-        if (va <= ta) oa += st;
-        if (vb <= tb) ob += st;
+      for (int j = 0; j < kSearchSub; ++j) L.mark[j * kWave + lane] = -1;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      const int rel = excl - t0;
+      if (n > 0 && rel >= 0 && rel < kSearchSub * kWave) L.mark[rel] = lane;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      int own[kSearchSub];
+      bool ok[kSearchSub];
+      float4 m[kSearchSub];
+#pragma unroll
+      for (int j = 0; j < kSearchSub; ++j) {
+        const int o = max(wave_scan_max(L.mark[j * kWave + lane]), carry);
+        carry = __builtin_amdgcn_readlane(o, kWave - 1);
+        own[j] = o & (kWave - 1);
       }
-      const int ua = ta - __shfl(excl, oa, kWave), ub = tb - __shfl(excl, ob, kWave);
-      const int la = __shfl(alen, oa, kWave), lb = __shfl(alen, ob, kWave);
-      const int aa = __shfl(a0, oa, kWave), ab = __shfl(a0, ob, kWave);
-      const int ba = __shfl(b0, oa, kWave), bb = __shfl(b0, ob, kWave);
-      const int pa = ua < la ? aa + ua : ba + (ua - la);
-      const int pb = ub < lb ? ab + ub : bb + (ub - lb);
-      const bool va = ta < total, vb = tb < total;
-      float4 ma = make_float4(0.0f, 0.0f, 0.0f, 0.0f), mb = ma;
-      if (va) ma = g.pts[pa];
-      if (vb) mb = g.pts[pb];
-      // residuals in the owner's coordinates: (cluster - origin) - state
-      const float rya = (ma.x - __shfl(oy, oa, kWave)) - __shfl(qy, oa, kWave);
-      const float rza = (ma.y - __shfl(oz, oa, kWave)) - __shfl(qz, oa, kWave);
-      const float cha = (rya * rya) * __shfl(iSy, oa, kWave) + (rza * rza) * __shfl(iSz, oa, kWave);
-      const float ryb = (mb.x - __shfl(oy, ob, kWave)) - __shfl(qy, ob, kWave);
-      const float rzb = (mb.y - __shfl(oz, ob, kWave)) - __shfl(qz, ob, kWave);
-      const float chb = (ryb * ryb) * __shfl(iSy, ob, kWave) + (rzb * rzb) * __shfl(iSz, ob, kWave);
-      const bool oka = va && cha <= chi2max, okb = vb && chb <= chi2max;
-      const uint64_t ka = (uint64_t(chi2_key(cha)) << 32) | uint32_t(__float_as_int(ma.z));
-      const uint64_t kb = (uint64_t(chi2_key(chb)) << 32) | uint32_t(__float_as_int(mb.z));
-      if (oka) atomicMin(&sbest[oa], (unsigned long long)ka);
-      if (okb) atomicMin(&sbest[ob], (unsigned long long)kb);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (oka && __hip_atomic_load(&sbest[oa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == ka)
-        scoord[oa] = make_float2(ma.x, ma.y);
-      if (okb && __hip_atomic_load(&sbest[ob], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == kb)
-        scoord[ob] = make_float2(mb.x, mb.y);
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      // candidate positions (an invalid slot reads position 0, which exists
+      // whenever there are candidates), all gathers issued before any use
+#pragma unroll
+      for (int j = 0; j < kSearchSub; ++j) {
+        const int t = t0 + j * kWave + lane;
+        const int4 r = L.range[own[j]];
+        const int u = t - r.x;
+        ok[j] = (t < total) & (u >= 0) & (u < r.y);
+        const int pb = __float_as_int(L.inv[own[j]].z) + (u - r.z);
+        const int pos = u < r.z ? r.w + u : pb;
+        m[j] = g.pts[ok[j] ? pos : 0];
+      }
+#pragma unroll
+      for (int j = 0; j < kSearchSub; ++j) {
+        // residuals in the owner's coordinates: (cluster - origin) - state
+        const float4 st = L.state[own[j]];
+        const float4 iv = L.inv[own[j]];
+        const float ry = (m[j].x - st.x) - st.y;
+        const float rz = (m[j].y - st.z) - st.w;
+        const float ch = (ry * ry) * iv.x + (rz * rz) * iv.y;
+        ok[j] = ok[j] && ch <= chi2max;
+        const uint64_t k = (uint64_t(chi2_key(ch)) << 32) | uint32_t(__float_as_int(m[j].z));
+        if (ok[j]) atomicMin(&L.best[own[j]], (unsigned long long)k);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (ok[j] && __hip_atomic_load(&L.best[own[j]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == k)
+          L.coord[own[j]] = make_float2(m[j].x, m[j].y);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      }
     }
   }
-  const uint64_t key = __hip_atomic_load(&sbest[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  const uint64_t key = __hip_atomic_load(&L.best[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
   if (!searching || key == ~0ull) return -1;
-  const float2 cc = scoord[lane];
+  const float2 cc = L.coord[lane];
   *out_my = cc.x;
   *out_mz = cc.y;
   return int32_t(uint32_t(key));
@@ -340,8 +359,7 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     TrackInputs in, Grid g, DevParams p, TrackletTmp out) {
   __shared__ int32_t hbuf[kConstructWaves][kHitBuf][kWave];
   __shared__ uint32_t rmask[kConstructWaves][kMaskWords][kWave];
-  __shared__ uint64_t sbest[kConstructWaves][kWave];
-  __shared__ float2 scoord[kConstructWaves][kWave];
+  __shared__ SearchLds slds[kConstructWaves];
   const int64_t n_start = counts[0] < cap_start ? counts[0] : cap_start;
   const bool ordered = counts[0] <= cap_start;
   const int R = g.n_rows;
@@ -529,7 +547,7 @@ __global__ void __launch_bounds__(kConstructBlock, 4) k_construct(
     if (__ballot(searching) != 0ull) {
       float sy = 0.0f, sz = 0.0f;
       const int32_t sc = kf_search_wave(g, box, searching, oy, oz, q.y, q.z, iSy, iSz, p.chi2max,
-                                        sbest[wv], scoord[wv], &sy, &sz);
+                                        slds[wv], &sy, &sz);
       if (searching) {
         c = sc;
         my = sy;
