@@ -370,9 +370,13 @@ typedef struct {
   uint8_t* reject;  /* [n_hits] 1: cluster rejected */
 } tpcx_fit_out;
 
-/* Workspace of tpcx_fit: 16 bytes per hit (the stored iteration-1 record)
- * and 4 bytes per track (the processing order: longest tracks first within
- * chunks of consecutive tracks).  n_tracks < 2^31. */
+/* Workspace of tpcx_fit: 17 bytes per record slot (the stored iteration-1
+ * record and its row), n_hits slots plus 16384 per 8192 tracks (the slack of
+ * the per-wavefront interleaved layout; a track of 256 or more clusters may
+ * make the fit fall back to one record per hit in track order, same results),
+ * 16 bytes per 64 tracks and 4 bytes per track (the processing order:
+ * longest tracks first within chunks of 8192 consecutive tracks).
+ * n_tracks < 2^31. */
 size_t tpcx_fit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_tracks, int64_t n_hits);
 
 /* Enqueues the fit of every track of `in`; ws 256-byte aligned. */

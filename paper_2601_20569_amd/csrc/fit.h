@@ -6,7 +6,10 @@
 // and cuts, the third applies the rejection).
 //
 // One lane per track, tracks taken longest first within chunks of
-// consecutive tracks (so the lanes of a wavefront have equal work).  Iteration 1 walks from the tracking result at x_ref
+// consecutive tracks (so the lanes of a wavefront have equal work); the
+// stored records are interleaved per wavefront so that its lanes read and
+// write one contiguous block per step, and every step's record and row are
+// loaded one step ahead.  Iteration 1 walks from the tracking result at x_ref
 // out to the outermost cluster, restarts there (y, z of the cluster, diagonal
 // covariance) and goes inwards; at every cluster it stores, per hit, the
 // cluster relative to the track's origin (its outermost cluster) and the
@@ -28,6 +31,7 @@ namespace tpcx {
 
 struct FitIn {
   int64_t n_tracks;
+  int32_t n_rows;  // of row_x (at most 255)
   const int64_t* hit_begin;
   const int32_t* hit_id;
   const uint8_t* hit_row;
@@ -96,22 +100,78 @@ __device__ __forceinline__ float fit_czz(const KState& q) {
   return q.dz + q.uzt * ctz;
 }
 
-// rec[q] = (cluster y, z relative to the origin, bf16 (d_y | d_z), bf16 (C_yy | C_zz)).
+// Records of iteration 1 (and the rows of a track's clusters) in a
+// workspace of `cap` slots.  When the wavefronts' records fit (every track
+// shorter than 256 clusters guarantees it), wavefront w's slots start at
+// wbase[w] and record i of its lane l is slot wbase[w] + 64 i + l: the 64
+// lanes' records of one step are one contiguous 1 KiB (coalesced).
+// Otherwise record i of a track is slot hit_begin + i.  The layout changes
+// no value.
+struct FitWs {
+  float4* rec;
+  uint8_t* rows;
+  const int64_t* wbase;  // [n_waves + 1]; wbase[n_waves] = slots needed
+  int64_t cap;
+};
+
+// wlen[w] = 64 x the longest track of wavefront w (processing order).
+__global__ void k_fit_wave_len(int64_t n, const int64_t* __restrict__ hit_begin,
+                               const int32_t* __restrict__ order, int64_t* __restrict__ wlen) {
+  const int64_t gid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int m = 0;
+  if (gid < n) {
+    const int64_t t = order[gid];
+    m = int(min(hit_begin[t + 1] - hit_begin[t], int64_t(1) << 30));
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) m = max(m, __shfl_xor(m, d, kWave));
+  if (lane_id() == 0 && gid < n) wlen[gid / kWave] = int64_t(m) * kWave;
+}
+
+// wbase[0 .. nw] = exclusive prefix sum of wlen[0 .. nw); one block of
+// kFitScanThreads, each summing a contiguous run.
+constexpr int kFitScanThreads = 1024;
+
+__global__ void __launch_bounds__(kFitScanThreads) k_fit_scan(int64_t nw, const int64_t* __restrict__ wlen,
+                                                             int64_t* __restrict__ wbase) {
+  __shared__ int64_t lds[kFitScanThreads / kWave];
+  const int64_t per = (nw + kFitScanThreads - 1) / kFitScanThreads;
+  const int64_t b = min(nw, int64_t(threadIdx.x) * per), e = min(nw, b + per);
+  int64_t s = 0;
+  for (int64_t w = b; w < e; ++w) s += wlen[w];
+  int64_t tot;
+  int64_t run = block_exclusive_scan(s, lds, &tot);
+  for (int64_t w = b; w < e; ++w) {
+    wbase[w] = run;
+    run += wlen[w];
+  }
+  if (threadIdx.x == 0) wbase[nw] = tot;
+}
+
+// rec slot = (cluster y, z relative to the origin, bf16 (d_y | d_z), bf16 (C_yy | C_zz));
+// iteration 2 replaces the last word by the rejection flag.
 __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts f, const int32_t* __restrict__ order,
-                                               float4* __restrict__ rec, FitOut out) {
+                                               FitWs ws, FitOut out) {
+  __shared__ float srx[256];
+  for (int r = threadIdx.x; r < 256; r += kWave) srx[r] = r < in.n_rows ? in.row_x[r] : __builtin_nanf("");
+  __syncthreads();
   const int64_t gid = int64_t(blockIdx.x) * kWave + threadIdx.x;
   if (gid >= in.n_tracks) return;
+  const int64_t nw = (in.n_tracks + kWave - 1) / kWave;
+  const bool inter = ws.wbase[nw] <= ws.cap;
   const int64_t t = order[gid];
   const int64_t b = in.hit_begin[t];
   const int n = int(in.hit_begin[t + 1] - b);
-  float4* R = rec + b;
+  const int64_t s0 = inter ? ws.wbase[blockIdx.x] + threadIdx.x : b;
+  const int64_t ss = inter ? kWave : 1;
+  float4* R = ws.rec + s0;
+  const uint8_t* rowp = inter ? ws.rows + s0 : in.hit_row + b;  // rows for iterations 2, 3
   uint8_t* rej = out.reject + b;
   bool good = n >= 3;
   int kept = 0;
   float chi2 = 0.0f;
   KState last{};
-  const float oy = in.y[in.hit_id[b + n - 1]], oz = in.z[in.hit_id[b + n - 1]];
-  auto X = [&](int i) { return in.row_x[in.hit_row[b + i]]; };
+  const float oy = good ? in.y[in.hit_id[b + n - 1]] : 0.0f, oz = good ? in.z[in.hit_id[b + n - 1]] : 0.0f;
+  auto X = [&](int i) { return srx[in.hit_row[b + i]]; };
   if (good) {
     // ---- iteration 1: inwards, storing the predictions
     const float* sd = in.seed + 5 * t;
@@ -126,38 +186,53 @@ __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts 
     fit_reset_cov(q, p, f);
     int first = 0;
     while (first < n && !(X(first) > xref)) ++first;
-    for (int i = first; i < n && good; ++i)
-      if (!(q.x == X(i))) good = fit_prop(q, X(i), p);
-    if (good && !(q.x == X(n - 1))) good = fit_prop(q, X(n - 1), p);
+    {
+      // out to the outermost cluster; the next row is loaded one step ahead
+      int rn = first < n ? in.hit_row[b + first] : 0;
+      for (int i = first; i < n && good; ++i) {
+        const float xi = srx[rn];
+        if (i + 1 < n) rn = in.hit_row[b + i + 1];
+        if (!(q.x == xi)) good = fit_prop(q, xi, p);
+      }
+    }
+    const float xo = X(n - 1);
+    if (good && !(q.x == xo)) good = fit_prop(q, xo, p);
     if (good) {
       q.y = 0.0f;  // the outermost cluster is the origin
       q.z = 0.0f;
       fit_reset_cov(q, p, f);
-      R[n - 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      // the cluster of the next step is loaded one step ahead
+      R[(n - 1) * ss] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (inter) ws.rows[s0 + (n - 1) * ss] = in.hit_row[b + n - 1];
+      // the cluster and row of the next step are loaded one step ahead
       int32_t cn = in.hit_id[b + n - 2];
       float yn = in.y[cn], zn = in.z[cn];
+      int rn = in.hit_row[b + n - 2];
       for (int i = n - 2; i >= 0 && good; --i) {
         const float ry = yn - oy, rz = zn - oz;
+        const int ri = rn;
         if (i > 0) {
           cn = in.hit_id[b + i - 1];
           yn = in.y[cn];
           zn = in.z[cn];
+          rn = in.hit_row[b + i - 1];
         }
-        good = fit_prop(q, X(i), p);
+        if (inter) ws.rows[s0 + i * ss] = uint8_t(ri);
+        good = fit_prop(q, srx[ri], p);
         if (!good) break;
         const uint32_t dd = bf16_bits(q.y - ry) | (bf16_bits(q.z - rz) << 16);
         const uint32_t cc = bf16_bits(fit_cyy(q)) | (bf16_bits(fit_czz(q)) << 16);
-        R[i] = make_float4(ry, rz, __uint_as_float(dd), __uint_as_float(cc));
+        R[i * ss] = make_float4(ry, rz, __uint_as_float(dd), __uint_as_float(cc));
         fit_update(q, ry, rz, p);
       }
     }
     // ---- iteration 2: outwards, interpolation and chi2 cut
     if (good) {
-      const float4 r0 = R[0];
+      float4 rn = R[0];
+      int xn = rowp[0];
+      const float4 r0 = rn;
       const float s1 = q.s, t1 = q.t, w1 = q.w;
       q = KState{};
-      q.x = X(0);
+      q.x = srx[xn];
       q.y = r0.x;
       q.z = r0.y;
       q.s = s1;
@@ -165,11 +240,17 @@ __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts 
       q.w = w1;
       fit_reset_cov(q, p, f);
       for (int i = 0; i < n && good; ++i) {
+        // record and row of step i + 1 loaded one step ahead
+        const float4 ri = rn;
+        const int xi = xn;
+        if (i + 1 < n) {
+          rn = R[(i + 1) * ss];
+          xn = rowp[(i + 1) * ss];
+        }
         if (i > 0) {
-          good = fit_prop(q, X(i), p);
+          good = fit_prop(q, srx[xi], p);
           if (!good) break;
         }
-        const float4 ri = R[i];
         const float ry = i == n - 1 ? 0.0f : ri.x, rz = i == n - 1 ? 0.0f : ri.y;
         float dy, dz, vy, vz;
         if (i == 0) {
@@ -198,27 +279,37 @@ __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts 
           }
         }
         const float c2 = (dy * dy) / (vy + p.sy2) + (dz * dz) / (vz + p.sz2);
-        rej[i] = c2 > f.chi2_cut ? 1 : 0;
+        const uint8_t rj = c2 > f.chi2_cut ? 1 : 0;
+        rej[i] = rj;
+        reinterpret_cast<float*>(&R[i * ss])[3] = __uint_as_float(uint32_t(rj));
         if (i > 0) fit_update(q, ry, rz, p);
       }
     }
     // ---- iteration 3: inwards over the kept clusters
     if (good) {
+      auto flag = [&](int i) { return __float_as_uint(reinterpret_cast<const float*>(&R[i * ss])[3]) != 0u; };
       int j = n - 1;
-      while (j >= 0 && rej[j]) --j;
+      while (j >= 0 && flag(j)) --j;
       good = j >= 2;
-      for (int i = n - 2; i >= j && good; --i) good = fit_prop(q, X(i), p);
+      for (int i = n - 2; i >= j && good; --i) good = fit_prop(q, srx[rowp[i * ss]], p);
       if (good) {
-        const float4 rj = R[j];
+        const float4 rj = R[j * ss];
         q.y = j == n - 1 ? 0.0f : rj.x;
         q.z = j == n - 1 ? 0.0f : rj.y;
         fit_reset_cov(q, p, f);
         kept = 1;
         last = q;
+        float4 rn = j > 0 ? R[(j - 1) * ss] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int xn = j > 0 ? rowp[(j - 1) * ss] : 0;
         for (int i = j - 1; i >= 0 && good; --i) {
-          good = fit_prop(q, X(i), p);
-          if (!good || rej[i]) continue;
-          const float4 ri = R[i];
+          const float4 ri = rn;
+          const int xi = xn;
+          if (i > 0) {
+            rn = R[(i - 1) * ss];
+            xn = rowp[(i - 1) * ss];
+          }
+          good = fit_prop(q, srx[xi], p);
+          if (!good || __float_as_uint(ri.w) != 0u) continue;
           chi2 = chi2 + fit_update(q, ri.x, ri.y, p);
           ++kept;
           last = q;

@@ -929,12 +929,45 @@ tpcx_status tpcx_timing_read(tpcx_ctx* c, float* ms_host, int32_t* n_calls) {
   return TPCX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Fit workspace: record slots for n_hits plus, per chunk of the length
+// order, one wavefront's worth of the longest possible track (the slack of
+// the per-wavefront layout when every track has fewer than 256 clusters),
+// the rows of the slots, per-wavefront sizes and offsets, the order.
+struct FitLayout {
+  float4* rec;
+  uint8_t* rows;
+  int64_t* wlen;
+  int64_t* wbase;
+  int32_t* order;
+  int64_t cap;
+  size_t bytes;
+};
+
+FitLayout carve_fit(void* base, int64_t n_tracks, int64_t n_hits) {
+  Carver cv{static_cast<char*>(base)};
+  FitLayout L{};
+  const int64_t nw = (n_tracks + kWave - 1) / kWave;
+  L.cap = n_hits + (n_tracks + kLenChunk - 1) / kLenChunk * int64_t(kWave) * 256;
+  L.rec = cv.take<float4>(L.cap);
+  L.rows = cv.take<uint8_t>(L.cap);
+  L.wlen = cv.take<int64_t>(nw);
+  L.wbase = cv.take<int64_t>(nw + 1);
+  L.order = cv.take<int32_t>(n_tracks);
+  L.bytes = cv.off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t tpcx_fit_workspace_bytes(const tpcx_ctx* c, int64_t n_tracks, int64_t n_hits) {
   if (!c || n_tracks < 0 || n_hits < 0) return 0;
-  Carver cv{nullptr};
-  cv.take<float4>(n_hits);
-  cv.take<int32_t>(n_tracks);
-  return cv.off;
+  return carve_fit(nullptr, n_tracks, n_hits).bytes;
 }
 
 tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* fp, const tpcx_fit_out* out,
@@ -948,10 +981,8 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
     return TPCX_E_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
   if (in->n_tracks >= (int64_t(1) << 31)) return TPCX_E_ARG;
-  Carver cv{static_cast<char*>(ws)};
-  auto* rec = cv.take<float4>(in->n_hits);
-  auto* order = cv.take<int32_t>(in->n_tracks);
-  if (!ws || ws_bytes < cv.off) return TPCX_E_ARG;
+  const FitLayout L = carve_fit(ws, in->n_tracks, in->n_hits);
+  if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
   if (in->n_tracks == 0) return TPCX_OK;
@@ -965,6 +996,7 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   fi.y = in->y;
   fi.z = in->z;
   fi.row_x = c->d_row_x;
+  fi.n_rows = c->n_rows;
   FitOut fo;
   fo.param = out->param;
   fo.cov = out->cov;
@@ -974,9 +1006,14 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   fo.ok = out->ok;
   fo.reject = out->reject;
   const FitConsts f{fp->chi2_cut, fp->var_s, fp->var_t, fp->var_w};
-  enqueue_length_order(in->n_tracks, in->hit_begin, order, stream);
-  hipLaunchKernelGGL(k_fit, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream, fi, c->dp, f, order,
-                     rec, fo);
+  enqueue_length_order(in->n_tracks, in->hit_begin, L.order, stream);
+  const int64_t nw = (in->n_tracks + kWave - 1) / kWave;
+  hipLaunchKernelGGL(k_fit_wave_len, dim3(blocks_for(in->n_tracks, 256)), dim3(256), 0, stream, in->n_tracks,
+                     in->hit_begin, L.order, L.wlen);
+  hipLaunchKernelGGL(k_fit_scan, dim3(1), dim3(kFitScanThreads), 0, stream, nw, L.wlen, L.wbase);
+  const FitWs fw{L.rec, L.rows, L.wbase, L.cap};
+  hipLaunchKernelGGL(k_fit, dim3(blocks_for(in->n_tracks, kWave)), dim3(kWave), 0, stream, fi, c->dp, f, L.order,
+                     fw, fo);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
 
