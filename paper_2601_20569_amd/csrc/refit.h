@@ -973,18 +973,20 @@ __global__ void __launch_bounds__(kRefitBlock) k_refit_bwd_scatter(RefitIn in, R
   float ph = fmodf(al[0], 6.28318530717958647692f);
   if (ph < 0.0f) ph += 6.28318530717958647692f;
   const int wref = int(floorf(ph / kMapDPhi));
+  // the lanes of a wavefront take the hits of 64 different tracks (thread
+  // tid: track tid % 64, every (blockDim / 64)-th hit of it): consecutive
+  // hits of one track share most of their 64 nodes, and same-address LDS
+  // atomics of one instruction are serialised
   const float4* hg = reinterpret_cast<const float4*>(ws.hgrad);
-  for (int64_t q = hb[0] + tid; q < hb[cnt]; q += blockDim.x) {
-    const float4 g = hg[q];
-    if (g.x == 0.0f && g.y == 0.0f && g.z == 0.0f) continue;
-    int lo = 0, hi = cnt - 1;  // last s with hb[s] <= q
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (hb[mid] <= q) lo = mid; else hi = mid - 1;
+  const int trk = tid % kScatterTracks, nsub = blockDim.x / kScatterTracks;
+  if (trk < cnt) {
+    for (int64_t q = hb[trk] + tid / kScatterTracks; q < hb[trk + 1]; q += nsub) {
+      const float4 g = hg[q];
+      if (g.x == 0.0f && g.y == 0.0f && g.z == 0.0f) continue;
+      float r;
+      const HitGeom h = hit_geom(in.row_x[in.hit_row[q]], in.y[in.hit_id[q]], in.z[in.hit_id[q]], al[trk], &r);
+      add_hit_gradient(h, r, g.x, g.y, g.z, wref, win, ws.acc);
     }
-    float r;
-    const HitGeom h = hit_geom(in.row_x[in.hit_row[q]], in.y[in.hit_id[q]], in.z[in.hit_id[q]], al[lo], &r);
-    add_hit_gradient(h, r, g.x, g.y, g.z, wref, win, ws.acc);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nwin; i += blockDim.x) {
