@@ -14,7 +14,9 @@
 // cut, keeps the K best by (chi2, caller id) and updates with the best.
 // k_rebuild_propose / k_rebuild_advance: R rounds of proposals; a cluster's
 // holder is the atomic maximum of its proposers' 64-bit rank keys, so the
-// result does not depend on the order of the atomics.
+// result does not depend on the order of the atomics.  Only a (track, row)
+// whose candidate changed proposes again (a key once proposed stays below
+// the holder's, which only grows).
 // k_rebuild_pass3: iteration 3 over the rows whose candidate the track holds.
 // IEEE binary32, no contraction, correctly rounded divide and square root.
 #pragma once
@@ -27,6 +29,9 @@
 namespace tpcx {
 
 constexpr int kRebuildK = 4;  // candidates kept per (track, row)
+// ptr byte of a (track, row): the current candidate in the low bits, and
+// kPtrMoved while that candidate has not been proposed yet
+constexpr uint8_t kPtrMoved = 0x80;
 
 struct RebuildIn {
   int64_t n_tracks;
@@ -228,7 +233,7 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
     int32_t best = -1;
     cnt[r] = uint8_t(rb_row_candidates(g, p, kb, r, oy, oz, pr.x, pr.y, bf16_lo(cc), bf16_hi(cc), f.chi2_extrap,
                                        cand + r * kRebuildK, &best));
-    ptr[r] = 0;
+    ptr[r] = kPtrMoved;
   }
   q = KState{};
   q.x = X(r_in);
@@ -270,7 +275,7 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
     int32_t best = -1;
     const int nb = rb_row_candidates(g, p, kb, r, oy, oz, iy, iz, vy, vz, f.chi2_cut, cand + r * kRebuildK, &best);
     cnt[r] = uint8_t(nb);
-    ptr[r] = 0;
+    ptr[r] = kPtrMoved;
     if (r > r_in && nb > 0) fit_update(q, in.y[best] - oy, in.z[best] - oz, p);
   }
   // Phase III outwards: the final state carried further out, without
@@ -284,7 +289,7 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
       int32_t best = -1;
       cnt[r] = uint8_t(rb_row_candidates(g, p, kb, r, oy, oz, q.y, q.z, fit_cyy(q), fit_czz(q), f.chi2_extrap,
                                          cand + r * kRebuildK, &best));
-      ptr[r] = 0;
+      ptr[r] = kPtrMoved;
       r_hi = r;
     }
   }
@@ -305,7 +310,10 @@ __global__ void __launch_bounds__(kWave) k_rebuild_propose(RebuildIn in, Rebuild
   const int R = in.n_rows;
   const unsigned long long key = ws.key[t];
   for (int r = meta[1]; r <= meta[2]; ++r) {
-    const int k = ws.ptr[t * R + r];
+    const int v = ws.ptr[t * R + r];
+    if (!(v & kPtrMoved)) continue;
+    const int k = v & ~kPtrMoved;
+    ws.ptr[t * R + r] = uint8_t(k);
     if (k < ws.cnt[t * R + r]) atomicMax(ws.holder + ws.cand[(t * R + r) * kRebuildK + k].x, key);
   }
 }
@@ -318,8 +326,9 @@ __global__ void __launch_bounds__(kWave) k_rebuild_advance(RebuildIn in, Rebuild
   const int R = in.n_rows;
   const unsigned long long key = ws.key[t];
   for (int r = meta[1]; r <= meta[2]; ++r) {
-    uint8_t& k = ws.ptr[t * R + r];
-    if (k < ws.cnt[t * R + r] && ws.holder[ws.cand[(t * R + r) * kRebuildK + k].x] != key) ++k;
+    const int k = ws.ptr[t * R + r] & ~kPtrMoved;
+    if (k < ws.cnt[t * R + r] && ws.holder[ws.cand[(t * R + r) * kRebuildK + k].x] != key)
+      ws.ptr[t * R + r] = uint8_t(k + 1) | kPtrMoved;
   }
 }
 
@@ -343,7 +352,7 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass3(RebuildIn in, DevParams
   const int r_in = meta[1], r_out = meta[2];
   const unsigned long long key = ws.key[t];
   auto got = [&](int r) -> int32_t {
-    const int k = ws.ptr[t * R + r];
+    const int k = ws.ptr[t * R + r] & ~kPtrMoved;
     if (k >= ws.cnt[t * R + r]) return -1;
     const int32_t id = ws.cand[(t * R + r) * kRebuildK + k].x;
     return ws.holder[id] == key ? id : -1;
