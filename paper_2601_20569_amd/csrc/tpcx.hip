@@ -277,9 +277,10 @@ extern "C" {
 void tpcx_default_tuning(int32_t n_units, int64_t n_clusters, tpcx_tuning* t) {
   if (!t) return;
   t->bin_y = 2.0f;
-  // about one cluster per bin for rows ~30 y-bins wide
+  // about half a cluster per bin for rows ~30 y-bins wide (fewer candidates
+  // per search box; finer bins than that cost more bin-range loads)
   const double per_row = double(n_clusters) / std::max(1.0, double(n_units) * 152.0);
-  int nz = int(per_row / 30.0);
+  int nz = int(per_row / 15.0);
   t->n_zbins = std::max(4, std::min(nz, 4096));
   t->block = 256;
   t->construct_grid = 1024;  // 4 blocks of 4 wavefronts per CU, persistent
