@@ -63,18 +63,44 @@ STAGE_KERNELS = {"grid": ["k_grid_build"], "neighbours": ["k_neighbours"],
                  "compact": ["k_keep_count", "k_keep_write"], "refit": ["k_correct_clusters", "k_refit_filter<true>"]}
 
 
-def recorded_traffic(stage, workload):
-    """HBM bytes per launch of a stage's kernels from the committed counter
-    summary, or None when it is missing or the kernel sources changed since."""
+def source_sha256():
+    """Hash of the kernel sources, as recorded in the counter summaries."""
     import glob
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
-    if not os.path.exists(path):
-        return None
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2601_20569_amd", "csrc", "*"))):
         with open(f, "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_valu(stage, workload):
+    """Per-kernel VALU issue rate per CU-cycle, active lanes, waiting fraction
+    and L2 hit rate of a stage's kernels from the committed counter summary,
+    or None when it is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec, sha = {}, None
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("source_sha256:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("valu "):
+            k, v = line[len("valu "):].split(":", 1)
+            rec[k.strip()] = {kv.split("=")[0]: float(kv.split("=")[1]) for kv in v.split()}
+    if sha != source_sha256():
+        return None
+    ks = [k for k in STAGE_KERNELS.get(stage, []) if k in rec]
+    return {k: rec[k] for k in ks} or None
+
+
+def recorded_traffic(stage, workload):
+    """HBM bytes per launch of a stage's kernels from the committed counter
+    summary, or None when it is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
     rec, sha = {}, None
     for line in open(path):
         line = line.strip()
@@ -83,7 +109,7 @@ def recorded_traffic(stage, workload):
         elif line.startswith("traffic_bytes_per_launch "):
             k, v = line[len("traffic_bytes_per_launch "):].split(":")
             rec[k.strip()] = int(v)
-    if sha != h.hexdigest():
+    if sha != source_sha256():
         return None
     ks = STAGE_KERNELS.get(stage, [])
     if not ks or any(k not in rec for k in ks):
@@ -625,7 +651,8 @@ def main():
         roof = dict(bound="hbm", achieved=round(gbs, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(gbs / HBM_PEAK_GBS, 5), traffic=tr_b,
                     copy_GBs=round(copy_gbs, 1), frac_of_copy=round(gbs / copy_gbs, 5), kernel=dom,
-                    kernels=STAGE_KERNELS.get(dom), kernel_ms=round(stage_ms[dom], 4), alg_bytes=int(b))
+                    kernels=STAGE_KERNELS.get(dom), kernel_ms=round(stage_ms[dom], 4), alg_bytes=int(b),
+                    valu=recorded_valu(dom, cfg["workload"]))
 
     known = [k for k in stage_ms if stage_bytes.get(k) is not None]
     # every stage against HBM: algorithmic bytes over its measured time, and
@@ -633,7 +660,8 @@ def main():
     stages_roof = {k: dict(alg_bytes=int(stage_bytes[k]),
                            GBs=round(stage_bytes[k] / (stage_ms[k] * 1e-3) / 1e9, 2),
                            frac=round(stage_bytes[k] / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
-                           traffic=recorded_traffic(k, cfg["workload"]))
+                           traffic=recorded_traffic(k, cfg["workload"]),
+                           valu=recorded_valu(k, cfg["workload"]))
                    for k in known if stage_ms[k] > 0}
     path = None
     if len(known) == len(stage_ms):

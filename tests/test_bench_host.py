@@ -36,6 +36,21 @@ def test_traffic_dropped_when_sources_changed(tmp_path, monkeypatch):
     assert bench.recorded_traffic("construct", "wl") is None
 
 
+def test_valu_figures_read_only_when_sources_match(tmp_path, monkeypatch):
+    _tree(tmp_path, "kernel v1")
+    h = hashlib.sha256(b"kernel v1").hexdigest()
+    (tmp_path / "profiles" / "valu_wl.md").write_text(
+        "# summary\n\n```\n"
+        f"source_sha256: {h}\n"
+        "valu k_construct: per_cu_cycle=0.8 lanes=0.75 waiting=0.6 l2_hit=0.26\n```\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.recorded_valu("construct", "wl") == {
+        "k_construct": {"per_cu_cycle": 0.8, "lanes": 0.75, "waiting": 0.6, "l2_hit": 0.26}}
+    assert bench.recorded_valu("refit", "wl") is None
+    (tmp_path / "paper_2601_20569_amd" / "csrc" / "a.h").write_text("kernel v2")
+    assert bench.recorded_valu("construct", "wl") is None
+
+
 def test_committed_summary_names_every_timed_kernel():
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "profiles",
                         "hbm_traffic_timeframe-slice-batch.md")
