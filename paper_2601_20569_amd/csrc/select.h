@@ -17,8 +17,16 @@
 //   decide   a tracklet is kept when, walking its clusters from the outermost
 //            row inwards, after every step k the count s(k) of clusters owned
 //            by another tracklet satisfies den s(k) <= num k;
-//   assign   the claim again with the kept tracklets only; each cluster goes
-//            to the kept tracklet whose key won (-1 when none holds it).
+//   reclaim  each kept tracklet replaces owner[c] by its key where the
+//            holder is a rejected tracklet or a kept one with a smaller key
+//            (compare-and-swap; where a kept tracklet holds the largest key
+//            of all, the common case, nothing is written), so owner[c] ends
+//            as the largest kept key, or a rejected key when no kept
+//            tracklet contains c;
+//   assign   each cluster goes to the kept tracklet whose key it holds (-1
+//            when none): at once, in the reclaim, where that is the largest
+//            key of all claimants; else by a pass over the tracklets that won
+//            a swap.
 #pragma once
 
 #include "tpcx_common.h"
@@ -88,6 +96,50 @@ __global__ void k_select_claim(SelectIn in, const int64_t* __restrict__ first,
   }
 }
 
+// The holder of owner word `cur` of a cluster of unit u (first[u] its first
+// tracklet): the tracklet whose key it is.
+__device__ __forceinline__ int64_t select_holder(unsigned long long cur, int64_t first_u, int64_t n) {
+  const int64_t t = first_u + (kSelectMaxPerUnit - 1 - int64_t(cur & (kSelectMaxPerUnit - 1)));
+  return t < n ? t : n - 1;  // (a unit of more than 2^24 tracklets is reported and its keys collide)
+}
+
+// owner[c] = the largest key of the kept tracklets containing c, where one
+// does; one lane per kept tracklet.  A kept tracklet that holds the largest
+// key of all claimants of c assigns c at once (no other tracklet writes
+// that word); one that wins a swap is marked (keep 3) for the assign pass.
+__global__ void k_select_reclaim(SelectIn in, const int64_t* __restrict__ first, uint8_t* __restrict__ keep,
+                                 unsigned long long* __restrict__ owner, int32_t* __restrict__ assign) {
+  const int64_t n = select_count(in);
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    if (!keep[t]) continue;
+    const unsigned long long key = select_key(in, first, t);
+    const int64_t fu = first[in.unit[t]];
+    const int64_t b = in.hit_begin[t];
+    const int m = in.n_hits[t];
+    bool swapped = false;
+    for (int j = 0; j < m; ++j) {
+      const int32_t c = in.hit_id[b + j];
+      unsigned long long* o = owner + c;
+      unsigned long long cur = __hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur == key) {  // the largest key of all: only this tracklet wrote it
+        assign[c] = int32_t(t);
+        continue;
+      }
+      while (true) {
+        if (cur > key && keep[select_holder(cur, fu, n)]) break;
+        const unsigned long long seen = atomicCAS(o, cur, key);
+        if (seen == cur) {
+          swapped = true;
+          break;
+        }
+        cur = seen;
+      }
+    }
+    if (swapped) keep[t] = 3;
+  }
+}
+
 // keep[t] from the outer-first shared count; n_sel[0] += kept tracklets.
 __global__ void k_select_decide(SelectIn in, const int64_t* __restrict__ first,
                                 const unsigned long long* __restrict__ owner, int32_t num, int32_t den,
@@ -117,14 +169,15 @@ __global__ void k_select_decide(SelectIn in, const int64_t* __restrict__ first,
                                         static_cast<unsigned long long>(kept));
 }
 
-// assign[c] = t for every cluster whose owner key is kept tracklet t's.
-__global__ void k_select_assign(SelectIn in, const int64_t* __restrict__ first,
-                                const uint8_t* __restrict__ keep,
+// assign[c] = t for every cluster whose owner key is tracklet t's, for the
+// tracklets the reclaim marked; their mark is cleared (keep 1).
+__global__ void k_select_assign(SelectIn in, const int64_t* __restrict__ first, uint8_t* __restrict__ keep,
                                 const unsigned long long* __restrict__ owner, int32_t* __restrict__ assign) {
   const int64_t n = select_count(in);
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
        t += int64_t(gridDim.x) * blockDim.x) {
-    if (!keep[t]) continue;
+    if (keep[t] != 3) continue;
+    keep[t] = 1;
     const unsigned long long key = select_key(in, first, t);
     const int64_t b = in.hit_begin[t];
     const int m = in.n_hits[t];

@@ -1271,10 +1271,7 @@ tpcx_status tpcx_select(tpcx_ctx* c, const tpcx_tracks* tracks, int32_t n_units,
                      static_cast<const uint8_t*>(nullptr), owner);
   hipLaunchKernelGGL(k_select_decide, dim3(grid_t), dim3(256), 0, stream, in, first, owner, shared_num,
                      shared_den, keep, sel_counts);
-  hipLaunchKernelGGL(k_fill_i64, dim3(grid_c), dim3(256), 0, stream, reinterpret_cast<int64_t*>(owner),
-                     n_clusters, int64_t(0));
-  hipLaunchKernelGGL(k_select_claim, dim3(grid_t), dim3(256), 0, stream, in, first,
-                     static_cast<const uint8_t*>(keep), owner);
+  hipLaunchKernelGGL(k_select_reclaim, dim3(grid_t), dim3(256), 0, stream, in, first, keep, owner, assign);
   hipLaunchKernelGGL(k_select_assign, dim3(grid_t), dim3(256), 0, stream, in, first, keep, owner, assign);
   return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
 }
