@@ -868,6 +868,9 @@ __device__ __forceinline__ void add_hit_gradient(const HitGeom& h, float r, floa
   const Weights4 wp = weights_phi(h.phi);
   const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
   const Weights4 wz = weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
+  // fully unrolled: the weights stay in registers (a dynamic index would
+  // put them in scratch memory)
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
     const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
     int rel = i - wref;
@@ -875,10 +878,12 @@ __device__ __forceinline__ void add_hit_gradient(const HitGeom& h, float r, floa
     if (rel <= -kMapNPhi / 2) rel += kMapNPhi;
     rel += kWinPhi / 2;
     const bool in_win = rel >= 0 && rel < kWinPhi;
+#pragma unroll
     for (int b = 0; b < 4; ++b) {
       const float wab = wp.w[a] * wr.w[b];
       if (wab == 0.0f) continue;
       const int j = wr.first + b;
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
         const float w = wab * wz.w[c];
         if (w == 0.0f) continue;
