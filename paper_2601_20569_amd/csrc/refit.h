@@ -868,37 +868,55 @@ __device__ __forceinline__ void add_hit_gradient(const HitGeom& h, float r, floa
   const Weights4 wp = weights_phi(h.phi);
   const Weights4 wr = weights_lin(r, kMapR0, 1.0f / kMapDR, kMapNR);
   const Weights4 wz = weights_lin(h.zm, kMapZ0, 1.0f / kMapDZ, kMapNZ);
-  // fully unrolled: the weights stay in registers (a dynamic index would
-  // put them in scratch memory)
+  // r and z nodes clamped into the map: a node outside has weight 0, so its
+  // terms are 0 and add nothing; the node loops then run without branches
+  int jj[4], kk[4];
 #pragma unroll
+  for (int b = 0; b < 4; ++b) jj[b] = min(max(wr.first + b, 0), kMapNR - 1);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) kk[c] = min(max(wz.first + c, 0), kMapNZ - 1);
+  constexpr int kWinComp = kWinPhi * kMapNR * kMapNZ;
   for (int a = 0; a < 4; ++a) {
+    // (selected, not indexed: the weights stay in registers)
+    const float wpa = a == 0 ? wp.w[0] : a == 1 ? wp.w[1] : a == 2 ? wp.w[2] : wp.w[3];
     const int i = ((wp.first + a) % kMapNPhi + kMapNPhi) % kMapNPhi;
     int rel = i - wref;
     if (rel > kMapNPhi / 2) rel -= kMapNPhi;
     if (rel <= -kMapNPhi / 2) rel += kMapNPhi;
     rel += kWinPhi / 2;
-    const bool in_win = rel >= 0 && rel < kWinPhi;
+    if (rel >= 0 && rel < kWinPhi) {
+      long long* wa = win + rel * (kMapNR * kMapNZ);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const float wab = wp.w[a] * wr.w[b];
-      if (wab == 0.0f) continue;
-      const int j = wr.first + b;
+      for (int b = 0; b < 4; ++b) {
+        const float wab = wpa * wr.w[b];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const float w = wab * wz.w[c];
-        if (w == 0.0f) continue;
-        const int k = wz.first + c;
-        const float g3[3] = {gdr * w, gdp * w, gdz * w};
+        for (int c = 0; c < 4; ++c) {
+          const float w = wab * wz.w[c];
+          const float g3[3] = {gdr * w, gdp * w, gdz * w};
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const long long v = llrint(double(g3[q]) * kFixScale);
-          if (v == 0) continue;
-          if (in_win)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&win[((q * kWinPhi + rel) * kMapNR + j) * kMapNZ + k]),
-                      static_cast<unsigned long long>(v));
-          else
-            atomicAdd(reinterpret_cast<unsigned long long*>(&acc[map_index(q, i, j, k)]),
-                      static_cast<unsigned long long>(v));
+          for (int q = 0; q < 3; ++q) {
+            const long long v = llrint(double(g3[q]) * kFixScale);
+            if (v != 0)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&wa[q * kWinComp + jj[b] * kMapNZ + kk[c]]),
+                        static_cast<unsigned long long>(v));
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const float wab = wpa * wr.w[b];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float w = wab * wz.w[c];
+          const float g3[3] = {gdr * w, gdp * w, gdz * w};
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const long long v = llrint(double(g3[q]) * kFixScale);
+            if (v != 0)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&acc[map_index(q, i, jj[b], kk[c])]),
+                        static_cast<unsigned long long>(v));
+          }
         }
       }
     }
