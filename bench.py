@@ -213,7 +213,7 @@ def size_run(tr, rb, y, z, n_units):
     return out
 
 
-def cpu_baseline(cs, n_units_sample, threads):
+def cpu_baseline(cs, n_units_sample, threads, where="the input"):
     """The oracle (float decisions) on the first units of the same input."""
     import oracle
     from synth import geometry as G
@@ -223,7 +223,7 @@ def cpu_baseline(cs, n_units_sample, threads):
     res = oracle.track(cs, units=(lo, hi), n_threads=threads)
     dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="clusters/s", cores=threads, kind="oracle",
-                sample=f"sectors {lo}-{hi - 1} of the first slice: {n} clusters, {dt:.1f} s"), res
+                sample=f"sectors {lo}-{hi - 1} of {where}: {n} clusters, {dt:.1f} s"), res
 
 
 def timed(fn, steps, stream=None, per_step=None):
@@ -620,8 +620,9 @@ def main():
         if first is None:  # input read from the cache: the first slice again, from its seed
             import synth
             first = synth.timeframe_slice(seed=4000, n_collisions=int(B["ncoll"][0]), device="cuda", truth=True)
-        cpu, ores = cpu_baseline(first, nu, threads)
-        one, _ = cpu_baseline(first, 1, 1)
+        where = "the first slice" if args.workload == "batched" else "the input"
+        cpu, ores = cpu_baseline(first, nu, threads, where)
+        one, _ = cpu_baseline(first, 1, 1, where)
         cpu["one_core"] = dict(value=one["value"], sample=one["sample"])
         cpu["cpu_model"] = cpu_model()
         cpu["host_cpus"] = os.cpu_count()
