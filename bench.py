@@ -500,7 +500,7 @@ def main():
     if not (args.no_autotune or args.tuning):
         t0 = time.perf_counter()
         with torch.cuda.stream(stream):
-            tuning = tr.autotune_batched(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta, reps=2,
+            tuning = tr.autotune_batched(rb, y, z, U, bufs, stream, unit_alpha=alpha, theta=theta, reps=3,
                                          map_z=map_z)
         log(f"autotuned in {time.perf_counter() - t0:.1f} s: {tuning}")
     log(f"workspace {bufs['ws_bytes'] / 2**30:.1f} GiB; capturing the graph")

@@ -551,8 +551,9 @@ size_t tpcx_autotune_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64
  * size of the per-row kernels, grid and refill threshold of the persistent
  * constructor, grid and refill threshold of the persistent refit filter.  A
  * candidate replaces the current best when it is at least 1% faster (one
- * warm-up run, then the mean of reps >= 1 runs; a candidate whose workspace
- * exceeds ws_bytes is skipped).  The best tuning becomes the context's
+ * warm-up run, then the mean of reps >= 1 runs), confirmed by timing both
+ * once more (the sums of the two timings must differ by 1%); a candidate
+ * whose workspace exceeds ws_bytes is skipped.  The best tuning becomes the context's
  * tuning and is written to *best.  Synchronises the stream.  Returns
  * TPCX_E_CAPACITY if the output capacities are too small for the input. */
 tpcx_status tpcx_autotune_batched(tpcx_ctx* ctx, const tpcx_clusters* in, void* ws, size_t ws_bytes,

@@ -13,7 +13,9 @@
 //   bits 23..0   2^24 - 1 - index in the unit
 // so an atomic maximum over the keys of the tracklets containing a cluster
 // names its owner, whatever the order of the atomics.
-//   claim    every tracklet raises owner[c] to its key for each cluster c;
+//   claim    every tracklet raises owner[c] to its key for each cluster c
+//            (the tracklets of chi2/ndf <= 1 first, then the others where
+//            the owner word is below their key);
 //   decide   a tracklet is kept when, walking its clusters from the outermost
 //            row inwards, after every step k the count s(k) of clusters owned
 //            by another tracklet satisfies den s(k) <= num k;
@@ -81,18 +83,29 @@ __global__ void k_select_first(SelectIn in, int64_t* __restrict__ first, int64_t
   }
 }
 
-// owner[c] = max over (kept, when keep is set) tracklets containing c of
-// their keys.  One lane per tracklet.
-__global__ void k_select_claim(SelectIn in, const int64_t* __restrict__ first,
-                               const uint8_t* __restrict__ keep, unsigned long long* __restrict__ owner) {
+// owner[c] = max over the tracklets containing c of their keys, in two
+// passes: pass 0 claims with the tracklets of q = chi2/ndf <= 1 (the upper
+// 32 key bits at least those of q = 1), pass 1 with the others, each of
+// which claims a cluster only where owner[c] is below its key (a cluster
+// claimed in pass 0 holds a larger key than any of pass 1, and a larger
+// value read stays larger: the maximum only grows).  The claims of the
+// many clones of a good track then end as reads.  One lane per tracklet.
+constexpr uint32_t kClaimSplit = ~0x3F800000u;  // ~bits(1.0f)
+
+__global__ void k_select_claim(SelectIn in, const int64_t* __restrict__ first, int pass,
+                               unsigned long long* __restrict__ owner) {
   const int64_t n = select_count(in);
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
        t += int64_t(gridDim.x) * blockDim.x) {
-    if (keep && !keep[t]) continue;
     const unsigned long long key = select_key(in, first, t);
+    if ((uint32_t(key >> 32) >= kClaimSplit) != (pass == 0)) continue;
     const int64_t b = in.hit_begin[t];
     const int m = in.n_hits[t];
-    for (int j = 0; j < m; ++j) atomicMax(owner + in.hit_id[b + j], key);
+    for (int j = 0; j < m; ++j) {
+      unsigned long long* o = owner + in.hit_id[b + j];
+      if (pass == 1 && __hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= key) continue;
+      atomicMax(o, key);
+    }
   }
 }
 
