@@ -551,7 +551,9 @@ size_t tpcx_autotune_workspace_bytes(const tpcx_ctx* ctx, int32_t n_units, int64
  * size of the per-row kernels, grid and refill threshold of the persistent
  * constructor, grid and refill threshold of the persistent refit filter.  A
  * candidate replaces the current best when it is at least 1% faster (one
- * warm-up run, then the mean of reps >= 1 runs), confirmed by timing both
+ * warm-up run, then the mean of reps >= 1 runs, each a replay of the
+ * candidate's sequence captured into a graph as the batched form runs it;
+ * directly launched on the legacy default stream), confirmed by timing both
  * once more (the sums of the two timings must differ by 1%); a candidate
  * whose workspace exceeds ws_bytes is skipped.  The best tuning becomes the context's
  * tuning and is written to *best.  Synchronises the stream.  Returns

@@ -847,16 +847,40 @@ tpcx_status tpcx_autotune_batched(tpcx_ctx* c, const tpcx_clusters* in, void* ws
     if (e0) (void)hipEventDestroy(e0);
     return TPCX_E_HIP;
   }
+  // A candidate is timed as the batched form runs it: its sequence captured
+  // once into a graph and replayed (eager launches of the same sequence
+  // rank the z-bin candidates differently); on the legacy default stream,
+  // which cannot be captured, the sequence is launched directly.
   auto measure = [&](const tpcx_tuning& t, float* ms) -> tpcx_status {
-    tpcx_status r = autotune_run(c, in, ws, ws_bytes, cap_start, out, refit, t, stream);  // warm-up
+    hipGraphExec_t ge = nullptr;
+    if (stream) {
+      const Layout L = carve(c, ws, in->n_units, in->n_clusters, cap_start, t.n_zbins, t.block);
+      const BatchRefitLayout RL = carve_batch_refit(static_cast<char*>(ws) + L.bytes, in->n_clusters);
+      if (L.bytes + RL.bytes > ws_bytes) return TPCX_E_ARG;
+      if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPCX_E_HIP;
+      enqueue_track(c, in, L, t, cap_start, out, stream, nullptr, refit ? c->ev_fork : nullptr);
+      if (refit) enqueue_batch_refit(c, in, out, refit, RL, t, stream);
+      hipGraph_t g = nullptr;
+      if (hipStreamEndCapture(stream, &g) != hipSuccess || !g) return TPCX_E_HIP;
+      const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) return TPCX_E_HIP;
+    }
+    auto run = [&]() -> tpcx_status {
+      if (ge) return hipGraphLaunch(ge, stream) == hipSuccess ? TPCX_OK : TPCX_E_HIP;
+      return autotune_run(c, in, ws, ws_bytes, cap_start, out, refit, t, stream);
+    };
+    tpcx_status r = run();  // warm-up
+    if (r == TPCX_OK && hipEventRecord(e0, stream) != hipSuccess) r = TPCX_E_HIP;
+    for (int i = 0; i < reps && r == TPCX_OK; ++i) r = run();
+    if (r == TPCX_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+      r = TPCX_E_HIP;
+    if (ge) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipGraphExecDestroy(ge);
+    }
     if (r != TPCX_OK) return r;
-    if (hipEventRecord(e0, stream) != hipSuccess) return TPCX_E_HIP;
-    for (int i = 0; i < reps && r == TPCX_OK; ++i)
-      r = autotune_run(c, in, ws, ws_bytes, cap_start, out, refit, t, stream);
-    if (r != TPCX_OK) return r;
-    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
-      return TPCX_E_HIP;
     *ms /= float(reps);
     return TPCX_OK;
   };
