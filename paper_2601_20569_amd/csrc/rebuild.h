@@ -16,7 +16,9 @@
 // holder is the atomic maximum of its proposers' 64-bit rank keys, so the
 // result does not depend on the order of the atomics.  Only a (track, row)
 // whose candidate changed proposes again (a key once proposed stays below
-// the holder's, which only grows).
+// the holder's, which only grows), and only the tracks that proposed or
+// lost a cluster to a proposer (whose key the atomic returns) check what
+// they hold: every other track still holds what it held.
 // k_rebuild_pass3: iteration 3 over the rows whose candidate the track holds.
 // IEEE binary32, no contraction, correctly rounded divide and square root.
 #pragma once
@@ -61,6 +63,9 @@ struct RebuildWs {
   int32_t* meta;             // [n][4] ok, r_in, r_out
   uint64_t* key;             // [n] rank key
   unsigned long long* holder;  // [n_clusters]
+  int64_t* first;            // [n] first track of the track's unit
+  uint8_t* active;           // [n] the track has candidates to propose this round
+  uint8_t* check;            // [n] the track must check what it holds this round
 };
 
 struct RebuildOut {
@@ -94,7 +99,8 @@ __device__ __forceinline__ void rb_reset(KState& q, const DevParams& p, const Re
 
 // rank key (as in the ambiguity solving) of every track; local index from
 // the first track of its unit (tracks are in unit order)
-__global__ void k_rebuild_keys(RebuildIn in, uint64_t* __restrict__ key) {
+__global__ void k_rebuild_keys(RebuildIn in, uint64_t* __restrict__ key, int64_t* __restrict__ first,
+                               uint8_t* __restrict__ active, uint8_t* __restrict__ check) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= in.n_tracks) return;
   const int32_t u = in.unit[t];
@@ -108,6 +114,9 @@ __global__ void k_rebuild_keys(RebuildIn in, uint64_t* __restrict__ key) {
   const int64_t local = t - lo;
   key[t] = uint64_t(~__float_as_uint(q)) << 32 | uint64_t(uint32_t(min(n, 255)) << 24 |
                                                           uint32_t(kSelectMaxPerUnit - 1 - min(local, kSelectMaxPerUnit - 1)));
+  first[t] = lo;
+  active[t] = 1;
+  check[t] = 0;
 }
 
 // The candidates of row r of unit row base kb against the prediction (iy,
@@ -304,32 +313,46 @@ __global__ void __launch_bounds__(kWave) k_rebuild_pass12(RebuildIn in, Grid g, 
 
 __global__ void __launch_bounds__(kWave) k_rebuild_propose(RebuildIn in, RebuildWs ws) {
   const int64_t t = int64_t(blockIdx.x) * kWave + threadIdx.x;
-  if (t >= in.n_tracks) return;
+  if (t >= in.n_tracks || !ws.active[t]) return;
+  ws.active[t] = 0;
   const int32_t* meta = ws.meta + 4 * t;
   if (!meta[0]) return;
+  ws.check[t] = 1;
   const int R = in.n_rows;
   const unsigned long long key = ws.key[t];
+  const int64_t fu = ws.first[t];
   for (int r = meta[1]; r <= meta[2]; ++r) {
     const int v = ws.ptr[t * R + r];
     if (!(v & kPtrMoved)) continue;
     const int k = v & ~kPtrMoved;
     ws.ptr[t * R + r] = uint8_t(k);
-    if (k < ws.cnt[t * R + r]) atomicMax(ws.holder + ws.cand[(t * R + r) * kRebuildK + k].x, key);
+    if (k >= ws.cnt[t * R + r]) continue;
+    const unsigned long long old = atomicMax(ws.holder + ws.cand[(t * R + r) * kRebuildK + k].x, key);
+    if (old != 0ull && old < key) {
+      // the holder (a track of the same unit) lost the cluster
+      const int64_t h = fu + (kSelectMaxPerUnit - 1 - int64_t(old & (kSelectMaxPerUnit - 1)));
+      if (h < in.n_tracks) ws.check[h] = 1;
+    }
   }
 }
 
 __global__ void __launch_bounds__(kWave) k_rebuild_advance(RebuildIn in, RebuildWs ws) {
   const int64_t t = int64_t(blockIdx.x) * kWave + threadIdx.x;
-  if (t >= in.n_tracks) return;
+  if (t >= in.n_tracks || !ws.check[t]) return;
+  ws.check[t] = 0;
   const int32_t* meta = ws.meta + 4 * t;
   if (!meta[0]) return;
   const int R = in.n_rows;
   const unsigned long long key = ws.key[t];
+  bool moved = false;
   for (int r = meta[1]; r <= meta[2]; ++r) {
     const int k = ws.ptr[t * R + r] & ~kPtrMoved;
-    if (k < ws.cnt[t * R + r] && ws.holder[ws.cand[(t * R + r) * kRebuildK + k].x] != key)
+    if (k < ws.cnt[t * R + r] && ws.holder[ws.cand[(t * R + r) * kRebuildK + k].x] != key) {
       ws.ptr[t * R + r] = uint8_t(k + 1) | kPtrMoved;
+      moved = true;
+    }
   }
+  if (moved) ws.active[t] = 1;
 }
 
 __global__ void __launch_bounds__(kWave) k_rebuild_pass3(RebuildIn in, DevParams p, RebuildConsts f,

@@ -1085,6 +1085,9 @@ RebuildLayout carve_rebuild(const tpcx_ctx* c, void* base, int32_t n_units, int6
   L.ws.meta = cv.take<int32_t>(4 * n_tracks);
   L.ws.key = cv.take<uint64_t>(n_tracks);
   L.ws.holder = cv.take<unsigned long long>(n_clusters);
+  L.ws.first = cv.take<int64_t>(n_tracks);
+  L.ws.active = cv.take<uint8_t>(n_tracks);
+  L.ws.check = cv.take<uint8_t>(n_tracks);
   L.bytes = cv.off;
   return L;
 }
@@ -1241,7 +1244,8 @@ tpcx_status tpcx_rebuild(tpcx_ctx* c, const tpcx_clusters* cl, const tpcx_rebuil
   ro.n_kept = out->n_kept;
   ro.ok = out->ok;
   const dim3 gw(blocks_for(in->n_tracks, kWave));
-  hipLaunchKernelGGL(k_rebuild_keys, dim3(blocks_for(in->n_tracks, 256)), dim3(256), 0, stream, ri, L.ws.key);
+  hipLaunchKernelGGL(k_rebuild_keys, dim3(blocks_for(in->n_tracks, 256)), dim3(256), 0, stream, ri, L.ws.key,
+                     L.ws.first, L.ws.active, L.ws.check);
   hipLaunchKernelGGL(k_rebuild_pass12, gw, dim3(kWave), 0, stream, ri, g, c->dp, f, L.ws);
   if (cl->n_clusters > 0)
     hipLaunchKernelGGL(k_fill_i64, dim3(std::max(1, std::min(blocks_for(cl->n_clusters, 256), 4096))), dim3(256),
