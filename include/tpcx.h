@@ -358,6 +358,7 @@ typedef struct {
   const float* x_ref;          /* [n_tracks] its plane */
   const float* y;              /* clusters */
   const float* z;
+  int64_t n_clusters;          /* length of y and z */
 } tpcx_fit_in;
 
 typedef struct {
@@ -374,10 +375,10 @@ typedef struct {
  * record and its row), n_hits slots plus 16384 per 8192 tracks (the slack of
  * the per-wavefront interleaved layout; a track of 256 or more clusters may
  * make the fit fall back to one record per hit in track order, same results),
- * 16 bytes per 64 tracks and 4 bytes per track (the processing order:
- * longest tracks first within chunks of 8192 consecutive tracks).
- * n_tracks < 2^31. */
-size_t tpcx_fit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_tracks, int64_t n_hits);
+ * 16 bytes per 64 tracks, 4 bytes per track (the processing order: longest
+ * tracks first within chunks of 8192 consecutive tracks) and 8 bytes per
+ * cluster (y and z side by side: one gather per hit).  n_tracks < 2^31. */
+size_t tpcx_fit_workspace_bytes(const tpcx_ctx* ctx, int64_t n_tracks, int64_t n_hits, int64_t n_clusters);
 
 /* Enqueues the fit of every track of `in`; ws 256-byte aligned. */
 tpcx_status tpcx_fit(tpcx_ctx* ctx, const tpcx_fit_in* in, const tpcx_fit_params* params,

@@ -81,7 +81,8 @@ class FitParams(ctypes.Structure):
 class FitInput(ctypes.Structure):
     _fields_ = [("n_tracks", ctypes.c_int64), ("n_hits", ctypes.c_int64), ("hit_begin", ctypes.c_void_p),
                 ("hit_id", ctypes.c_void_p), ("hit_row", ctypes.c_void_p), ("seed", ctypes.c_void_p),
-                ("x_ref", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+                ("x_ref", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("n_clusters", ctypes.c_int64)]
 
 
 class FitOutput(ctypes.Structure):
@@ -181,7 +182,7 @@ def lib():
                                          ctypes.c_int64, ctypes.POINTER(Tracks),
                                          ctypes.POINTER(BatchRefit), P]
         L.tpcx_track_batched.restype = ctypes.c_int32
-        L.tpcx_fit_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.c_int64]
+        L.tpcx_fit_workspace_bytes.argtypes = [P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]
         L.tpcx_fit_workspace_bytes.restype = ctypes.c_size_t
         L.tpcx_fit.argtypes = [P, ctypes.POINTER(FitInput), ctypes.POINTER(FitParams),
                                ctypes.POINTER(FitOutput), P, ctypes.c_size_t, P]
@@ -411,6 +412,9 @@ class SectorTracker:
                       (seed, torch.float32), (x_ref, torch.float32), (y, torch.float32), (z, torch.float32)):
             if v.dtype != dt or not v.is_cuda or not v.is_contiguous():
                 raise TpcxError("fit inputs must be contiguous device tensors of the documented types")
+        if y.numel() != z.numel():
+            raise TpcxError("fit: y and z must have one entry per cluster")
+        nc = int(y.numel())
         dev = hit_begin.device
         f32, i32 = torch.float32, torch.int32
         out = dict(param=torch.zeros((max(n, 1), 5), dtype=f32, device=dev),
@@ -420,11 +424,11 @@ class SectorTracker:
                    n_kept=torch.zeros(max(n, 1), dtype=i32, device=dev),
                    ok=torch.zeros(max(n, 1), dtype=i32, device=dev),
                    reject=torch.zeros(max(nh, 1), dtype=torch.uint8, device=dev))
-        nb = int(lib().tpcx_fit_workspace_bytes(self._h, n, nh))
+        nb = int(lib().tpcx_fit_workspace_bytes(self._h, n, nh, nc))
         ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         off = (-ws.data_ptr()) % 256
         fi = FitInput(n, nh, _ptr(hit_begin), _ptr(hit_id), _ptr(hit_row), _ptr(seed), _ptr(x_ref), _ptr(y),
-                      _ptr(z))
+                      _ptr(z), nc)
         fo = FitOutput(*[_ptr(out[k]) for k in ("param", "cov", "chi2", "x_out", "n_kept", "ok", "reject")])
         fp = FitParams(chi2_cut, var_s, var_t, var_w)
         s = stream if stream is not None else torch.cuda.current_stream()

@@ -37,8 +37,7 @@ struct FitIn {
   const uint8_t* hit_row;
   const float* seed;   // [n][5]
   const float* x_ref;  // [n]
-  const float* y;
-  const float* z;
+  const float2* yz;    // clusters' y, z side by side (one gather per hit)
   const float* row_x;
 };
 
@@ -114,6 +113,14 @@ struct FitWs {
   int64_t cap;
 };
 
+// yz[c] = (y[c], z[c]): the fit gathers one 8-byte pair per hit instead of
+// two 4-byte values from separate arrays.
+__global__ void k_fit_pack(int64_t n, const float* __restrict__ y, const float* __restrict__ z,
+                           float2* __restrict__ yz) {
+  for (int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; c < n; c += int64_t(gridDim.x) * blockDim.x)
+    yz[c] = make_float2(y[c], z[c]);
+}
+
 // wlen[w] = 64 x the longest track of wavefront w (processing order).
 __global__ void k_fit_wave_len(int64_t n, const int64_t* __restrict__ hit_begin,
                                const int32_t* __restrict__ order, int64_t* __restrict__ wlen) {
@@ -170,7 +177,8 @@ __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts 
   int kept = 0;
   float chi2 = 0.0f;
   KState last{};
-  const float oy = good ? in.y[in.hit_id[b + n - 1]] : 0.0f, oz = good ? in.z[in.hit_id[b + n - 1]] : 0.0f;
+  const float2 o2 = good ? in.yz[in.hit_id[b + n - 1]] : make_float2(0.0f, 0.0f);
+  const float oy = o2.x, oz = o2.y;
   auto X = [&](int i) { return srx[in.hit_row[b + i]]; };
   if (good) {
     // ---- iteration 1: inwards, storing the predictions
@@ -203,86 +211,130 @@ __global__ void __launch_bounds__(kWave) k_fit(FitIn in, DevParams p, FitConsts 
       fit_reset_cov(q, p, f);
       R[(n - 1) * ss] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (inter) ws.rows[s0 + (n - 1) * ss] = in.hit_row[b + n - 1];
-      // the cluster and row of the next step are loaded one step ahead
-      int32_t cn = in.hit_id[b + n - 2];
-      float yn = in.y[cn], zn = in.z[cn];
-      int rn = in.hit_row[b + n - 2];
-      for (int i = n - 2; i >= 0 && good; --i) {
-        const float ry = yn - oy, rz = zn - oz;
-        const int ri = rn;
-        if (i > 0) {
-          cn = in.hit_id[b + i - 1];
-          yn = in.y[cn];
-          zn = in.z[cn];
-          rn = in.hit_row[b + i - 1];
+      // Two register sets, A for the hits n-2, n-4, ... and B for n-3, n-5,
+      // ...: a step uses its set's cluster (y, z, row) and reloads the set
+      // for the hit two steps later, whose id the set loaded two steps
+      // before; so no register is copied between steps, and a step waits
+      // only for loads two steps old.  Every lane runs every step of the
+      // wavefront's loop (its loads with indices clamped into the track, its
+      // arithmetic only while active), so the loads are never conditional.
+      auto hid = [&](int j) { return in.hit_id[b + max(j, 0)]; };
+      float2 mA, mB;
+      int rA, rB;
+      int32_t idA, idB;
+      {
+        mA = in.yz[hid(n - 2)];
+        rA = in.hit_row[b + n - 2];
+        idA = hid(n - 4);
+        mB = in.yz[hid(n - 3)];
+        rB = in.hit_row[b + max(n - 3, 0)];
+        idB = hid(n - 5);
+      }
+      auto step = [&](float2& mv, int& rv, int32_t& idv, int i, bool act) {
+        if (act) {
+          const float ry = mv.x - oy, rz = mv.y - oz;
+          if (inter) ws.rows[s0 + i * ss] = uint8_t(rv);
+          good = fit_prop(q, srx[rv], p);
+          if (good) {
+            const uint32_t dd = bf16_bits(q.y - ry) | (bf16_bits(q.z - rz) << 16);
+            const uint32_t cc = bf16_bits(fit_cyy(q)) | (bf16_bits(fit_czz(q)) << 16);
+            R[i * ss] = make_float4(ry, rz, __uint_as_float(dd), __uint_as_float(cc));
+            fit_update(q, ry, rz, p);
+          }
         }
-        if (inter) ws.rows[s0 + i * ss] = uint8_t(ri);
-        good = fit_prop(q, srx[ri], p);
-        if (!good) break;
-        const uint32_t dd = bf16_bits(q.y - ry) | (bf16_bits(q.z - rz) << 16);
-        const uint32_t cc = bf16_bits(fit_cyy(q)) | (bf16_bits(fit_czz(q)) << 16);
-        R[i * ss] = make_float4(ry, rz, __uint_as_float(dd), __uint_as_float(cc));
-        fit_update(q, ry, rz, p);
+        // the set's reload, after its use (into the same registers)
+        rv = in.hit_row[b + max(i - 2, 0)];
+        mv = in.yz[idv];
+        idv = hid(i - 4);
+      };
+      for (int i = n - 2;; i -= 2) {
+        const bool a0 = good && i >= 0;
+        if (__ballot(a0) == 0ull) break;
+        step(mA, rA, idA, i, a0);
+        step(mB, rB, idB, i - 1, good && i - 1 >= 0);
       }
     }
     // ---- iteration 2: outwards, interpolation and chi2 cut
     if (good) {
-      float4 rn = R[0];
-      int xn = rowp[0];
-      const float4 r0 = rn;
+      // two register sets (records and rows of the even and the odd
+      // steps), each reloaded after its use for the step two later, every
+      // lane running every step of the wavefront's loop (as in iteration 1)
+      float4 rA = R[0], rB = R[ss];
+      int xA = rowp[0], xB = rowp[ss];
       const float s1 = q.s, t1 = q.t, w1 = q.w;
       q = KState{};
-      q.x = srx[xn];
-      q.y = r0.x;
-      q.z = r0.y;
+      q.x = srx[xA];
+      q.y = rA.x;
+      q.z = rA.y;
       q.s = s1;
       q.t = t1;
       q.w = w1;
       fit_reset_cov(q, p, f);
-      for (int i = 0; i < n && good; ++i) {
-        // record and row of step i + 1 loaded one step ahead
-        const float4 ri = rn;
-        const int xi = xn;
-        if (i + 1 < n) {
-          rn = R[(i + 1) * ss];
-          xn = rowp[(i + 1) * ss];
-        }
-        if (i > 0) {
-          good = fit_prop(q, srx[xi], p);
-          if (!good) break;
-        }
-        const float ry = i == n - 1 ? 0.0f : ri.x, rz = i == n - 1 ? 0.0f : ri.y;
-        float dy, dz, vy, vz;
-        if (i == 0) {
-          const uint32_t dd = __float_as_uint(ri.z), cc = __float_as_uint(ri.w);
-          dy = bf16_lo(dd);
-          dz = bf16_hi(dd);
-          vy = bf16_lo(cc);
-          vz = bf16_hi(cc);
-        } else {
-          const float cy = fit_cyy(q), cz = fit_czz(q);
-          const float dout = q.y - ry, eout = q.z - rz;
-          if (i == n - 1) {
-            dy = dout;
-            dz = eout;
-            vy = cy;
-            vz = cz;
+      // rejection flags gathered per 4-byte word of rej (whole words stored
+      // where they lie inside the track)
+      uint32_t racc = 0;
+      const uint32_t rmis = uint32_t(reinterpret_cast<uintptr_t>(rej) & 3);
+      auto put_flag = [&](int i, uint32_t rj) {
+        const uint32_t lb = (rmis + uint32_t(i)) & 3;
+        racc |= rj << (8 * lb);
+        if (lb == 3 || i == n - 1) {
+          const int i0 = i - int(lb);
+          if (lb == 3 && i0 >= 0) {
+            *reinterpret_cast<uint32_t*>(rej + i0) = racc;
           } else {
-            const uint32_t dd = __float_as_uint(ri.z), cc = __float_as_uint(ri.w);
-            const float din = bf16_lo(dd), ein = bf16_hi(dd), cin = bf16_lo(cc), kin = bf16_hi(cc);
-            const float iy = 1.0f / (cin + cy);
-            const float iz = 1.0f / (kin + cz);
-            dy = (din * cy + dout * cin) * iy;
-            dz = (ein * cz + eout * kin) * iz;
-            vy = (cin * cy) * iy;
-            vz = (kin * cz) * iz;
+            for (int k = max(i0, 0); k <= i; ++k) rej[k] = uint8_t(racc >> (8 * (k - i0)));
+          }
+          racc = 0;
+        }
+      };
+      auto step2 = [&](float4& rv, int& xv, int i, bool act) {
+        if (act) {
+          if (i > 0) good = fit_prop(q, srx[xv], p);
+          if (good) {
+            const float4 ri = rv;
+            const float ry = i == n - 1 ? 0.0f : ri.x, rz = i == n - 1 ? 0.0f : ri.y;
+            float dy, dz, vy, vz;
+            if (i == 0) {
+              const uint32_t dd = __float_as_uint(ri.z), cc = __float_as_uint(ri.w);
+              dy = bf16_lo(dd);
+              dz = bf16_hi(dd);
+              vy = bf16_lo(cc);
+              vz = bf16_hi(cc);
+            } else {
+              const float cy = fit_cyy(q), cz = fit_czz(q);
+              const float dout = q.y - ry, eout = q.z - rz;
+              if (i == n - 1) {
+                dy = dout;
+                dz = eout;
+                vy = cy;
+                vz = cz;
+              } else {
+                const uint32_t dd = __float_as_uint(ri.z), cc = __float_as_uint(ri.w);
+                const float din = bf16_lo(dd), ein = bf16_hi(dd), cin = bf16_lo(cc), kin = bf16_hi(cc);
+                const float iy = 1.0f / (cin + cy);
+                const float iz = 1.0f / (kin + cz);
+                dy = (din * cy + dout * cin) * iy;
+                dz = (ein * cz + eout * kin) * iz;
+                vy = (cin * cy) * iy;
+                vz = (kin * cz) * iz;
+              }
+            }
+            const float c2 = (dy * dy) / (vy + p.sy2) + (dz * dz) / (vz + p.sz2);
+            const uint32_t rj = c2 > f.chi2_cut ? 1u : 0u;
+            put_flag(i, rj);
+            reinterpret_cast<float*>(&R[i * ss])[3] = __uint_as_float(rj);
+            if (i > 0) fit_update(q, ry, rz, p);
           }
         }
-        const float c2 = (dy * dy) / (vy + p.sy2) + (dz * dz) / (vz + p.sz2);
-        const uint8_t rj = c2 > f.chi2_cut ? 1 : 0;
-        rej[i] = rj;
-        reinterpret_cast<float*>(&R[i * ss])[3] = __uint_as_float(uint32_t(rj));
-        if (i > 0) fit_update(q, ry, rz, p);
+        const int64_t nx = min(i + 2, n - 1);
+        rv = R[nx * ss];
+        xv = rowp[nx * ss];
+      };
+      for (int i = 0;; i += 2) {
+        const bool a0 = good && i < n;
+        if (__ballot(a0) == 0ull) break;
+        step2(rA, xA, i, a0);
+        step2(rB, xB, i + 1, good && i + 1 < n);
       }
     }
     // ---- iteration 3: inwards over the kept clusters

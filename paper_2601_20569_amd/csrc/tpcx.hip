@@ -976,6 +976,7 @@ namespace {
 // the per-wavefront layout when every track has fewer than 256 clusters),
 // the rows of the slots, per-wavefront sizes and offsets, the order.
 struct FitLayout {
+  float2* yz;
   float4* rec;
   uint8_t* rows;
   int64_t* wlen;
@@ -985,9 +986,10 @@ struct FitLayout {
   size_t bytes;
 };
 
-FitLayout carve_fit(void* base, int64_t n_tracks, int64_t n_hits) {
+FitLayout carve_fit(void* base, int64_t n_tracks, int64_t n_hits, int64_t n_clusters) {
   Carver cv{static_cast<char*>(base)};
   FitLayout L{};
+  L.yz = cv.take<float2>(n_clusters);
   const int64_t nw = (n_tracks + kWave - 1) / kWave;
   L.cap = n_hits + (n_tracks + kLenChunk - 1) / kLenChunk * int64_t(kWave) * 256;
   L.rec = cv.take<float4>(L.cap);
@@ -1003,14 +1005,16 @@ FitLayout carve_fit(void* base, int64_t n_tracks, int64_t n_hits) {
 
 extern "C" {
 
-size_t tpcx_fit_workspace_bytes(const tpcx_ctx* c, int64_t n_tracks, int64_t n_hits) {
-  if (!c || n_tracks < 0 || n_hits < 0) return 0;
-  return carve_fit(nullptr, n_tracks, n_hits).bytes;
+size_t tpcx_fit_workspace_bytes(const tpcx_ctx* c, int64_t n_tracks, int64_t n_hits, int64_t n_clusters) {
+  if (!c || n_tracks < 0 || n_hits < 0 || n_clusters < 0) return 0;
+  return carve_fit(nullptr, n_tracks, n_hits, n_clusters).bytes;
 }
 
 tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* fp, const tpcx_fit_out* out,
                      void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (!c || !in || !fp || !out || in->n_tracks < 0 || in->n_hits < 0) return TPCX_E_ARG;
+  if (!c || !in || !fp || !out || in->n_tracks < 0 || in->n_hits < 0 || in->n_clusters < 0) return TPCX_E_ARG;
+  if (in->n_clusters > 0 && (!in->y || !in->z)) return TPCX_E_ARG;
+  if (in->n_hits > 0 && in->n_clusters == 0) return TPCX_E_ARG;
   if (in->n_tracks > 0 && (!in->hit_begin || !in->seed || !in->x_ref || !out->param || !out->cov ||
                            !out->chi2 || !out->x_out || !out->n_kept || !out->ok))
     return TPCX_E_ARG;
@@ -1019,7 +1023,7 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
     return TPCX_E_ARG;
   if (reinterpret_cast<uintptr_t>(ws) % kAlign != 0) return TPCX_E_ARG;
   if (in->n_tracks >= (int64_t(1) << 31)) return TPCX_E_ARG;
-  const FitLayout L = carve_fit(ws, in->n_tracks, in->n_hits);
+  const FitLayout L = carve_fit(ws, in->n_tracks, in->n_hits, in->n_clusters);
   if (!ws || ws_bytes < L.bytes) return TPCX_E_ARG;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != c->device) return TPCX_E_ARG;
@@ -1031,8 +1035,7 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   fi.hit_row = in->hit_row;
   fi.seed = in->seed;
   fi.x_ref = in->x_ref;
-  fi.y = in->y;
-  fi.z = in->z;
+  fi.yz = L.yz;
   fi.row_x = c->d_row_x;
   fi.n_rows = c->n_rows;
   FitOut fo;
@@ -1044,6 +1047,9 @@ tpcx_status tpcx_fit(tpcx_ctx* c, const tpcx_fit_in* in, const tpcx_fit_params* 
   fo.ok = out->ok;
   fo.reject = out->reject;
   const FitConsts f{fp->chi2_cut, fp->var_s, fp->var_t, fp->var_w};
+  if (in->n_clusters > 0)
+    hipLaunchKernelGGL(k_fit_pack, dim3(std::min(blocks_for(in->n_clusters, 256), 4096)), dim3(256), 0, stream,
+                       in->n_clusters, in->y, in->z, L.yz);
   enqueue_length_order(in->n_tracks, in->hit_begin, L.order, stream);
   const int64_t nw = (in->n_tracks + kWave - 1) / kWave;
   hipLaunchKernelGGL(k_fit_wave_len, dim3(blocks_for(in->n_tracks, 256)), dim3(256), 0, stream, in->n_tracks,
