@@ -14,8 +14,8 @@
 // so an atomic maximum over the keys of the tracklets containing a cluster
 // names its owner, whatever the order of the atomics.
 //   claim    every tracklet raises owner[c] to its key for each cluster c
-//            (the tracklets of chi2/ndf <= 1 first, then the others where
-//            the owner word is below their key);
+//            (in bands of chi2/ndf, best first, each claim only where the
+//            owner word is below the tracklet's key);
 //   decide   a tracklet is kept when, walking its clusters from the outermost
 //            row inwards, after every step k the count s(k) of clusters owned
 //            by another tracklet satisfies den s(k) <= num k;
@@ -83,14 +83,18 @@ __global__ void k_select_first(SelectIn in, int64_t* __restrict__ first, int64_t
   }
 }
 
-// owner[c] = max over the tracklets containing c of their keys, in two
-// passes: pass 0 claims with the tracklets of q = chi2/ndf <= 1 (the upper
-// 32 key bits at least those of q = 1), pass 1 with the others, each of
-// which claims a cluster only where owner[c] is below its key (a cluster
-// claimed in pass 0 holds a larger key than any of pass 1, and a larger
-// value read stays larger: the maximum only grows).  The claims of the
-// many clones of a good track then end as reads.  One lane per tracklet.
-constexpr uint32_t kClaimSplit = ~0x3F800000u;  // ~bits(1.0f)
+// owner[c] = max over the tracklets containing c of their keys, in passes
+// over bands of q = chi2/ndf (best first: q <= 0.5, <= 1, <= 2, the rest;
+// the upper 32 key bits are ~bits(q)); a tracklet claims a cluster only
+// where owner[c] is below its key (a larger value read stays larger: the
+// maximum only grows).  A cluster claimed in an earlier band holds a larger
+// key than any of a later one, so the claims of the many clones of a good
+// track end as reads.  One lane per tracklet.
+constexpr int kClaimPasses = 4;
+__device__ __forceinline__ uint32_t claim_band_floor(int pass) {
+  // ~bits of 0.5, 1, 2: a key's upper half at least this is in bands 0 .. pass
+  return pass == 0 ? ~0x3F000000u : pass == 1 ? ~0x3F800000u : ~0x40000000u;
+}
 
 __global__ void k_select_claim(SelectIn in, const int64_t* __restrict__ first, int pass,
                                unsigned long long* __restrict__ owner) {
@@ -98,12 +102,15 @@ __global__ void k_select_claim(SelectIn in, const int64_t* __restrict__ first, i
   for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
        t += int64_t(gridDim.x) * blockDim.x) {
     const unsigned long long key = select_key(in, first, t);
-    if ((uint32_t(key >> 32) >= kClaimSplit) != (pass == 0)) continue;
+    const uint32_t hi = uint32_t(key >> 32);
+    const bool mine = (pass == kClaimPasses - 1 || hi >= claim_band_floor(pass)) &&
+                      (pass == 0 || hi < claim_band_floor(pass - 1));
+    if (!mine) continue;
     const int64_t b = in.hit_begin[t];
     const int m = in.n_hits[t];
     for (int j = 0; j < m; ++j) {
       unsigned long long* o = owner + in.hit_id[b + j];
-      if (pass == 1 && __hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= key) continue;
+      if (__hip_atomic_load(o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= key) continue;
       atomicMax(o, key);
     }
   }

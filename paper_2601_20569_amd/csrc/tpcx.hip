@@ -1314,7 +1314,7 @@ tpcx_status tpcx_select(tpcx_ctx* c, const tpcx_tracks* tracks, int32_t n_units,
   }
   if (tracks->cap_tracks == 0 || n_clusters == 0) return hipGetLastError() == hipSuccess ? TPCX_OK : TPCX_E_HIP;
   hipLaunchKernelGGL(k_select_first, dim3(grid_t), dim3(256), 0, stream, in, first, sel_counts + 1);
-  for (int pass = 0; pass < 2; ++pass)
+  for (int pass = 0; pass < kClaimPasses; ++pass)
     hipLaunchKernelGGL(k_select_claim, dim3(grid_t), dim3(256), 0, stream, in, first, pass, owner);
   hipLaunchKernelGGL(k_select_decide, dim3(grid_t), dim3(256), 0, stream, in, first, owner, shared_num,
                      shared_den, keep, sel_counts);
