@@ -100,6 +100,7 @@ struct Layout {
 };
 
 constexpr int kKeepBlocks = 4096;
+constexpr int kGridBuildBlock = 1024;
 
 int blocks_for(int64_t n, int b) { return int((n + b - 1) / b); }
 
@@ -443,7 +444,9 @@ void enqueue_track(const tpcx_ctx* c, const tpcx_clusters* in, const Layout& L, 
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, L.queue, int64_t(1), 0);
   const int UR = U * R;
   const size_t hist_bytes = sizeof(int32_t) * (size_t(t.n_zbins) * max_row_ny(c) + 1);
-  hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(B), hist_bytes, stream, in->row_begin, in->y,
+  // the row's bin counters fill most of the LDS, so one block runs per CU:
+  // the largest block keeps 4 wavefronts per SIMD on the row's gathers
+  hipLaunchKernelGGL(k_grid_build, dim3(UR), dim3(kGridBuildBlock), hist_bytes, stream, in->row_begin, in->y,
                      in->z, g, L.row_z, L.bins, L.pts,
                      reinterpret_cast<unsigned long long*>(out->counts + 3));
   if (after_grid) (void)hipEventRecord(after_grid, stream);
