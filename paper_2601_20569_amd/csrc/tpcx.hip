@@ -99,7 +99,9 @@ struct Layout {
   size_t bytes;
 };
 
-constexpr int kKeepBlocks = 4096;
+// compaction blocks: one resident round on 256 CUs (5 blocks of 4 wavefronts
+// per CU at the kernel's register count), so no partial last round
+constexpr int kKeepBlocks = 1280;
 constexpr int kGridBuildBlock = 1024;
 
 int blocks_for(int64_t n, int b) { return int((n + b - 1) / b); }
